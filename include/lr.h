@@ -1,0 +1,136 @@
+/*
+ * lr.h — C-ABI of the MI355X library for the 2D multimaterial Lagrange–Remap
+ * step with the one-step "Direct remap with Corner Fluxes" (DirectCF) of
+ * B. Chaudet, arXiv:2208.13409.  One context holds one problem: a regular
+ * orthogonal grid of nx x ny cells, nmat perfect-gas materials and reflective
+ * walls.  All state lives in device memory owned by the library; every
+ * argument pointer below is HOST memory, FP64, row-major with x fastest,
+ * unless stated otherwise.
+ *
+ * Every function returns 0 (LR_OK) or a negative LR_E* code and never aborts;
+ * lr_last_error() then describes the failure.  A context is not thread-safe:
+ * one host thread at a time per context.  Kernels run on the context's HIP
+ * stream (its own non-blocking stream unless lr_bind_stream is called).
+ */
+#ifndef LR_H
+#define LR_H
+#include <stddef.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LR_MAXMAT 4
+
+enum {
+  LR_OK = 0,
+  LR_EINVAL = -1,    /* bad argument (sizes, options, null pointers, t_end < t) */
+  LR_ENOMEM = -2,    /* device or host allocation failed                        */
+  LR_EDEVICE = -3,   /* a HIP call failed                                       */
+  LR_ENEGATIVE = -4, /* negative partial volume / mass / energy, Vol^lagCF <= 0 */
+  LR_ENAN = -5,      /* non-finite value in the inputs or the state             */
+  LR_EDT = -6,       /* time step not positive or not finite                    */
+  LR_EAGAIN = -7,    /* reserved                                                */
+  LR_ESTATE = -8     /* no state set, or volume fractions outside [0,1] / sum != 1 */
+};
+
+enum { LR_BC_REFLECT = 0 };     /* the only boundary: reflective wall          */
+enum { LR_FP64 = 0, LR_FP32 = 1 };
+
+/* material equation of state: perfect gas p = (gamma-1) rho e (paper §5.1);
+ * pinf must be 0 (stiffened gas is not part of this build) */
+typedef struct { double gamma, pinf; } lr_eos;
+
+typedef struct {
+  double x0, x1, y0, y1; /* domain; dx = (x1-x0)/nx, dy = (y1-y0)/ny                    */
+  double cfl;            /* CFL number; default 0.5                                     */
+  double a1, a2;         /* Wilkins linear / quadratic pseudo-viscosity (§1.2); 0.5, 1.0  */
+  int precision;         /* LR_FP64 (default); LR_FP32 returns LR_EINVAL in this build    */
+  int recon_order;       /* 1 = upwind everywhere, 2 = limited linear (§2.1.1, §3.3)      */
+  int kinematic;         /* 1 = node velocities prescribed, no forces, no momentum remap  */
+  double k_eps;          /* a material is present where V_a > k_eps * dx*dy; 1e-10        */
+  double fixed_dt;       /* > 0: this time step instead of the CFL one                    */
+} lr_opts;
+
+/* field mask bits for lr_get_fields, in the order the output pointers are
+ * given (lowest bit first).  Mixture fields are [ny][nx]; per-material fields
+ * [nmat][ny][nx] (0 where the material is absent); node fields [ny+1][nx+1]. */
+enum {
+  LR_F_RHO = 1,      /* mixture density  sum M_a / (dx dy)                    */
+  LR_F_P = 2,        /* mixture pressure sum k_a P_a (§4.1)                   */
+  LR_F_E = 4,        /* mixture specific internal energy sum E_a / sum M_a    */
+  LR_F_K = 8,        /* volume fractions V_a / (dx dy)                        */
+  LR_F_RHOA = 16,    /* partial densities M_a / V_a                           */
+  LR_F_EA = 32,      /* partial specific internal energies E_a / M_a          */
+  LR_F_PA = 64,      /* partial pressures                                     */
+  LR_F_UX = 128,     /* nodal velocity x                                      */
+  LR_F_UY = 256,     /* nodal velocity y                                      */
+  LR_F_VOL = 512,    /* conserved partial volumes V_a                         */
+  LR_F_MASS = 1024,  /* conserved partial masses M_a                          */
+  LR_F_IE = 2048     /* conserved partial internal energies E_a = M_a e_a     */
+};
+
+typedef struct lr_ctx lr_ctx;
+
+/* fill *o with the defaults listed in lr_opts */
+void lr_default_opts(lr_opts *o);
+
+/* Create a problem context and allocate its device memory on the current HIP
+ * device.  nx, ny >= 2; 1 <= nmat <= LR_MAXMAT; eos[nmat]; bc[4] = {xlo, xhi,
+ * ylo, yhi}, all LR_BC_REFLECT (NULL means all reflective); opts NULL means
+ * defaults.  *out receives the context (NULL on failure). */
+int lr_create(int nx, int ny, int nmat, const lr_eos *eos, const int bc[4],
+              const lr_opts *opts, lr_ctx **out);
+
+/* Launch this context's kernels on the given hipStream_t (passed as void*,
+ * e.g. torch.cuda.current_stream().cuda_stream).  The caller keeps the
+ * stream alive; NULL returns to the context's own stream. */
+int lr_bind_stream(lr_ctx *c, void *hip_stream);
+
+/* Set the state at time t from host arrays, copied: k[nmat][ny][nx] volume
+ * fractions (>= 0, each cell sums to 1 within 1e-12), rho and e [nmat][ny][nx]
+ * per-material density (> 0) and specific internal energy (>= 0) where k > 0
+ * (ignored elsewhere), ux, uy [ny+1][nx+1] nodal velocities (the wall-normal
+ * component on wall nodes is set to 0).  Partial volumes are k dx dy, masses
+ * rho V, energies M e.  Computes the first CFL time step; synchronizes. */
+int lr_set_state(lr_ctx *c, double t, const double *k, const double *rho,
+                 const double *e, const double *ux, const double *uy);
+
+/* One time step (Lagrangian phase, DirectCF remap with partial VOF fluxes,
+ * momentum remap; paper §1.2, §2.3, §4.1, §4.4).  *dt_out (may be NULL)
+ * receives the step used.  Synchronizes. */
+int lr_step(lr_ctx *c, double *dt_out);
+
+/* Step until t reaches t_end (the last step is shortened to land on it) or
+ * max_steps steps were taken.  The time step is chosen on the device; the
+ * host checks completion every few steps only.  *steps_out, *t_out may be
+ * NULL.  Synchronizes. */
+int lr_run(lr_ctx *c, double t_end, long max_steps, long *steps_out, double *t_out);
+
+/* Copy the fields selected by field_mask into caller-allocated host arrays,
+ * out[0..popcount(mask)-1] in increasing bit order (shapes above). */
+int lr_get_fields(lr_ctx *c, unsigned field_mask, double *const *out);
+
+/* FP64 totals, out[3*nmat+3]: sum V_a, sum M_a, sum E_a per material, then
+ * sum w m_p u_x, sum w m_p u_y and the total energy sum E_a + sum w m_p |u|^2/2
+ * (m_p = 1/4 of the adjacent cell masses, w = 1, 1/2 on walls, 1/4 at corners). */
+int lr_totals(lr_ctx *c, double *out);
+
+/* Copy a named intermediate array of the last step into out (host), for
+ * stage-by-stage checks: "dt", "t", "Q", "S", "volcf", "VL" [ny][nx];
+ * "eL", "rhocf", "P_half" [nmat][ny][nx]; "mp", "uhx", "uhy", "uLx", "uLy",
+ * "dpx", "dpy", "muD", "muA" [ny+1][nx+1]; "muX" [ny][nx+1]; "muY" [ny+1][nx];
+ * "Wpx" [nmat][ny][nx+1]; "Wpy" [nmat][ny+1][nx]; "Wpc" [nmat][ny+1][nx+1].
+ * Fluxes are signed along +x, +y, the main diagonal (SW->NE) or the
+ * anti-diagonal (NW->SE). */
+int lr_debug_get(lr_ctx *c, const char *name, double *out);
+
+/* Text of the last failure on this context; valid until the next call. */
+const char *lr_last_error(const lr_ctx *c);
+
+/* Free the context and its device memory (NULL is ignored). */
+void lr_destroy(lr_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

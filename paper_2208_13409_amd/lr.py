@@ -1,0 +1,188 @@
+"""ctypes binding of ``liblr.so`` (the C-ABI in ``include/lr.h``).
+
+Argument marshalling only: every step of the scheme runs in the library's HIP
+kernels.  The functions keep the C names (``lr_create``, ``lr_set_state``,
+``lr_step``, ``lr_run``, ``lr_get_fields``, ``lr_totals``, ``lr_debug_get``,
+``lr_bind_stream``, ``lr_destroy``); ``Solver`` wraps one context.  There is
+no fallback: if the library is missing or the device is absent, the calls
+raise.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(_HERE, "liblr.so")
+_LIB = None
+
+LR_OK, LR_EINVAL, LR_ENOMEM, LR_EDEVICE, LR_ENEGATIVE, LR_ENAN, LR_EDT, LR_EAGAIN, LR_ESTATE = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+LR_FP64, LR_FP32 = 0, 1
+F_RHO, F_P, F_E, F_K, F_RHOA, F_EA, F_PA, F_UX, F_UY, F_VOL, F_MASS, F_IE = (1 << i for i in range(12))
+PER_MAT = {F_K, F_RHOA, F_EA, F_PA, F_VOL, F_MASS, F_IE}
+NODE = {F_UX, F_UY}
+FIELD_BITS = {"rho": F_RHO, "p": F_P, "e": F_E, "k": F_K, "rho_a": F_RHOA, "e_a": F_EA,
+              "p_a": F_PA, "ux": F_UX, "uy": F_UY, "vol": F_VOL, "mass": F_MASS, "ie": F_IE}
+EXPORTS = ("lr_default_opts", "lr_create", "lr_bind_stream", "lr_set_state", "lr_step", "lr_run",
+           "lr_get_fields", "lr_totals", "lr_debug_get", "lr_last_error", "lr_destroy")
+
+
+class lr_eos(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("pinf", C.c_double)]
+
+
+class lr_opts(C.Structure):
+    _fields_ = [("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double),
+                ("y1", C.c_double), ("cfl", C.c_double), ("a1", C.c_double),
+                ("a2", C.c_double), ("precision", C.c_int), ("recon_order", C.c_int),
+                ("kinematic", C.c_int), ("k_eps", C.c_double), ("fixed_dt", C.c_double)]
+
+
+class LRError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"liblr error {code}: {msg}")
+        self.code = code
+
+
+def load():
+    """Load liblr.so (built by ``paper_2208_13409_amd.build``); raise if absent."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(SO_PATH):
+        raise FileNotFoundError(f"{SO_PATH} is missing: run paper_2208_13409_amd/build.py "
+                                "(the HIP library is required; there is no fallback)")
+    lib = C.CDLL(SO_PATH)
+    P = C.POINTER
+    dp = P(C.c_double)
+    lib.lr_default_opts.argtypes = [P(lr_opts)]
+    lib.lr_default_opts.restype = None
+    lib.lr_create.argtypes = [C.c_int, C.c_int, C.c_int, P(lr_eos), P(C.c_int), P(lr_opts),
+                              P(C.c_void_p)]
+    lib.lr_bind_stream.argtypes = [C.c_void_p, C.c_void_p]
+    lib.lr_set_state.argtypes = [C.c_void_p, C.c_double, dp, dp, dp, dp, dp]
+    lib.lr_step.argtypes = [C.c_void_p, dp]
+    lib.lr_run.argtypes = [C.c_void_p, C.c_double, C.c_long, P(C.c_long), dp]
+    lib.lr_get_fields.argtypes = [C.c_void_p, C.c_uint, P(dp)]
+    lib.lr_totals.argtypes = [C.c_void_p, dp]
+    lib.lr_debug_get.argtypes = [C.c_void_p, C.c_char_p, dp]
+    lib.lr_last_error.argtypes = [C.c_void_p]
+    lib.lr_last_error.restype = C.c_char_p
+    lib.lr_destroy.argtypes = [C.c_void_p]
+    lib.lr_destroy.restype = None
+    for n in ("lr_create", "lr_bind_stream", "lr_set_state", "lr_step", "lr_run",
+              "lr_get_fields", "lr_totals", "lr_debug_get"):
+        getattr(lib, n).restype = C.c_int
+    _LIB = lib
+    return lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def lr_default_opts():
+    o = lr_opts()
+    load().lr_default_opts(C.byref(o))
+    return o
+
+
+def lr_create(nx, ny, gammas, opts):
+    eos = (lr_eos * len(gammas))(*[lr_eos(float(g), 0.0) for g in gammas])
+    bc = (C.c_int * 4)(0, 0, 0, 0)
+    h = C.c_void_p()
+    rc = load().lr_create(int(nx), int(ny), len(gammas), eos, bc, C.byref(opts), C.byref(h))
+    if rc != LR_OK:
+        raise LRError(rc, "lr_create failed")
+    return h
+
+
+class Solver:
+    """One problem on the GPU library (same methods as the oracle's RefSolver)."""
+
+    def __init__(self, nx, ny, gammas, domain=(0.0, 1.0, 0.0, 1.0), cfl=0.5, a1=0.5, a2=1.0,
+                 recon_order=2, kinematic=False, k_eps=1e-10, fixed_dt=0.0, precision=LR_FP64,
+                 stream=None):
+        self.lib = load()
+        self.nx, self.ny, self.nmat = int(nx), int(ny), len(gammas)
+        o = lr_default_opts()
+        o.x0, o.x1, o.y0, o.y1 = map(float, domain)
+        o.cfl, o.a1, o.a2 = float(cfl), float(a1), float(a2)
+        o.recon_order, o.kinematic = int(recon_order), int(bool(kinematic))
+        o.k_eps, o.fixed_dt, o.precision = float(k_eps), float(fixed_dt), int(precision)
+        self.h = lr_create(nx, ny, gammas, o)
+        if stream is not None:
+            self.bind_stream(stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lr_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def _check(self, rc):
+        if rc != LR_OK:
+            raise LRError(rc, self.lib.lr_last_error(self.h).decode())
+        return rc
+
+    def bind_stream(self, stream):
+        """stream: a torch.cuda.Stream (its cuda_stream handle is used) or a raw handle."""
+        handle = getattr(stream, "cuda_stream", stream)
+        self._check(self.lib.lr_bind_stream(self.h, C.c_void_p(handle)))
+
+    def set_state(self, t, k, rho, e, ux, uy):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (k, rho, e, ux, uy)]
+        self._check(self.lib.lr_set_state(self.h, float(t), *[_dptr(a) for a in arrs]))
+
+    def step(self):
+        dt = C.c_double()
+        self._check(self.lib.lr_step(self.h, C.byref(dt)))
+        return dt.value
+
+    def run(self, t_end, max_steps=1 << 40):
+        n, t = C.c_long(), C.c_double()
+        self._check(self.lib.lr_run(self.h, float(t_end), int(max_steps), C.byref(n), C.byref(t)))
+        return n.value, t.value
+
+    def run_raw(self, t_end, max_steps=1 << 40):
+        n, t = C.c_long(), C.c_double()
+        rc = self.lib.lr_run(self.h, float(t_end), int(max_steps), C.byref(n), C.byref(t))
+        return rc, n.value, t.value
+
+    def fields(self, *names):
+        mask = 0
+        for n_ in names:
+            mask |= FIELD_BITS[n_]
+        bufs, outs = {}, []
+        for bit in sorted(FIELD_BITS.values()):
+            if not mask & bit:
+                continue
+            if bit in PER_MAT:
+                shape = (self.nmat, self.ny, self.nx)
+            elif bit in NODE:
+                shape = (self.ny + 1, self.nx + 1)
+            else:
+                shape = (self.ny, self.nx)
+            bufs[bit] = np.zeros(shape)
+            outs.append(bufs[bit])
+        ptrs = (C.POINTER(C.c_double) * len(outs))(*[_dptr(b) for b in outs])
+        self._check(self.lib.lr_get_fields(self.h, mask, ptrs))
+        return {n_: bufs[FIELD_BITS[n_]] for n_ in names}
+
+    def totals(self):
+        out = np.zeros(3 * self.nmat + 3)
+        self._check(self.lib.lr_totals(self.h, _dptr(out)))
+        return out
+
+    def stage(self, name):
+        nx, ny, nm = self.nx, self.ny, self.nmat
+        shapes = {"Q": (ny, nx), "S": (ny, nx), "volcf": (ny, nx), "VL": (ny, nx),
+                  "dxL": (ny, nx), "dyL": (ny, nx), "eL": (nm, ny, nx), "rhocf": (nm, ny, nx),
+                  "P_half": (nm, ny, nx), "muX": (ny, nx + 1), "muY": (ny + 1, nx),
+                  "Wpx": (nm, ny, nx + 1), "Wpy": (nm, ny + 1, nx), "Wpc": (nm, ny + 1, nx + 1),
+                  "dt": (1,), "t": (1,)}
+        out = np.zeros(shapes.get(name, (ny + 1, nx + 1)))
+        self._check(self.lib.lr_debug_get(self.h, name.encode(), _dptr(out)))
+        return out

@@ -1,0 +1,67 @@
+"""C-ABI contract checks that need no GPU: the HIP library loads and exports
+every entry point declared in include/lr.h, the oracle exports the same call
+shapes, and the binding refuses to work without the library or a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    text = open(os.path.join(ROOT, header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lr_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared("include/lr.h")
+    for n in ("lr_create", "lr_set_state", "lr_step", "lr_run", "lr_get_fields", "lr_totals",
+              "lr_destroy", "lr_bind_stream", "lr_last_error", "lr_debug_get", "lr_default_opts"):
+        assert n in names
+
+
+def test_hip_library_exports_every_declared_symbol():
+    so = os.path.join(ROOT, "paper_2208_13409_amd", "liblr.so")
+    if not os.path.exists(so):
+        from paper_2208_13409_amd import build
+        build.build()
+    lib = ctypes.CDLL(so)
+    for n in _declared("include/lr.h"):
+        assert hasattr(lib, n), n
+
+
+def test_oracle_exports_the_same_calls():
+    from oracle import load
+    lib = load()
+    for n in _declared("include/lr.h"):
+        if n == "lr_bind_stream":
+            continue  # host-only oracle: no streams
+        assert hasattr(lib, n.replace("lr_", "lr_ref_", 1)), n
+
+
+def test_binding_has_no_fallback(monkeypatch, tmp_path):
+    from paper_2208_13409_amd import lr
+    monkeypatch.setattr(lr, "_LIB", None)
+    monkeypatch.setattr(lr, "SO_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(FileNotFoundError):
+        lr.Solver(4, 4, [1.4])
+
+
+def test_argument_validation_without_device():
+    """Bad sizes are rejected before any device call."""
+    from paper_2208_13409_amd import lr
+    lib = lr.load()
+    o = lr.lr_default_opts()
+    eos = (lr.lr_eos * 1)(lr.lr_eos(1.4, 0.0))
+    h = ctypes.c_void_p()
+    assert lib.lr_create(1, 4, 1, eos, None, ctypes.byref(o), ctypes.byref(h)) == lr.LR_EINVAL
+    assert lib.lr_create(4, 4, 0, eos, None, ctypes.byref(o), ctypes.byref(h)) == lr.LR_EINVAL
+    o.precision = 7
+    assert lib.lr_create(4, 4, 1, eos, None, ctypes.byref(o), ctypes.byref(h)) == lr.LR_EINVAL
+    bad = (lr.lr_eos * 1)(lr.lr_eos(1.4, 3.0))
+    o = lr.lr_default_opts()
+    assert lib.lr_create(4, 4, 1, bad, None, ctypes.byref(o), ctypes.byref(h)) == lr.LR_EINVAL
+    assert lib.lr_step(None, None) == lr.LR_EINVAL

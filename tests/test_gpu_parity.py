@@ -1,0 +1,233 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle, element by
+element on the same seeded inputs.  Tolerances: FP64 mode, relative L1 of
+density and pressure <= 1e-10, and element-wise relative error <= 1e-9
+(scaled by the field's magnitude) on every conserved quantity."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import RefSolver
+from paper_2208_13409_amd import inputs
+from paper_2208_13409_amd.lr import LRError, Solver
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-9
+L1_TOL = 1e-10
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def pair(p, **kw):
+    g = Solver(p["nx"], p["ny"], p["gammas"], p["domain"], **kw)
+    r = RefSolver(p["nx"], p["ny"], p["gammas"], p["domain"], **kw)
+    for s in (g, r):
+        s.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+    return g, r
+
+
+def close(a, b, rtol=RTOL, name=""):
+    scale = max(np.abs(b).max(), 1e-300)
+    err = np.abs(a - b).max() / scale
+    assert err <= rtol, f"{name}: max scaled error {err:.3e} > {rtol}"
+    return err
+
+
+def rel_l1(a, b):
+    return np.abs(a - b).sum() / max(np.abs(b).sum(), 1e-300)
+
+
+def compare_state(g, r, tag):
+    fg = g.fields("vol", "mass", "ie", "ux", "uy", "rho", "p")
+    fr = r.fields("vol", "mass", "ie", "ux", "uy", "rho", "p")
+    for key in ("vol", "mass", "ie"):
+        for a in range(fr[key].shape[0]):
+            close(fg[key][a], fr[key][a], name=f"{tag} {key}[{a}]")
+    uscale = max(np.abs(fr["ux"]).max(), np.abs(fr["uy"]).max(), 1e-12)
+    assert np.abs(fg["ux"] - fr["ux"]).max() <= RTOL * uscale, f"{tag} ux"
+    assert np.abs(fg["uy"] - fr["uy"]).max() <= RTOL * uscale, f"{tag} uy"
+    l1r, l1p = rel_l1(fg["rho"], fr["rho"]), rel_l1(fg["p"], fr["p"])
+    assert l1r <= L1_TOL and l1p <= L1_TOL, f"{tag} L1 rho {l1r:.2e} p {l1p:.2e}"
+    return l1r, l1p
+
+
+# ------------------------------------------------------------------ stages ---
+@pytest.mark.parametrize("nmat,seed", [(2, 101), (3, 102)])
+def test_stage_parity_one_step(nmat, seed):
+    """Every intermediate of one step: Q, P+Q, nodal velocities, volumes,
+    Lagrangian energies, flux-consistent densities, region fluxes."""
+    p = inputs.random_mixed(seed, 77, 45, nmat=nmat)
+    say(f"stage parity nmat={nmat} seed={seed} 77x45")
+    g, r = pair(p)
+    dg, dr = g.step(), r.step()
+    assert dg == dr
+    for name in ("Q", "S", "volcf", "VL", "mp", "uhx", "uhy", "uLx", "uLy", "eL", "rhocf",
+                 "P_half", "dxL", "dyL"):
+        a, b = g.stage(name), r.stage(name)
+        if name in ("eL",):  # energies of absent materials are not defined
+            k = r.fields("k")["k"]
+            a, b = np.where(k > 1e-10, a, 0), np.where(k > 1e-10, b, 0)
+        close(a, b, name=name)
+    # region fluxes (wall faces carry nothing)
+    close(g.stage("muX")[:, 1:-1], r.stage("muX")[:, 1:-1], name="muX")
+    close(g.stage("muY")[1:-1, :], r.stage("muY")[1:-1, :], name="muY")
+    close(g.stage("muD")[1:-1, 1:-1], r.stage("muD")[1:-1, 1:-1], name="muD")
+    close(g.stage("muA")[1:-1, 1:-1], r.stage("muA")[1:-1, 1:-1], name="muA")
+    for a in range(nmat):
+        close(g.stage("Wpx")[a][:, 1:-1], r.stage("Wpx")[a][:, 1:-1], name=f"Wpx{a}")
+        close(g.stage("Wpy")[a][1:-1, :], r.stage("Wpy")[a][1:-1, :], name=f"Wpy{a}")
+        close(g.stage("Wpc")[a][1:-1, 1:-1], r.stage("Wpc")[a][1:-1, 1:-1], name=f"Wpc{a}")
+    compare_state(g, r, "after 1 step")
+
+
+# ------------------------------------------------------------ whole runs -----
+@pytest.mark.parametrize("nx,ny,nmat,seed,steps", [
+    (131, 67, 2, 7, 25),      # several 64x4 tiles and ragged tails
+    (200, 120, 3, 8, 15),
+    (2, 2, 1, 9, 10),         # smallest grid
+    (5, 3, 4, 10, 10),        # four materials on a tiny grid
+    (64, 4, 2, 11, 30),       # exactly one tile wide
+])
+def test_random_mixed_runs(nx, ny, nmat, seed, steps):
+    p = inputs.random_mixed(seed, nx, ny, nmat=nmat)
+    say(f"random mixed {nx}x{ny} nmat={nmat} seed={seed} steps={steps}")
+    g, r = pair(p)
+    for it in range(steps):
+        dg, dr = g.step(), r.step()
+        assert dg == pytest.approx(dr, rel=1e-12), f"dt differs at step {it}"
+    compare_state(g, r, f"{nx}x{ny}")
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_first_order_and_kinematic_modes(order):
+    p = inputs.random_mixed(21, 50, 40, nmat=2)
+    say(f"recon_order={order} full and kinematic")
+    g, r = pair(p, recon_order=order)
+    for _ in range(10):
+        assert g.step() == pytest.approx(r.step(), rel=1e-12)
+    compare_state(g, r, f"order {order}")
+    g, r = pair(p, recon_order=order, kinematic=True)
+    for _ in range(10):
+        assert g.step() == pytest.approx(r.step(), rel=1e-12)
+    compare_state(g, r, f"kinematic order {order}")
+
+
+def test_sod_full_run():
+    """Sod tube 400x4 to t = 0.2: same number of steps, final time exactly
+    t_end, fields within tolerance."""
+    p = inputs.sod(400, 4)
+    say("sod 400x4 to t=0.2")
+    g, r = pair(p)
+    ng, tg = g.run(p["t_end"])
+    nr, tr = r.run(p["t_end"])
+    assert ng == nr and tg == tr == p["t_end"]
+    l1r, l1p = compare_state(g, r, "sod")
+    say(f"sod parity L1 rho {l1r:.3e} p {l1p:.3e} steps {ng}")
+
+
+def test_triple_point_full_size_steps():
+    """Triple point at its full 448x192 size, 20 steps (the oracle computes
+    every cell), then 200 more on the GPU alone checked by conservation."""
+    p = inputs.triple_point(1)
+    say("triple point 448x192, 20 steps")
+    g, r = pair(p)
+    ng, _ = g.run(p["t_end"], max_steps=20)
+    nr, _ = r.run(p["t_end"], max_steps=20)
+    assert ng == nr == 20
+    compare_state(g, r, "triple point")
+    t0 = g.totals()
+    g.run(p["t_end"], max_steps=200)
+    t1 = g.totals()
+    m0, m1 = t0[3:6], t1[3:6]
+    assert np.all(np.abs(m1 - m0) <= 1e-12 * m0)
+    assert abs(t1[:3].sum() - 21.0) < 1e-12 * 21.0
+
+
+# ---------------------------------------------------------- paper pins -------
+@pytest.mark.parametrize("sx,sy", [(1, 1), (-1, -1), (1, -1), (-1, 1)])
+def test_gpu_corner_transport_formula(sx, sy):
+    """§3.1 bilinear corner-transport formula on the GPU directly."""
+    nx, ny, ex, ey = 12, 10, 0.3, 0.2
+    rng = np.random.default_rng(5)
+    rho = rng.uniform(0.5, 2.0, size=(ny, nx))
+    say(f"gpu CTU {sx},{sy}")
+    g = Solver(nx, ny, [1.4], (0.0, nx, 0.0, ny), recon_order=1, kinematic=True, fixed_dt=1.0)
+    g.set_state(0.0, np.ones((1, ny, nx)), rho[None], np.ones((1, ny, nx)),
+                np.full((ny + 1, nx + 1), sx * ex), np.full((ny + 1, nx + 1), sy * ey))
+    g.step()
+    got = g.fields("mass")["mass"][0]
+    for j in range(2, ny - 2):
+        for i in range(2, nx - 2):
+            a = rho[j, i] * (1 - ex) * (1 - ey) + rho[j, i - sx] * ex * (1 - ey) + \
+                rho[j - sy, i] * ey * (1 - ex) + rho[j - sy, i - sx] * ex * ey
+            assert got[j, i] == pytest.approx(a, rel=1e-14)
+
+
+def test_gpu_single_node_displacement():
+    """§3.2 single displaced node on the GPU: Vol^CF = 1 + eps/(1+eps) + eps^2."""
+    n, eps = 5, 0.1
+    k = np.zeros((2, n, n))
+    k[1] = 1.0
+    k[0, 2, 2], k[1, 2, 2] = 1.0, 0.0
+    ux = np.zeros((n + 1, n + 1))
+    uy = np.zeros((n + 1, n + 1))
+    ux[3, 3] = uy[3, 3] = eps
+    say("gpu single node")
+    g = Solver(n, n, [1.4, 1.4], (0.0, n, 0.0, n), recon_order=1, kinematic=True, fixed_dt=1.0)
+    g.set_state(0.0, k, np.where(k > 0, 1.0, 0.0), np.where(k > 0, 1.0, 0.0), ux, uy)
+    g.step()
+    vcf = 1.0 + eps / (1.0 + eps) + eps ** 2
+    assert g.stage("VL")[2, 2] == pytest.approx(1.0 + eps, rel=1e-14)
+    assert g.stage("volcf")[2, 2] == pytest.approx(vcf, rel=1e-14)
+    m = g.fields("mass")["mass"][0]
+    assert m[3, 3] == pytest.approx(eps ** 2 / vcf, rel=1e-13)
+
+
+# ------------------------------------------------------ properties -----------
+def test_run_equals_steps_and_is_deterministic():
+    p = inputs.random_mixed(31, 90, 70, nmat=2)
+    say("run vs step, determinism")
+    a = Solver(p["nx"], p["ny"], p["gammas"], p["domain"])
+    b = Solver(p["nx"], p["ny"], p["gammas"], p["domain"])
+    for s in (a, b):
+        s.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+    n, t = a.run(0.05)
+    assert t == 0.05
+    m = 0
+    while True:
+        rc, k_, tb = b.run_raw(0.05, max_steps=1)
+        assert rc == 0
+        m += k_
+        if tb >= 0.05:
+            break
+    assert m == n
+    fa, fb = a.fields("vol", "mass", "ie", "ux", "uy"), b.fields("vol", "mass", "ie", "ux", "uy")
+    for key in fa:
+        assert np.array_equal(fa[key], fb[key]), key
+
+
+def test_error_paths():
+    p = inputs.random_mixed(41, 10, 8, nmat=2)
+    say("error paths")
+    g = Solver(p["nx"], p["ny"], p["gammas"], p["domain"])
+    with pytest.raises(LRError) as ex:
+        g.step()
+    assert ex.value.code == -8
+    bad = p["k"].copy()
+    bad[0, 0, 0] += 0.1
+    with pytest.raises(LRError) as ex:
+        g.set_state(0.0, bad, p["rho"], p["e"], p["ux"], p["uy"])
+    assert ex.value.code == -8
+    g.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+    with pytest.raises(LRError) as ex:
+        g.run(-1.0)
+    assert ex.value.code == -1
+    # an absurd CFL number drives the state negative: reported, not crashed
+    h = Solver(p["nx"], p["ny"], p["gammas"], p["domain"], cfl=50.0)
+    h.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+    rc, n, _ = h.run_raw(1.0, max_steps=50)
+    assert rc in (-4, -5, -6)
