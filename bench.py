@@ -1,0 +1,164 @@
+#!/usr/bin/env python3
+"""Throughput of the DirectCF multimaterial Lagrange–Remap step on one MI355X.
+
+A step is one pass of the whole hot path (CFL time step, staggered
+Lagrangian phase, DirectCF remap with VOF partial fluxes, momentum remap)
+over the grid.  The default workload is the three-material triple point,
+448 x 192 cells, FP64, synthetic initial state (no dataset); the metric is
+cell-updates per second = cells x steps / wall time of the timed steps, with
+the state resident in device memory.
+
+Prints one JSON line.  The "roofline" object is for the dominant kernel:
+its algorithmic bytes per launch (each array it must read or write touched
+once) over its average duration measured with HIP event pairs on the
+kernel's own stream.  "cpu_baseline" is the FP64 oracle timed on a bounded
+sample of the same workload on the host (one thread).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+W64 = 8
+
+
+def kernel_bytes(nx, ny, nmat, w=W64):
+    """Algorithmic bytes per launch of each kernel: every array the kernel has
+    to read or write, touched once (C cells, N nodes, region fluxes
+    3 nmat + 1 values on the C x-faces, y-faces and corners)."""
+    C = nx * ny
+    N = (nx + 1) * (ny + 1)
+    R = ((nx + 1) * ny + nx * (ny + 1) + N) * (3 * nmat + 1)
+    return {
+        "k_lag_cell": w * (3 * nmat * C + 2 * N + (3 + nmat) * C),
+        "k_lag_node": w * (2 * C + 2 * N + 5 * N),
+        "k_remap_cell": w * (2 * N + 4 * nmat * C + C + 6 * C + 2 * nmat * C) + 4 * C,
+        "k_flux": w * (2 * N + 4 * nmat * C + 5 * C + R) + 4 * C,
+        "k_update_cell": w * (R + 2 * N + 4 * nmat * C + C + 3 * nmat * C + C),
+        "k_update_node": w * (3 * C + 7 * N + 2 * N + C),
+        "k_control": 64,
+    }
+
+
+def step_bytes(nx, ny, nmat, w=W64):
+    """The per-cell-update figure of the whole step: the persistent state
+    (V, M, E per material and the nodal velocity) read and written once."""
+    return 2 * (3 * nmat + 2) * w * nx * ny
+
+
+def workload(name):
+    from paper_2208_13409_amd import inputs
+    if name == "triple_point_448x192":
+        return inputs.triple_point(1)
+    if name == "triple_point_1792x768":
+        return inputs.triple_point(4)
+    if name == "sod_400x4":
+        return inputs.sod(400, 4)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(p, steps):
+    from oracle import RefSolver
+    r = RefSolver(p["nx"], p["ny"], p["gammas"], p["domain"])
+    r.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+    t0 = time.perf_counter()
+    n, _ = r.run(p["t_end"], max_steps=steps)
+    el = time.perf_counter() - t0
+    return {"value": p["nx"] * p["ny"] * n / el, "unit": "cell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{p['name']} FP64, the first {n} steps from t=0, single thread "
+                      f"({el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="triple_point_448x192")
+    ap.add_argument("--profile-steps", type=int, default=64,
+                    help="steps run again with per-kernel HIP event pairs")
+    ap.add_argument("--cpu-steps", type=int, default=150)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2208_13409_amd.lr import Solver
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    p = workload(args.workload)
+    nx, ny, nmat = p["nx"], p["ny"], len(p["gammas"])
+    cells = nx * ny
+    stream = torch.cuda.Stream()
+    g = Solver(nx, ny, p["gammas"], p["domain"], stream=stream)
+    g.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+    t_end = 1e30  # the timed steps follow the CFL step and never land on t_end
+
+    nw, _ = g.run(t_end, max_steps=args.warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    t0 = time.perf_counter()
+    n, t = g.run(t_end, max_steps=args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    assert n == args.steps, f"only {n} of {args.steps} steps ran"
+
+    # the same kind of steps again, with an event pair around every launch
+    g.profile(True)
+    g.run(t_end, max_steps=args.profile_steps)
+    prof = g.profile_read()
+    g.profile(False)
+    kb = kernel_bytes(nx, ny, nmat)
+    avg_us = {k: (ms / cnt * 1e3 if cnt else 0.0) for k, (ms, cnt) in prof.items()}
+    dom = max(prof, key=lambda k: prof[k][0])
+    dom_s = avg_us[dom] * 1e-6
+    achieved = kb[dom] / dom_s / 1e9
+    step_us = sum(avg_us.values())
+    value = cells * n / wall
+    out = {
+        "metric": "cell-updates/s per step (FP64 plain, 1 GPU)",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": n,
+        "warmup": nw,
+        "ms_per_step": wall * 1e3 / n,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": p["name"], "nx": nx, "ny": ny, "nmat": nmat, "precision": "fp64",
+                   "t_start": 0.0, "cfl": 0.5},
+        "gpu_event_ms_per_step": gpu_ms / n,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": kb[dom], "avg_launch_us": avg_us[dom]},
+        "roofline_step": {"bytes_per_cell_update": step_bytes(1, 1, nmat),
+                          "achieved_GBs": step_bytes(nx, ny, nmat) / (wall / n) / 1e9,
+                          "frac": step_bytes(nx, ny, nmat) / (wall / n) / 1e9 / HBM_PEAK_GBS,
+                          "sum_kernel_us": step_us},
+        "kernels_avg_us": avg_us,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

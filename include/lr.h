@@ -124,6 +124,16 @@ int lr_totals(lr_ctx *c, double *out);
  * anti-diagonal (NW->SE). */
 int lr_debug_get(lr_ctx *c, const char *name, double *out);
 
+/* Kernel timing for benchmarks.  lr_profile(c, 1) makes every later step
+ * record a HIP event pair around each of its kernel launches on the
+ * context's stream; lr_profile_read adds up the elapsed milliseconds and the
+ * launch counts per kernel into ms[n], counts[n] (n <= lr_kernel_count(), in
+ * the order of lr_kernel_name(i)) and resets them.  Off by default. */
+int lr_profile(lr_ctx *c, int enable);
+int lr_profile_read(lr_ctx *c, double *ms, long *counts, int n);
+int lr_kernel_count(void);
+const char *lr_kernel_name(int i);
+
 /* Text of the last failure on this context; valid until the next call. */
 const char *lr_last_error(const lr_ctx *c);
 

@@ -1046,6 +1046,12 @@ struct lr_ctx {
   std::vector<void *> allocs;
   double *scratch = nullptr;  // staging for outputs, C*nmat doubles at least
   size_t scratch_n = 0;
+  // kernel timing (lr_profile): event pairs of the steps of one chunk
+  bool prof = false;
+  std::vector<hipEvent_t> ev;  // [kChunk][kKernels][2]
+  int prof_steps = 0;          // steps recorded in the current chunk
+  double prof_ms[16] = {0};
+  long prof_n[16] = {0};
 };
 
 namespace {
@@ -1077,18 +1083,45 @@ dim3 node_grid(const Grid &g, dim3 b) {
   return dim3((g.nx + 1 + b.x - 1) / b.x, (g.ny + 1 + b.y - 1) / b.y);
 }
 const dim3 kBlock(64, 4);
+constexpr int kChunk = 16;  // steps between completion checks
+constexpr int kKernels = 7;
+const char *const kKernelNames[kKernels] = {"k_lag_cell",    "k_lag_node",    "k_remap_cell",
+                                            "k_flux",        "k_update_cell", "k_update_node",
+                                            "k_control"};
 
 int launch_step(lr_ctx *c) {
   const Grid &g = c->g;
   hipStream_t s = c->stream;
-  k_lag_cell<<<cell_grid(g, kBlock), kBlock, 0, s>>>(g, c->f);
-  k_lag_node<<<node_grid(g, kBlock), kBlock, 0, s>>>(g, c->f);
-  k_remap_cell<<<cell_grid(g, kBlock), kBlock, 0, s>>>(g, c->f);
-  k_flux<<<cell_grid(g, kBlock), kBlock, 0, s>>>(g, c->f);
-  k_update_cell<<<cell_grid(g, kBlock), kBlock, 0, s>>>(g, c->f);
-  k_update_node<<<node_grid(g, kBlock), kBlock, 0, s>>>(g, c->f);
-  k_control<<<1, 1, 0, s>>>(g, c->f.s, 1, 0.0, 0);
+  const bool prof = c->prof && c->prof_steps < kChunk;
+  hipEvent_t *ev = prof ? &c->ev[(size_t)c->prof_steps * kKernels * 2] : nullptr;
+  auto mark = [&](int k, int side) {
+    if (prof) (void)hipEventRecord(ev[2 * k + side], s);
+  };
+  mark(0, 0); k_lag_cell<<<cell_grid(g, kBlock), kBlock, 0, s>>>(g, c->f); mark(0, 1);
+  mark(1, 0); k_lag_node<<<node_grid(g, kBlock), kBlock, 0, s>>>(g, c->f); mark(1, 1);
+  mark(2, 0); k_remap_cell<<<cell_grid(g, kBlock), kBlock, 0, s>>>(g, c->f); mark(2, 1);
+  mark(3, 0); k_flux<<<cell_grid(g, kBlock), kBlock, 0, s>>>(g, c->f); mark(3, 1);
+  mark(4, 0); k_update_cell<<<cell_grid(g, kBlock), kBlock, 0, s>>>(g, c->f); mark(4, 1);
+  mark(5, 0); k_update_node<<<node_grid(g, kBlock), kBlock, 0, s>>>(g, c->f); mark(5, 1);
+  mark(6, 0); k_control<<<1, 1, 0, s>>>(g, c->f.s, 1, 0.0, 0); mark(6, 1);
+  if (prof) ++c->prof_steps;
   HIP_CHECK(c, hipGetLastError());
+  return LR_OK;
+}
+
+// add up the event pairs recorded since the last completion check
+int collect_profile(lr_ctx *c) {
+  if (!c->prof || c->prof_steps == 0) return LR_OK;
+  HIP_CHECK(c, hipStreamSynchronize(c->stream));
+  for (int st = 0; st < c->prof_steps; ++st)
+    for (int k = 0; k < kKernels; ++k) {
+      float ms = 0.0f;
+      hipEvent_t *e = &c->ev[((size_t)st * kKernels + k) * 2];
+      HIP_CHECK(c, hipEventElapsedTime(&ms, e[0], e[1]));
+      c->prof_ms[k] += ms;
+      c->prof_n[k] += 1;
+    }
+  c->prof_steps = 0;
   return LR_OK;
 }
 
@@ -1113,9 +1146,11 @@ int run_steps(lr_ctx *c, double t_end, long long max_steps) {
   const long long limit = c->hs->step + max_steps;
   k_control<<<1, 1, 0, c->stream>>>(c->g, c->f.s, 0, t_end, limit);
   HIP_CHECK(c, hipGetLastError());
-  const int chunk = 16;
+  const int chunk = kChunk;
   for (;;) {
     int rc = read_scalars(c);
+    if (rc) return rc;
+    rc = collect_profile(c);
     if (rc) return rc;
     if (c->hs->done) break;
     const long long left = c->hs->step_limit - c->hs->step;
@@ -1144,6 +1179,7 @@ void lr_default_opts(lr_opts *o) {
 void lr_destroy(lr_ctx *c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   for (void *p : c->allocs) (void)hipFree(p);
   if (c->hs) (void)hipHostFree(c->hs);
   if (c->own) (void)hipStreamDestroy(c->own);
@@ -1417,6 +1453,36 @@ int lr_debug_get(lr_ctx *c, const char *name, double *out) {
   }
   return set_err(c, LR_EINVAL, "unknown stage name");
 }
+
+int lr_profile(lr_ctx *c, int enable) {
+  if (!c) return LR_EINVAL;
+  if (enable && c->ev.empty()) {
+    c->ev.resize((size_t)kChunk * kKernels * 2);
+    for (auto &e : c->ev) HIP_CHECK(c, hipEventCreate(&e));
+  }
+  c->prof = enable != 0;
+  c->prof_steps = 0;
+  return LR_OK;
+}
+
+int lr_profile_read(lr_ctx *c, double *ms, long *counts, int n) {
+  if (!c || n < 0 || n > kKernels) return LR_EINVAL;
+  int rc = collect_profile(c);
+  if (rc) return rc;
+  for (int k = 0; k < n; ++k) {
+    if (ms) ms[k] = c->prof_ms[k];
+    if (counts) counts[k] = c->prof_n[k];
+  }
+  for (int k = 0; k < kKernels; ++k) {
+    c->prof_ms[k] = 0.0;
+    c->prof_n[k] = 0;
+  }
+  return LR_OK;
+}
+
+int lr_kernel_count(void) { return kKernels; }
+
+const char *lr_kernel_name(int i) { return (i >= 0 && i < kKernels) ? kKernelNames[i] : ""; }
 
 const char *lr_last_error(const lr_ctx *c) { return c ? c->err.c_str() : "null context"; }
 

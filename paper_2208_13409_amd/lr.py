@@ -25,7 +25,8 @@ NODE = {F_UX, F_UY}
 FIELD_BITS = {"rho": F_RHO, "p": F_P, "e": F_E, "k": F_K, "rho_a": F_RHOA, "e_a": F_EA,
               "p_a": F_PA, "ux": F_UX, "uy": F_UY, "vol": F_VOL, "mass": F_MASS, "ie": F_IE}
 EXPORTS = ("lr_default_opts", "lr_create", "lr_bind_stream", "lr_set_state", "lr_step", "lr_run",
-           "lr_get_fields", "lr_totals", "lr_debug_get", "lr_last_error", "lr_destroy")
+           "lr_get_fields", "lr_totals", "lr_debug_get", "lr_last_error", "lr_destroy",
+           "lr_profile", "lr_profile_read", "lr_kernel_count", "lr_kernel_name")
 
 
 class lr_eos(C.Structure):
@@ -71,8 +72,14 @@ def load():
     lib.lr_last_error.restype = C.c_char_p
     lib.lr_destroy.argtypes = [C.c_void_p]
     lib.lr_destroy.restype = None
+    lib.lr_profile.argtypes = [C.c_void_p, C.c_int]
+    lib.lr_profile_read.argtypes = [C.c_void_p, dp, P(C.c_long), C.c_int]
+    lib.lr_kernel_count.argtypes = []
+    lib.lr_kernel_name.argtypes = [C.c_int]
+    lib.lr_kernel_name.restype = C.c_char_p
     for n in ("lr_create", "lr_bind_stream", "lr_set_state", "lr_step", "lr_run",
-              "lr_get_fields", "lr_totals", "lr_debug_get"):
+              "lr_get_fields", "lr_totals", "lr_debug_get", "lr_profile", "lr_profile_read",
+              "lr_kernel_count"):
         getattr(lib, n).restype = C.c_int
     _LIB = lib
     return lib
@@ -175,6 +182,17 @@ class Solver:
         out = np.zeros(3 * self.nmat + 3)
         self._check(self.lib.lr_totals(self.h, _dptr(out)))
         return out
+
+    def profile(self, enable=True):
+        self._check(self.lib.lr_profile(self.h, int(bool(enable))))
+
+    def profile_read(self):
+        """{kernel name: (total ms, launches)} since the last read."""
+        n = self.lib.lr_kernel_count()
+        ms = np.zeros(n)
+        cnt = (C.c_long * n)()
+        self._check(self.lib.lr_profile_read(self.h, _dptr(ms), cnt, n))
+        return {self.lib.lr_kernel_name(i).decode(): (float(ms[i]), int(cnt[i])) for i in range(n)}
 
     def stage(self, name):
         nx, ny, nm = self.nx, self.ny, self.nmat
