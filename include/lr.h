@@ -44,11 +44,14 @@ typedef struct {
   double x0, x1, y0, y1; /* domain; dx = (x1-x0)/nx, dy = (y1-y0)/ny                    */
   double cfl;            /* CFL number; default 0.5                                     */
   double a1, a2;         /* Wilkins linear / quadratic pseudo-viscosity (§1.2); 0.5, 1.0  */
-  int precision;         /* LR_FP64 (default); LR_FP32 returns LR_EINVAL in this build    */
+  int precision;         /* LR_FP64 (default) or LR_FP32: FP32 bulk arithmetic and state,
+                            FP64 interface, clipping and totals, compensated cell sums    */
   int recon_order;       /* 1 = upwind everywhere, 2 = limited linear (§2.1.1, §3.3)      */
   int kinematic;         /* 1 = node velocities prescribed, no forces, no momentum remap  */
-  double k_eps;          /* a material is present where V_a > k_eps * dx*dy; 1e-10        */
+  double k_eps;          /* a material is present where V_a > k_eps * dx*dy; 1e-10
+                            (FP32 uses at least 1e-6)                                     */
   double fixed_dt;       /* > 0: this time step instead of the CFL one                    */
+  int stages;            /* 1 = keep the intermediates of each step for lr_debug_get      */
 } lr_opts;
 
 /* field mask bits for lr_get_fields, in the order the output pointers are
@@ -116,7 +119,9 @@ int lr_get_fields(lr_ctx *c, unsigned field_mask, double *const *out);
 int lr_totals(lr_ctx *c, double *out);
 
 /* Copy a named intermediate array of the last step into out (host), for
- * stage-by-stage checks: "dt", "t", "Q", "S", "volcf", "VL" [ny][nx];
+ * stage-by-stage checks (all but "dt", "t", "eL", "mp", "uh*", "uL*", "dp*",
+ * "muX", "muY", "muD", "muA" need opts.stages = 1): "dt", "t", "Q", "S",
+ * "volcf", "VL" [ny][nx];
  * "eL", "rhocf", "P_half" [nmat][ny][nx]; "mp", "uhx", "uhy", "uLx", "uLy",
  * "dpx", "dpy", "muD", "muA" [ny+1][nx+1]; "muX" [ny][nx+1]; "muY" [ny+1][nx];
  * "Wpx" [nmat][ny][nx+1]; "Wpy" [nmat][ny+1][nx]; "Wpc" [nmat][ny+1][nx+1].

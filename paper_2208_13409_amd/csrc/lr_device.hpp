@@ -1,7 +1,8 @@
 // lr_device.hpp — device helpers of the DirectCF Lagrange–Remap kernels
 // (gfx950).  Geometry of the flux volumes (paper §2.3), closed-form
 // rectangle / half-plane areas and their inverse for the VOF interface (§4.4),
-// the Van Leer limited slope (§2.1.1) and the wall mirrors.
+// the Van Leer limited slope (§2.1.1), the wall mirrors, and the per-problem
+// descriptors the kernels work on.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -10,32 +11,73 @@
 namespace lr {
 
 constexpr int MAXMAT = LR_MAXMAT;
+constexpr int TX = 32, TY = 8;  // tile of cells or nodes handled by one 256-thread block
+constexpr int NTHREADS = TX * TY;
 
-// Problem constants, passed by value to every kernel.
+// Problem constants (FP64 whatever the bulk precision).
 struct Grid {
   int nx, ny, nmat;
   int recon_order, kinematic;
-  double dx, dy, A;     // cell sizes and area
-  double Lx, Ly;        // domain extents x1-x0, y1-y0
+  double dx, dy, A;  // cell sizes and area
+  double Lx, Ly;     // domain extents x1-x0, y1-y0
   double cfl, a1, a2, k_eps, fixed_dt;
+  double neg_tol;  // a partial V, M, E below -neg_tol of the cell scale is an error
   double gamma[MAXMAT];
 };
 
-// Device-resident time-stepping control: the host never needs dt per step.
-struct Scalars {
-  double t;                  // time at the start of the current step
-  double dt;                 // time step of the current step
-  double t_end;              // end of the current run
-  unsigned long long dtmin;  // bits of the next CFL bound (positive double), atomicMin target
-  long long step;            // steps taken since lr_set_state
-  long long step_limit;      // the run stops when step reaches it
-  int last;                  // the current step lands on t_end
-  int done;                  // no step is pending: kernels return at once
-  int err;                   // error bits (ERR_*)
+// Device-side time control.  Step n of a problem reads slot[n & 1 ^ flip];
+// the remap kernel of step n prepares the other slot for step n+1 and the
+// dual kernel of step n accumulates the CFL bound of the new state into it,
+// so no control kernel and no host round trip is needed between steps.
+constexpr int NDT = 32;  // CFL-bound partial minima, spread to keep atomics uncontended
+struct Slot {
+  double t;                       // time at the start of the step
+  double t_end;                   // end of the current run
+  unsigned long long dtmin[NDT];  // bits of the CFL bound of the state at t (positive
+                                  // doubles): its min over the NDT entries
+  long long step;                 // index of the step
+  long long limit;                // the run stops when step reaches it
+  int done;                       // no step to take: the kernels return at once
+  int nmix;                       // mixed cells listed for this step
+};
+struct Ctl {
+  Slot slot[2];
+  int err;  // sticky error bits (ERR_*), cleared when a run starts
   int pad;
 };
+enum { ERR_NEG = 1, ERR_NAN = 2, ERR_DT = 4, ERR_VOLCF = 8, ERR_NODEMASS = 16, ERR_MIXCAP = 32 };
 
-enum { ERR_NEG = 1, ERR_NAN = 2, ERR_DT = 4, ERR_VOLCF = 8, ERR_NODEMASS = 16 };
+// Optional stage arrays, written only when non-null (stage-by-stage checks).
+template <typename R>
+struct Dbg {
+  R *Q, *S, *VL, *Ph;       // [C], [C], [C], [nmat][C]
+  R *volcf, *rhocf;         // [C], [nmat][C]
+  R *Wpx, *Wpy, *Wpc;       // per-material signed partial volumes of the regions
+};
+
+// Everything a kernel needs to step one problem (device pointers).
+template <typename R>
+struct Prob {
+  Grid g;
+  int flip;                       // slot parity of step 0
+  R *V[2], *M[2], *E[2];          // [nmat][C] conserved partial volume, mass, internal energy,
+                                  // double-buffered by slot: step in slot p reads [p], writes [p^1]
+  R *ux, *uy;                     // [N] nodal velocity
+  R *uhx, *uhy, *uLx, *uLy, *mp;  // [N] u^{n+1/2}, u^{lag}, nodal mass
+  R *eL;                          // [nmat][C] specific internal energy at the end of Lagrange
+  R *cs;                          // [C] sound speed of the updated state
+  R *MX, *MY, *MC;                // signed total mass flux of x-faces, y-faces, corners
+  int *mix_cell, *mix_slot;       // compacted mixed cells; cell -> list position or -1
+  int mix_cap;
+  double *mix_W;                  // [mix_cap][8][nmat] outflow partial volumes (FP64)
+  Ctl *ctl;
+  Dbg<R> dbg;
+};
+
+// block -> (problem, tile origin) of one launch over a batch
+struct BlockMap {
+  int prob, i0, j0, n;  // n: blocks of this problem (list kernels)
+};
 
 // ---------------------------------------------------------------- indexing
 __device__ __forceinline__ int refl_cell(int i, int n) {
@@ -48,21 +90,36 @@ __device__ __forceinline__ int refl_node(int I, int n) {
 // ---------------------------------------------------------------- limiter
 // Van Leer: for one-sided slopes of the same sign, the harmonic mean
 // 2 dm dp / (dm + dp); otherwise 0 (the limiter of §2.1.1 written out).
-__device__ __forceinline__ double van_leer(double dm, double dp) {
-  return (dm * dp > 0.0) ? 2.0 * dm * dp / (dm + dp) : 0.0;
+template <typename R>
+__device__ __forceinline__ R van_leer(R dm, R dp) {
+  return (dm * dp > R(0)) ? R(2) * dm * dp / (dm + dp) : R(0);
 }
 
 // ---------------------------------------------------------------- geometry
 // Quadrilateral area F of §1.2 from node positions relative to a common origin:
 // half the absolute cross product of the left and bottom edges plus half that
 // of the right and top edges.
-__device__ __forceinline__ double quad_area(double blx, double bly, double brx, double bry,
-                                            double tlx, double tly, double trx, double try_) {
-  const double lx = tlx - blx, ly = tly - bly;
-  const double bx = brx - blx, by = bry - bly;
-  const double rx = trx - brx, ry = try_ - bry;
-  const double tx = trx - tlx, ty = try_ - tly;
-  return 0.5 * fabs(lx * by - ly * bx) + 0.5 * fabs(rx * ty - ry * tx);
+template <typename R>
+__device__ __forceinline__ R quad_area(R blx, R bly, R brx, R bry, R tlx, R tly, R trx, R try_) {
+  const R lx = tlx - blx, ly = tly - bly;
+  const R bx = brx - blx, by = bry - bly;
+  const R rx = trx - brx, ry = try_ - bry;
+  const R tx = trx - tlx, ty = try_ - tly;
+  return R(0.5) * fabs(lx * by - ly * bx) + R(0.5) * fabs(rx * ty - ry * tx);
+}
+
+// F - A as the exact polynomial in the node displacements of a non-inverted
+// cell of sides (Dx, Dy): free of the cancellation of F - A in FP32.
+template <typename R>
+__device__ __forceinline__ R quad_area_change(R Dx, R Dy, R blx, R bly, R brx, R bry, R tlx, R tly,
+                                              R trx, R try_) {
+  // triangle BL-BR-TL: (Dx + brx - blx)(Dy + tly - bly) - (bry - bly)(tlx - blx) - Dx Dy
+  const R b1x = brx - blx, l1y = tly - bly, b1y = bry - bly, l1x = tlx - blx;
+  const R t1 = Dx * l1y + Dy * b1x + b1x * l1y - b1y * l1x;
+  // triangle TR-TL-BR: (Dy + try - bry)(Dx + trx - tlx) - (trx - brx)(try - tly) - Dx Dy
+  const R r2y = try_ - bry, t2x = trx - tlx, r2x = trx - brx, t2y = try_ - tly;
+  const R t2 = Dx * r2y + Dy * t2x + r2y * t2x - r2x * t2y;
+  return R(0.5) * (t1 + t2);
 }
 
 // DirectCF face flux volume (§2.3) of a face of length D whose end nodes are
@@ -71,25 +128,67 @@ __device__ __forceinline__ double quad_area(double blx, double bly, double brx, 
 // Eulerian face and the Lagrangian face line, cut at t- = max(0, da_t) and
 // t+ = D + min(0, db_t), is replaced by a rectangle of width w (the mean
 // offset of the line at t-, t+) and height h; the flux volume is w h.
+template <typename R>
 struct FaceGeo {
-  double w;   // signed width: > 0 flux along +n
-  double h;   // height (>= 0)
-  double t0;  // start of the rectangle along the face, from the lower node
+  R w;   // signed width: > 0 flux along +n
+  R h;   // height (>= 0)
+  R t0;  // start of the rectangle along the face, from the lower node
 };
-__device__ __forceinline__ FaceGeo face_geo(double da_n, double da_t, double db_n, double db_t,
-                                            double D) {
-  const double tlo = fmax(0.0, da_t);
-  const double thi = D + fmin(0.0, db_t);
-  double h = thi - tlo;
-  if (h < 0.0) h = 0.0;
-  const double slope = (db_n - da_n) / ((D + db_t) - da_t);
-  const double nlo = da_n + (tlo - da_t) * slope;
-  const double nhi = da_n + (thi - da_t) * slope;
-  FaceGeo g;
-  g.w = 0.5 * (nlo + nhi);
+template <typename R>
+__device__ __forceinline__ FaceGeo<R> face_geo(R da_n, R da_t, R db_n, R db_t, R D) {
+  const R tlo = fmax(R(0), da_t);
+  const R thi = D + fmin(R(0), db_t);
+  R h = thi - tlo;
+  if (h < R(0)) h = R(0);
+  const R slope = (db_n - da_n) / ((D + db_t) - da_t);
+  const R nlo = da_n + (tlo - da_t) * slope;
+  const R nhi = da_n + (thi - da_t) * slope;
+  FaceGeo<R> g;
+  g.w = R(0.5) * (nlo + nhi);
   g.h = h;
   g.t0 = tlo;
   return g;
+}
+
+// The eight flux regions touching a cell: W, E, S, N faces, then the corners
+// at its BL, BR, TL, TR nodes (§2.3, donor table of §3.3).  role: +1 the cell
+// is the donor, -1 the receiver, 0 not involved (corner of the other diagonal).
+template <typename R>
+struct CellRegions {
+  FaceGeo<R> fg[4];
+  R vol[8];
+  int role[8];
+};
+template <typename R>
+__device__ __forceinline__ void cell_regions(R Dx, R Dy, R blx, R bly, R brx, R bry, R tlx, R tly,
+                                             R trx, R try_, CellRegions<R> &r) {
+  r.fg[0] = face_geo(blx, bly, tlx, tly, Dy);  // W face: normal x, lower node BL
+  r.fg[1] = face_geo(brx, bry, trx, try_, Dy);  // E face
+  r.fg[2] = face_geo(bly, blx, bry, brx, Dx);  // S face: normal y, left node BL
+  r.fg[3] = face_geo(tly, tlx, try_, trx, Dx);  // N face
+#pragma unroll
+  for (int s = 0; s < 4; ++s) r.vol[s] = fabs(r.fg[s].w * r.fg[s].h);
+  r.role[0] = r.fg[0].w >= R(0) ? -1 : 1;
+  r.role[1] = r.fg[1].w >= R(0) ? 1 : -1;
+  r.role[2] = r.fg[2].w >= R(0) ? -1 : 1;
+  r.role[3] = r.fg[3].w >= R(0) ? 1 : -1;
+  const R cx[4] = {blx, brx, tlx, trx}, cy[4] = {bly, bry, tly, try_};
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    r.vol[4 + s] = fabs(cx[s] * cy[s]);
+    const bool sx = cx[s] >= R(0), sy = cy[s] >= R(0);
+    int role;
+    if (s == 0) role = (sx == sy) ? (sx ? -1 : 1) : 0;       // cell is NE of its BL node
+    else if (s == 1) role = (sx != sy) ? (sx ? 1 : -1) : 0;  // NW of its BR node
+    else if (s == 2) role = (sx != sy) ? (sx ? -1 : 1) : 0;  // SE of its TL node
+    else role = (sx == sy) ? (sx ? 1 : -1) : 0;              // SW of its TR node
+    r.role[4 + s] = role;
+  }
+}
+// corner kind at a node: main diagonal when both displacement signs agree
+template <typename R>
+__device__ __forceinline__ bool corner_main(R dx, R dy) {
+  return (dx >= R(0)) == (dy >= R(0));
 }
 
 // Area of the part of the rectangle [x0,x1] x [y0,y1] where nx x + ny y >= s,
@@ -100,8 +199,7 @@ __device__ __forceinline__ FaceGeo face_geo(double da_n, double da_t, double db_
 // opposite sides; s' < 0 uses the complement.
 __device__ __forceinline__ double corner_piece(double a, double b, double P, double Q, double t) {
   if (t <= 0.0) return 0.0;
-  const bool x_first = a * P <= b * Q;  // the line leaves the x-range first
-  if (x_first) {
+  if (a * P <= b * Q) {  // the line leaves the x-range first
     if (t <= 2.0 * a * P) return t * t / (2.0 * P * Q);
     return 2.0 * a * (t - a * P) / Q;
   }
@@ -116,12 +214,11 @@ __device__ __forceinline__ double rect_halfplane_area(double x0, double x1, doub
   const double P = fabs(nx), Q = fabs(ny);
   const double h = P * a + Q * b;
   const double full = 4.0 * a * b;
-  if (sc >= h) return 0.0;
-  if (sc <= -h) return (x1 - x0) * (y1 - y0);
-  double area;
-  if (sc >= 0.0) area = corner_piece(a, b, P, Q, h - sc);
-  else area = full - corner_piece(a, b, P, Q, h + sc);
   const double whole = (x1 - x0) * (y1 - y0);
+  if (sc >= h) return 0.0;
+  if (sc <= -h) return whole;
+  const double area = sc >= 0.0 ? corner_piece(a, b, P, Q, h - sc)
+                                : full - corner_piece(a, b, P, Q, h + sc);
   return area < 0.0 ? 0.0 : (area > whole ? whole : area);
 }
 
@@ -129,7 +226,7 @@ __device__ __forceinline__ double rect_halfplane_area(double x0, double x1, doub
 __device__ __forceinline__ double corner_depth(double a, double b, double P, double Q, double T) {
   if (T <= 0.0) return 0.0;
   if (a * P <= b * Q) {
-    const double Tt = 2.0 * a * a * P / Q;  // area where the triangle reaches x-extent
+    const double Tt = 2.0 * a * a * P / Q;  // area when the triangle spans the x-range
     if (T <= Tt) return sqrt(2.0 * P * Q * T);
     return T * Q / (2.0 * a) + a * P;
   }
@@ -152,6 +249,40 @@ __device__ __forceinline__ double interface_offset(double x0, double x1, double 
   if (T <= 0.5 * full) sc = h - corner_depth(a, b, P, Q, T);
   else sc = -(h - corner_depth(a, b, P, Q, full - T));
   return sc + (nx * (0.5 * (x0 + x1)) + ny * (0.5 * (y0 + y1)));
+}
+
+// time step of the step a slot describes (the CFL bound or the fixed step,
+// shortened to land on t_end)
+// the block's minimum of a per-thread bound (bits of a positive double) goes
+// to one of the NDT partial minima of the slot: one atomic per block
+__device__ __forceinline__ void block_min_to_slot(unsigned long long cand, Slot &s) {
+  __shared__ unsigned long long wmin[16];
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long w = __shfl_xor(cand, o, 64);
+    cand = w < cand ? w : cand;
+  }
+  const int wave = threadIdx.x / 64, nw = (blockDim.x + 63) / 64;
+  if (__lane_id() == 0) wmin[wave] = cand;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long m = wmin[0];
+    for (int k = 1; k < nw; ++k) m = wmin[k] < m ? wmin[k] : m;
+    if (m != ~0ull) atomicMin(&s.dtmin[blockIdx.x % NDT], m);
+  }
+}
+
+__device__ __forceinline__ double slot_dt(const Grid &g, const Slot &s, bool &last) {
+  unsigned long long b = s.dtmin[0];
+#pragma unroll
+  for (int k = 1; k < NDT; ++k) b = s.dtmin[k] < b ? s.dtmin[k] : b;
+  const double dtmin = __longlong_as_double((long long)b);
+  double dt = g.fixed_dt > 0.0 ? g.fixed_dt : g.cfl * dtmin;
+  last = false;
+  if (s.t_end - s.t <= dt) {
+    dt = s.t_end - s.t;
+    last = true;
+  }
+  return dt;
 }
 
 }  // namespace lr

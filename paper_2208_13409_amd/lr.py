@@ -37,7 +37,8 @@ class lr_opts(C.Structure):
     _fields_ = [("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double),
                 ("y1", C.c_double), ("cfl", C.c_double), ("a1", C.c_double),
                 ("a2", C.c_double), ("precision", C.c_int), ("recon_order", C.c_int),
-                ("kinematic", C.c_int), ("k_eps", C.c_double), ("fixed_dt", C.c_double)]
+                ("kinematic", C.c_int), ("k_eps", C.c_double), ("fixed_dt", C.c_double),
+                ("stages", C.c_int)]
 
 
 class LRError(RuntimeError):
@@ -110,7 +111,7 @@ class Solver:
 
     def __init__(self, nx, ny, gammas, domain=(0.0, 1.0, 0.0, 1.0), cfl=0.5, a1=0.5, a2=1.0,
                  recon_order=2, kinematic=False, k_eps=1e-10, fixed_dt=0.0, precision=LR_FP64,
-                 stream=None):
+                 stages=False, stream=None):
         self.lib = load()
         self.nx, self.ny, self.nmat = int(nx), int(ny), len(gammas)
         o = lr_default_opts()
@@ -118,6 +119,7 @@ class Solver:
         o.cfl, o.a1, o.a2 = float(cfl), float(a1), float(a2)
         o.recon_order, o.kinematic = int(recon_order), int(bool(kinematic))
         o.k_eps, o.fixed_dt, o.precision = float(k_eps), float(fixed_dt), int(precision)
+        o.stages = int(bool(stages))
         self.h = lr_create(nx, ny, gammas, o)
         if stream is not None:
             self.bind_stream(stream)
