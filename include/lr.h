@@ -29,7 +29,7 @@ enum {
   LR_ENEGATIVE = -4, /* negative partial volume / mass / energy, Vol^lagCF <= 0 */
   LR_ENAN = -5,      /* non-finite value in the inputs or the state             */
   LR_EDT = -6,       /* time step not positive or not finite                    */
-  LR_EAGAIN = -7,    /* reserved                                                */
+  LR_EAGAIN = -7,    /* a batch has no free slot or device memory for it now    */
   LR_ESTATE = -8     /* no state set, or volume fractions outside [0,1] / sum != 1 */
 };
 
@@ -98,6 +98,13 @@ int lr_bind_stream(lr_ctx *c, void *hip_stream);
 int lr_set_state(lr_ctx *c, double t, const double *k, const double *rho,
                  const double *e, const double *ux, const double *uy);
 
+/* As lr_set_state, from DEVICE arrays of the same shapes (dtype LR_F64:
+ * double, LR_F32: float), copied on the context's stream.  The checks of
+ * lr_set_state run on the device; synchronizes. */
+enum { LR_F64 = 0, LR_F32 = 1 };
+int lr_set_state_device(lr_ctx *c, double t, const void *k, const void *rho,
+                        const void *e, const void *ux, const void *uy, int dtype);
+
 /* One time step (Lagrangian phase, DirectCF remap with partial VOF fluxes,
  * momentum remap; paper §1.2, §2.3, §4.1, §4.4).  *dt_out (may be NULL)
  * receives the step used.  Synchronizes. */
@@ -138,6 +145,61 @@ int lr_profile(lr_ctx *c, int enable);
 int lr_profile_read(lr_ctx *c, double *ms, long *counts, int n);
 int lr_kernel_count(void);
 const char *lr_kernel_name(int i);
+
+/* ------------------------------------------------------------------ batch
+ * Many independent problems of different grid sizes stepped together: each
+ * kernel of a step is one launch over the tiles of every running problem of
+ * the batch (a grid no larger than the device holds at once, each block
+ * walking the tile list), optionally replayed from a HIP graph.  Problems
+ * are admitted while others run (continuous batching): a submitted problem
+ * takes a free slot and a range of the batch's device pool, starts with the
+ * next chunk of steps and leaves the launches when it finishes; its state
+ * stays resident until released.  Every problem of a batch has the batch's
+ * nmat and precision.  Each problem's arithmetic is that of a single context
+ * (its own time step, same kernels), so its result is the same alone and in
+ * any mix.  One host thread at a time per batch. */
+typedef struct {
+  int max_slots;        /* problems resident at once (>= 1)                      */
+  size_t pool_bytes;    /* device memory for problem state, allocated at create  */
+  int nmat;             /* materials of every problem                            */
+  int precision;        /* LR_FP64 or LR_FP32                                     */
+  int chunk_steps;      /* steps per lr_batch_step (even, >= 2); default 16      */
+  int use_graph;        /* 1: replay each chunk from a captured HIP graph        */
+  int persistent;       /* 1: grids limited to the blocks resident on the device */
+} lr_batch_opts;
+typedef struct lr_batch lr_batch;
+
+void lr_batch_default_opts(lr_batch_opts *o);
+int lr_batch_create(const lr_batch_opts *o, lr_batch **out);
+int lr_batch_bind_stream(lr_batch *b, void *hip_stream);
+/* device bytes of the pool one problem of this size takes */
+size_t lr_batch_footprint(int nx, int ny, int nmat, int precision);
+/* Admit a problem: grid nx x ny, eos[nmat], opts as for lr_create (its
+ * precision must be the batch's; stages must be 0; NULL = defaults), initial
+ * state at t = 0 as for lr_set_state (host arrays, copied), run until t_end
+ * or max_steps steps.  *req_id receives its id (>= 0).  LR_EAGAIN: no free
+ * slot or no pool range large enough now (retry after a release). */
+int lr_batch_submit(lr_batch *b, int nx, int ny, const lr_eos *eos, const lr_opts *opts,
+                    double t_end, long max_steps, const double *k, const double *rho,
+                    const double *e, const double *ux, const double *uy, long *req_id);
+/* Run one chunk of opts.chunk_steps steps of every running problem, then
+ * check which finished.  *n_running (may be NULL) receives the number still
+ * running.  Synchronizes. */
+int lr_batch_step(lr_batch *b, int *n_running);
+/* Ids of problems that finished (t_end or max_steps reached, or failed)
+ * since the last poll, at most cap of them; *n receives the count. */
+int lr_batch_poll(lr_batch *b, long *ids, int cap, int *n);
+/* rc: LR_OK, a failure code of the problem, or LR_EAGAIN while it runs;
+ * steps taken and time reached (any may be NULL). */
+int lr_batch_status(lr_batch *b, long id, int *rc, long *steps, double *t);
+/* as lr_get_fields / lr_totals for one resident problem */
+int lr_batch_get_fields(lr_batch *b, long id, unsigned field_mask, double *const *out);
+int lr_batch_totals(lr_batch *b, long id, double *out);
+/* free the problem's slot and pool range */
+int lr_batch_release(lr_batch *b, long id);
+int lr_batch_running(lr_batch *b);
+const char *lr_batch_last_error(const lr_batch *b);
+void lr_batch_destroy(lr_batch *b);
 
 /* Text of the last failure on this context; valid until the next call. */
 const char *lr_last_error(const lr_ctx *c);

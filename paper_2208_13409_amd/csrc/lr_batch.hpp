@@ -1,0 +1,506 @@
+// lr_batch.hpp — batch part of the C-ABI declared in include/lr.h (part of
+// the lr_kernels.hip translation unit): many problems of different sizes in
+// one device pool, stepped together by shared launches over the tiles of all
+// running problems, admitted and retired between chunks of steps
+// (continuous batching).
+#pragma once
+
+#include <deque>
+#include <map>
+#include <unordered_map>
+
+namespace {
+
+// First-fit ranges of one device pool; freed ranges merge with their
+// neighbours.  Offsets and sizes are multiples of 256 bytes.
+class PoolRanges {
+ public:
+  void init(size_t n) {
+    free_.clear();
+    if (n) free_[0] = n;
+  }
+  bool take(size_t n, size_t *off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < n) continue;
+      *off = it->first;
+      const size_t rest = it->second - n, o = it->first;
+      free_.erase(it);
+      if (rest) free_[o + n] = rest;
+      return true;
+    }
+    return false;
+  }
+  void give(size_t off, size_t n) {
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t largest() const {
+    size_t m = 0;
+    for (const auto &f : free_) m = std::max(m, f.second);
+    return m;
+  }
+
+ private:
+  std::map<size_t, size_t> free_;  // offset -> length
+};
+
+struct BatchReq {
+  long id = -1;
+  bool used = false, running = false;
+  int rc = LR_OK;
+  size_t off = 0, bytes = 0;
+  Grid g{};
+  Prob<double> pd{};
+  Prob<float> pf{};
+};
+
+}  // namespace
+
+struct lr_batch {
+  lr_batch_opts o{};
+  hipStream_t own = nullptr, stream = nullptr;
+  char *pool = nullptr;
+  PoolRanges ranges;
+  void *dprobs = nullptr;  // device Prob<R>[max_slots]
+  size_t prob_size = 0;    // sizeof(Prob<R>)
+  Ctl *ctl = nullptr;   // device [max_slots]
+  Ctl *hctl = nullptr;  // pinned mirror, read after every chunk
+  BlockMap *node_map = nullptr, *cell_map = nullptr;
+  size_t node_cap = 0, cell_cap = 0;
+  int node_blocks = 0, cell_blocks = 0;
+  bool maps_dirty = true;
+  StepFn step = nullptr;
+  std::vector<BatchReq> slots;
+  std::unordered_map<long, int> where;  // request id -> slot
+  std::deque<long> finished;
+  long next_id = 0;
+  // input staging: pinned host and device copies of one request's FP64
+  // arrays, reused once the previous request's set-up kernels ran
+  char *hstage = nullptr;
+  double *dstage = nullptr;
+  size_t stage_bytes = 0;
+  hipEvent_t stage_ev = nullptr;
+  double *scratch = nullptr;  // outputs
+  size_t scratch_n = 0;
+  hipGraphExec_t gexec = nullptr;
+  bool graph_ok = false;
+  std::string err;
+};
+
+namespace {
+
+int bset(lr_batch *b, int code, const std::string &msg) {
+  if (b) b->err = msg;
+  return code;
+}
+#define HIP_B(b, call)                                                                \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return bset((b), LR_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+bool bfp32(const lr_batch *b) { return b->o.precision == LR_FP32; }
+
+size_t prob_bytes(const Grid &g, int precision) {
+  if (precision == LR_FP32) {
+    Prob<float> P;
+    return carve_prob(P, nullptr, g, false, nullptr);
+  }
+  Prob<double> P;
+  return carve_prob(P, nullptr, g, false, nullptr);
+}
+
+int grow_stage(lr_batch *b, size_t bytes) {
+  if (bytes <= b->stage_bytes) return LR_OK;
+  HIP_B(b, hipStreamSynchronize(b->stream));
+  const size_t n = std::max(bytes, b->stage_bytes * 2);
+  if (b->hstage) (void)hipHostFree(b->hstage);
+  if (b->dstage) (void)hipFree(b->dstage);
+  b->hstage = nullptr;
+  b->dstage = nullptr;
+  b->stage_bytes = 0;
+  if (hipHostMalloc((void **)&b->hstage, n, hipHostMallocDefault) != hipSuccess ||
+      hipMalloc((void **)&b->dstage, n) != hipSuccess)
+    return bset(b, LR_ENOMEM, "input staging");
+  b->stage_bytes = n;
+  return LR_OK;
+}
+
+int grow_scratch(lr_batch *b, size_t n) {
+  if (n <= b->scratch_n) return LR_OK;
+  HIP_B(b, hipStreamSynchronize(b->stream));
+  if (b->scratch) (void)hipFree(b->scratch);
+  b->scratch = nullptr;
+  b->scratch_n = 0;
+  if (hipMalloc((void **)&b->scratch, n * sizeof(double)) != hipSuccess)
+    return bset(b, LR_ENOMEM, "output scratch");
+  b->scratch_n = n;
+  return LR_OK;
+}
+
+// block maps over the tiles of every running problem
+int rebuild_maps(lr_batch *b) {
+  std::vector<BlockMap> nm, cm;
+  for (size_t s = 0; s < b->slots.size(); ++s)
+    if (b->slots[s].running) tile_maps(b->slots[s].g, (int)s, nm, cm);
+  if (nm.size() > b->node_cap || cm.size() > b->cell_cap) {
+    HIP_B(b, hipStreamSynchronize(b->stream));
+    if (b->node_map) (void)hipFree(b->node_map);
+    if (b->cell_map) (void)hipFree(b->cell_map);
+    b->node_map = b->cell_map = nullptr;
+    b->node_cap = std::max(nm.size(), 2 * b->node_cap);
+    b->cell_cap = std::max(cm.size(), 2 * b->cell_cap);
+    if (hipMalloc(&b->node_map, std::max<size_t>(b->node_cap, 1) * sizeof(BlockMap)) != hipSuccess ||
+        hipMalloc(&b->cell_map, std::max<size_t>(b->cell_cap, 1) * sizeof(BlockMap)) != hipSuccess)
+      return bset(b, LR_ENOMEM, "block maps");
+  }
+  // the maps are read by launches already queued: copy after they ran
+  HIP_B(b, hipStreamSynchronize(b->stream));
+  if (!nm.empty())
+    HIP_B(b, hipMemcpy(b->node_map, nm.data(), nm.size() * sizeof(BlockMap), hipMemcpyHostToDevice));
+  if (!cm.empty())
+    HIP_B(b, hipMemcpy(b->cell_map, cm.data(), cm.size() * sizeof(BlockMap), hipMemcpyHostToDevice));
+  b->node_blocks = (int)nm.size();
+  b->cell_blocks = (int)cm.size();
+  b->maps_dirty = false;
+  b->graph_ok = false;
+  return LR_OK;
+}
+
+template <typename R>
+int batch_admit(lr_batch *b, int s, BatchReq &q, Prob<R> &P, const double *const in[5], double t_end,
+                long long limit) {
+  const Grid &g = q.g;
+  const size_t C = (size_t)g.nx * g.ny, N = (size_t)(g.nx + 1) * (g.ny + 1), nm = g.nmat;
+  carve_prob(P, b->pool + q.off, g, false, b->ctl + s);
+  int rc = clear_prob(P, b->stream, b->err);
+  if (rc) return rc;
+  const size_t nd = 3 * nm * C + 2 * N;
+  const size_t bytes = nd * sizeof(double) + sizeof(Ctl) + sizeof(Prob<R>) + 512;
+  rc = grow_stage(b, bytes);
+  if (rc) return rc;
+  HIP_B(b, hipEventSynchronize(b->stage_ev));  // the previous admission consumed the staging
+  double *hk = reinterpret_cast<double *>(b->hstage);
+  const size_t cnt[5] = {nm * C, nm * C, nm * C, N, N};
+  size_t off = 0;
+  for (int a = 0; a < 5; ++a) {
+    std::memcpy(hk + off, in[a], cnt[a] * sizeof(double));
+    off += cnt[a];
+  }
+  char *tail = b->hstage + ((nd * sizeof(double) + 255) & ~size_t(255));
+  Ctl *hc = reinterpret_cast<Ctl *>(tail);
+  *hc = initial_ctl(0.0, t_end, limit);
+  Prob<R> *hp = reinterpret_cast<Prob<R> *>(tail + ((sizeof(Ctl) + 255) & ~size_t(255)));
+  *hp = P;
+  b->hctl[s] = *hc;
+  HIP_B(b, hipMemcpyAsync(b->dstage, hk, nd * sizeof(double), hipMemcpyHostToDevice, b->stream));
+  HIP_B(b, hipMemcpyAsync(b->ctl + s, hc, sizeof(Ctl), hipMemcpyHostToDevice, b->stream));
+  HIP_B(b, hipMemcpyAsync(static_cast<char *>(b->dprobs) + s * b->prob_size, hp, sizeof(Prob<R>),
+                          hipMemcpyHostToDevice, b->stream));
+  launch_init<R>(P, b->dstage, b->stream);
+  HIP_B(b, hipGetLastError());
+  HIP_B(b, hipEventRecord(b->stage_ev, b->stream));
+  return LR_OK;
+}
+
+// run one chunk of steps of every running problem
+int batch_chunk(lr_batch *b) {
+  const Launch L{b->dprobs, b->node_map, b->cell_map, b->node_blocks, b->cell_blocks,
+                 b->o.persistent != 0};
+  const int n = b->o.chunk_steps;
+  if (!b->o.use_graph) {
+    for (int st = 0; st < n; ++st) b->step(L, st & 1, b->stream, nullptr);
+    HIP_B(b, hipGetLastError());
+    return LR_OK;
+  }
+  if (!b->graph_ok) {
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    HIP_B(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    for (int st = 0; st < n; ++st) b->step(L, st & 1, b->stream, nullptr);
+    const hipError_t launch_err = hipGetLastError();
+    const hipError_t e = hipStreamEndCapture(b->stream, &graph);
+    if (launch_err != hipSuccess || e != hipSuccess || !graph) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return bset(b, LR_EDEVICE, "graph capture failed");
+    }
+    const hipError_t ei = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return bset(b, LR_EDEVICE, "graph instantiation failed");
+    b->graph_ok = true;
+  }
+  HIP_B(b, hipGraphLaunch(b->gexec, b->stream));
+  return LR_OK;
+}
+
+int find_req(lr_batch *b, long id, BatchReq **q) {
+  auto it = b->where.find(id);
+  if (it == b->where.end()) return bset(b, LR_EINVAL, "unknown request id");
+  *q = &b->slots[it->second];
+  return LR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lr_batch_default_opts(lr_batch_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->max_slots = 256;
+  o->pool_bytes = size_t(4) << 30;
+  o->nmat = 2;
+  o->precision = LR_FP32;
+  o->chunk_steps = kChunk;
+  o->use_graph = 1;
+  o->persistent = 1;
+}
+
+void lr_batch_destroy(lr_batch *b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->stage_ev) (void)hipEventDestroy(b->stage_ev);
+  for (void *p : {(void *)b->pool, b->dprobs, (void *)b->ctl, (void *)b->node_map,
+                  (void *)b->cell_map, (void *)b->dstage, (void *)b->scratch})
+    if (p) (void)hipFree(p);
+  if (b->hctl) (void)hipHostFree(b->hctl);
+  if (b->hstage) (void)hipHostFree(b->hstage);
+  if (b->own) (void)hipStreamDestroy(b->own);
+  delete b;
+}
+
+int lr_batch_create(const lr_batch_opts *opts, lr_batch **out) {
+  if (!out) return LR_EINVAL;
+  *out = nullptr;
+  lr_batch_opts o;
+  if (opts) o = *opts;
+  else lr_batch_default_opts(&o);
+  if (o.max_slots < 1 || o.max_slots > (1 << 20) || o.pool_bytes < 256 || o.nmat < 1 ||
+      o.nmat > LR_MAXMAT || (o.precision != LR_FP64 && o.precision != LR_FP32) ||
+      o.chunk_steps < 2 || (o.chunk_steps & 1))
+    return LR_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return LR_EDEVICE;
+  lr_batch *b = new (std::nothrow) lr_batch();
+  if (!b) return LR_ENOMEM;
+  b->o = o;
+  b->o.pool_bytes &= ~size_t(255);
+  // the kernels index the descriptors as an array of Prob<R>
+  b->prob_size = o.precision == LR_FP32 ? sizeof(Prob<float>) : sizeof(Prob<double>);
+  b->slots.resize(o.max_slots);
+  int rc = LR_OK;
+  if (hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->stage_ev, hipEventDisableTiming) != hipSuccess)
+    rc = LR_EDEVICE;
+  b->stream = b->own;
+  if (rc == LR_OK && (hipMalloc((void **)&b->pool, b->o.pool_bytes) != hipSuccess ||
+                      hipMalloc(&b->dprobs, b->prob_size * o.max_slots) != hipSuccess ||
+                      hipMalloc((void **)&b->ctl, sizeof(Ctl) * o.max_slots) != hipSuccess ||
+                      hipHostMalloc((void **)&b->hctl, sizeof(Ctl) * o.max_slots, hipHostMallocDefault) !=
+                          hipSuccess))
+    rc = LR_ENOMEM;
+  if (rc == LR_OK) {
+    std::memset(b->hctl, 0, sizeof(Ctl) * o.max_slots);
+    b->ranges.init(b->o.pool_bytes);
+    b->step = bfp32(b) ? step_fn<float>(o.nmat) : step_fn<double>(o.nmat);
+    if (bfp32(b)) warm_resident<float>(o.nmat);
+    else warm_resident<double>(o.nmat);
+    if (hipEventRecord(b->stage_ev, b->stream) != hipSuccess) rc = LR_EDEVICE;
+  }
+  if (rc != LR_OK) {
+    lr_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return LR_OK;
+}
+
+int lr_batch_bind_stream(lr_batch *b, void *hip_stream) {
+  if (!b) return LR_EINVAL;
+  HIP_B(b, hipStreamSynchronize(b->stream));
+  b->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : b->own;
+  HIP_B(b, hipEventRecord(b->stage_ev, b->stream));
+  return LR_OK;
+}
+
+size_t lr_batch_footprint(int nx, int ny, int nmat, int precision) {
+  if (nx < 2 || ny < 2 || nmat < 1 || nmat > LR_MAXMAT) return 0;
+  Grid g{};
+  g.nx = nx;
+  g.ny = ny;
+  g.nmat = nmat;
+  return prob_bytes(g, precision);
+}
+
+int lr_batch_submit(lr_batch *b, int nx, int ny, const lr_eos *eos, const lr_opts *opts, double t_end,
+                    long max_steps, const double *k, const double *rho, const double *e,
+                    const double *ux, const double *uy, long *req_id) {
+  if (!b || !req_id || !k || !rho || !e || !ux || !uy) return LR_EINVAL;
+  *req_id = -1;
+  lr_opts o;
+  if (opts) o = *opts;
+  else {
+    lr_default_opts(&o);
+    o.precision = b->o.precision;
+  }
+  if (o.precision != b->o.precision || o.stages) return bset(b, LR_EINVAL, "precision differs from the batch's, or stages set");
+  if (!(t_end >= 0.0) || max_steps < 0) return bset(b, LR_EINVAL, "t_end < 0 or max_steps < 0");
+  Grid g;
+  if (make_grid(nx, ny, b->o.nmat, eos, nullptr, o, g) != LR_OK) return bset(b, LR_EINVAL, "bad grid, eos or options");
+  const char *msg = "";
+  const int chk = check_state_host(g, k, rho, e, ux, uy, &msg);
+  if (chk) return bset(b, chk, msg);
+  int s = -1;
+  for (int i = 0; i < (int)b->slots.size(); ++i)
+    if (!b->slots[i].used) {
+      s = i;
+      break;
+    }
+  if (s < 0) return bset(b, LR_EAGAIN, "no free slot");
+  const size_t bytes = prob_bytes(g, b->o.precision);
+  size_t off = 0;
+  if (!b->ranges.take(bytes, &off)) return bset(b, LR_EAGAIN, "no pool range large enough");
+  BatchReq &q = b->slots[s];
+  q = BatchReq{};
+  q.g = g;
+  q.off = off;
+  q.bytes = bytes;
+  const double *in[5] = {k, rho, e, ux, uy};
+  const int rc = bfp32(b) ? batch_admit<float>(b, s, q, q.pf, in, t_end, max_steps)
+                          : batch_admit<double>(b, s, q, q.pd, in, t_end, max_steps);
+  if (rc != LR_OK) {
+    b->ranges.give(off, bytes);
+    q = BatchReq{};
+    return rc;
+  }
+  q.used = true;
+  q.id = b->next_id++;
+  b->where[q.id] = s;
+  const Slot &s0 = b->hctl[s].slot[0];
+  if (s0.done) {
+    b->finished.push_back(q.id);
+  } else {
+    q.running = true;
+    b->maps_dirty = true;
+  }
+  *req_id = q.id;
+  return LR_OK;
+}
+
+int lr_batch_step(lr_batch *b, int *n_running) {
+  if (!b) return LR_EINVAL;
+  int rc = LR_OK;
+  if (b->maps_dirty) rc = rebuild_maps(b);
+  if (rc) return rc;
+  int running = 0;
+  if (b->node_blocks > 0) {
+    rc = batch_chunk(b);
+    if (rc) return rc;
+    HIP_B(b, hipMemcpyAsync(b->hctl, b->ctl, sizeof(Ctl) * b->slots.size(), hipMemcpyDeviceToHost,
+                            b->stream));
+    HIP_B(b, hipStreamSynchronize(b->stream));
+    for (size_t s = 0; s < b->slots.size(); ++s) {
+      BatchReq &q = b->slots[s];
+      if (!q.running) continue;
+      const Ctl &k = b->hctl[s];
+      if (k.slot[cur_slot(k)].done || k.err) {
+        const char *msg = "";
+        q.rc = err_code(k.err, &msg);
+        q.running = false;
+        b->finished.push_back(q.id);
+        b->maps_dirty = true;
+      } else {
+        ++running;
+      }
+    }
+  }
+  if (n_running) *n_running = running;
+  return LR_OK;
+}
+
+int lr_batch_running(lr_batch *b) {
+  if (!b) return 0;
+  int n = 0;
+  for (const auto &q : b->slots) n += q.running;
+  return n;
+}
+
+int lr_batch_poll(lr_batch *b, long *ids, int cap, int *n) {
+  if (!b || !n || cap < 0 || (cap > 0 && !ids)) return LR_EINVAL;
+  int m = 0;
+  while (m < cap && !b->finished.empty()) {
+    ids[m++] = b->finished.front();
+    b->finished.pop_front();
+  }
+  *n = m;
+  return LR_OK;
+}
+
+int lr_batch_status(lr_batch *b, long id, int *rc, long *steps, double *t) {
+  if (!b) return LR_EINVAL;
+  BatchReq *q = nullptr;
+  const int r = find_req(b, id, &q);
+  if (r) return r;
+  const int s = b->where[id];
+  const Ctl &k = b->hctl[s];
+  const Slot &cur = k.slot[cur_slot(k)];
+  if (rc) *rc = q->running ? LR_EAGAIN : q->rc;
+  if (steps) *steps = (long)cur.step;
+  if (t) *t = cur.t;
+  return LR_OK;
+}
+
+int lr_batch_get_fields(lr_batch *b, long id, unsigned mask, double *const *out) {
+  if (!b || !out) return LR_EINVAL;
+  BatchReq *q = nullptr;
+  int rc = find_req(b, id, &q);
+  if (rc) return rc;
+  const Grid &g = q->g;
+  rc = grow_scratch(b, std::max((size_t)g.nmat * g.nx * g.ny, (size_t)(g.nx + 1) * (g.ny + 1)));
+  if (rc) return rc;
+  const int buf = cur_slot(b->hctl[b->where[id]]);
+  return bfp32(b) ? fields_out<float>(q->pf, buf, mask, out, b->scratch, b->stream, b->err)
+                  : fields_out<double>(q->pd, buf, mask, out, b->scratch, b->stream, b->err);
+}
+
+int lr_batch_totals(lr_batch *b, long id, double *out) {
+  if (!b || !out) return LR_EINVAL;
+  BatchReq *q = nullptr;
+  const int rc = find_req(b, id, &q);
+  if (rc) return rc;
+  const int buf = cur_slot(b->hctl[b->where[id]]);
+  return bfp32(b) ? totals_out<float>(q->pf, buf, out, b->stream, b->err)
+                  : totals_out<double>(q->pd, buf, out, b->stream, b->err);
+}
+
+int lr_batch_release(lr_batch *b, long id) {
+  if (!b) return LR_EINVAL;
+  BatchReq *q = nullptr;
+  const int rc = find_req(b, id, &q);
+  if (rc) return rc;
+  // launches still queued may read the problem: free its range after them
+  HIP_B(b, hipStreamSynchronize(b->stream));
+  if (q->running) b->maps_dirty = true;
+  b->ranges.give(q->off, q->bytes);
+  b->where.erase(id);
+  *q = BatchReq{};
+  return LR_OK;
+}
+
+const char *lr_batch_last_error(const lr_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+}  // extern "C"

@@ -79,6 +79,20 @@ struct BlockMap {
   int prob, i0, j0, n;  // n: blocks of this problem (list kernels)
 };
 
+// ---------------------------------------------------------------- memory
+// Loads and stores through the arrays of a problem descriptor.  The pointers
+// are read from device memory, so the compiler cannot tell global memory from
+// LDS and would issue flat instructions, whose completion counter is shared
+// with LDS operations; the cast makes them global-memory instructions.
+template <typename T>
+__device__ __forceinline__ T ldg(const T *p) {
+  return *(const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ void stg(T *p, T v) {
+  *(__attribute__((address_space(1))) T *)p = v;
+}
+
 // ---------------------------------------------------------------- indexing
 __device__ __forceinline__ int refl_cell(int i, int n) {
   return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i);
@@ -271,15 +285,21 @@ __device__ __forceinline__ void block_min_to_slot(unsigned long long cand, Slot 
   }
 }
 
+// (called by all 64 lanes of every wave: lane k reads partial k % NDT and
+// the wave combines them with shuffles)
 __device__ __forceinline__ double slot_dt(const Grid &g, const Slot &s, bool &last) {
-  unsigned long long b = s.dtmin[0];
+  unsigned long long b = ldg(&s.dtmin[__lane_id() % NDT]);
 #pragma unroll
-  for (int k = 1; k < NDT; ++k) b = s.dtmin[k] < b ? s.dtmin[k] : b;
+  for (int o = NDT / 2; o > 0; o >>= 1) {
+    const unsigned long long w = __shfl_xor(b, o, 64);
+    b = w < b ? w : b;
+  }
   const double dtmin = __longlong_as_double((long long)b);
+  const double t = ldg(&s.t), t_end = ldg(&s.t_end);
   double dt = g.fixed_dt > 0.0 ? g.fixed_dt : g.cfl * dtmin;
   last = false;
-  if (s.t_end - s.t <= dt) {
-    dt = s.t_end - s.t;
+  if (t_end - t <= dt) {
+    dt = t_end - t;
     last = true;
   }
   return dt;

@@ -1,8 +1,261 @@
-// lr_host.hpp — host side of the C-ABI declared in include/lr.h (part of the
-// lr_kernels.hip translation unit): device allocation of one problem in the
-// chosen precision, block maps, device-side time control, outputs.
+// lr_host.hpp — host side of the single-problem C-ABI declared in
+// include/lr.h (part of the lr_kernels.hip translation unit), and the helpers
+// it shares with the batch: layout of one problem's device arrays, grid and
+// state checks, block maps, device-side time control, outputs.
 #pragma once
 
+namespace {
+
+constexpr int kChunk = 16;  // steps launched between completion checks
+
+#define HIP_TRY(err, call)                                                      \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess) {                                                     \
+      (err) = std::string(#call ": ") + hipGetErrorString(e_);                  \
+      return LR_EDEVICE;                                                        \
+    }                                                                           \
+  } while (0)
+
+// ------------------------------------------------------------ problem layout
+// All device arrays of one problem in one allocation, each 256-byte aligned.
+// With base == nullptr only the size is computed.
+struct Carver {
+  char *base;
+  size_t off = 0;
+  template <typename T>
+  T *take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += (n ? n : 1) * sizeof(T);
+    return p;
+  }
+};
+
+template <typename R>
+size_t carve_prob(Prob<R> &P, char *base, const Grid &g, bool stages, Ctl *ctl) {
+  const size_t C = (size_t)g.nx * g.ny, N = (size_t)(g.nx + 1) * (g.ny + 1), m = g.nmat;
+  const size_t nX = (size_t)(g.nx + 1) * g.ny, nY = (size_t)g.nx * (g.ny + 1);
+  Carver cv{base};
+  P = Prob<R>{};
+  P.g = g;
+  P.flip = 0;
+  for (int b = 0; b < 2; ++b) {
+    P.V[b] = cv.take<R>(m * C);
+    P.M[b] = cv.take<R>(m * C);
+    P.E[b] = cv.take<R>(m * C);
+  }
+  P.ux = cv.take<R>(N); P.uy = cv.take<R>(N);
+  P.uhx = cv.take<R>(N); P.uhy = cv.take<R>(N);
+  P.uLx = cv.take<R>(N); P.uLy = cv.take<R>(N); P.mp = cv.take<R>(N);
+  P.eL = cv.take<R>(m * C);
+  P.cs = cv.take<R>(C);
+  P.MX = cv.take<R>(nX); P.MY = cv.take<R>(nY); P.MC = cv.take<R>(N);
+  P.mix_cell = cv.take<int>(C); P.mix_slot = cv.take<int>(C);
+  P.mix_cap = (int)C;
+  P.mix_W = cv.take<double>(C * 8 * m);
+  if (stages) {
+    P.dbg.Q = cv.take<R>(C); P.dbg.S = cv.take<R>(C); P.dbg.VL = cv.take<R>(C);
+    P.dbg.Ph = cv.take<R>(m * C); P.dbg.volcf = cv.take<R>(C);
+    P.dbg.rhocf = cv.take<R>(m * C);
+    P.dbg.Wpx = cv.take<R>(m * nX); P.dbg.Wpy = cv.take<R>(m * nY);
+    P.dbg.Wpc = cv.take<R>(m * N);
+  }
+  P.ctl = ctl;
+  return (cv.off + 255) & ~size_t(255);
+}
+
+// wall regions are never written: keep them zero (outside any graph)
+template <typename R>
+int clear_prob(const Prob<R> &P, hipStream_t s, std::string &err) {
+  const Grid &g = P.g;
+  const size_t N = (size_t)(g.nx + 1) * (g.ny + 1), m = g.nmat;
+  const size_t nX = (size_t)(g.nx + 1) * g.ny, nY = (size_t)g.nx * (g.ny + 1);
+  HIP_TRY(err, hipMemsetAsync(P.MX, 0, nX * sizeof(R), s));
+  HIP_TRY(err, hipMemsetAsync(P.MY, 0, nY * sizeof(R), s));
+  HIP_TRY(err, hipMemsetAsync(P.MC, 0, N * sizeof(R), s));
+  if (P.dbg.Wpx) {
+    HIP_TRY(err, hipMemsetAsync(P.dbg.Wpx, 0, m * nX * sizeof(R), s));
+    HIP_TRY(err, hipMemsetAsync(P.dbg.Wpy, 0, m * nY * sizeof(R), s));
+    HIP_TRY(err, hipMemsetAsync(P.dbg.Wpc, 0, m * N * sizeof(R), s));
+  }
+  return LR_OK;
+}
+
+// ------------------------------------------------------------ checks
+int make_grid(int nx, int ny, int nmat, const lr_eos *eos, const int bc[4], const lr_opts &o,
+              Grid &g) {
+  if (nx < 2 || ny < 2 || nmat < 1 || nmat > LR_MAXMAT || !eos) return LR_EINVAL;
+  if ((long long)nx * ny > (1ll << 28)) return LR_EINVAL;
+  if (bc)
+    for (int s = 0; s < 4; ++s)
+      if (bc[s] != LR_BC_REFLECT) return LR_EINVAL;
+  for (int a = 0; a < nmat; ++a)
+    if (!(eos[a].gamma > 1.0) || eos[a].pinf != 0.0) return LR_EINVAL;
+  if (!(o.x1 > o.x0) || !(o.y1 > o.y0) || !(o.cfl > 0) || (o.recon_order != 1 && o.recon_order != 2) ||
+      !(o.k_eps >= 0) || o.fixed_dt < 0 || (o.precision != LR_FP64 && o.precision != LR_FP32))
+    return LR_EINVAL;
+  g = Grid{};
+  g.nx = nx; g.ny = ny; g.nmat = nmat;
+  g.recon_order = o.recon_order; g.kinematic = o.kinematic ? 1 : 0;
+  g.dx = (o.x1 - o.x0) / nx; g.dy = (o.y1 - o.y0) / ny; g.A = g.dx * g.dy;
+  g.Lx = o.x1 - o.x0; g.Ly = o.y1 - o.y0;
+  g.cfl = o.cfl; g.a1 = o.a1; g.a2 = o.a2; g.k_eps = o.k_eps; g.fixed_dt = o.fixed_dt;
+  // FP32 rounding leaves residues of about 1e-7 of a cell behind a material
+  // that moved out: presence and negativity thresholds above that level
+  g.neg_tol = o.precision == LR_FP32 ? 1e-5 : 1e-10;
+  if (o.precision == LR_FP32 && g.k_eps < 1e-6) g.k_eps = 1e-6;
+  for (int a = 0; a < nmat; ++a) g.gamma[a] = eos[a].gamma;
+  return LR_OK;
+}
+
+// the host checks of an initial state; LR_OK or the code, with *msg
+int check_state_host(const Grid &g, const double *k, const double *rho, const double *e,
+                     const double *ux, const double *uy, const char **msg) {
+  const int nm = g.nmat;
+  const size_t C = (size_t)g.nx * g.ny, N = (size_t)(g.nx + 1) * (g.ny + 1);
+  for (size_t q = 0; q < C; ++q) {
+    double ks = 0.0;
+    for (int a = 0; a < nm; ++a) {
+      const size_t h = a * C + q;
+      if (!std::isfinite(k[h]) || !std::isfinite(rho[h]) || !std::isfinite(e[h])) {
+        *msg = "non-finite input";
+        return LR_ENAN;
+      }
+      if (k[h] < 0.0 || k[h] > 1.0) {
+        *msg = "volume fraction outside [0,1]";
+        return LR_ESTATE;
+      }
+      if (k[h] > 0.0 && (!(rho[h] > 0.0) || e[h] < 0.0)) {
+        *msg = "rho <= 0 or e < 0 where k > 0";
+        return LR_ESTATE;
+      }
+      ks += k[h];
+    }
+    if (std::fabs(ks - 1.0) > 1e-12) {
+      *msg = "volume fractions do not sum to 1";
+      return LR_ESTATE;
+    }
+  }
+  for (size_t p = 0; p < N; ++p)
+    if (!std::isfinite(ux[p]) || !std::isfinite(uy[p])) {
+      *msg = "non-finite velocity";
+      return LR_ENAN;
+    }
+  return LR_OK;
+}
+
+// control record of a fresh state at time t: slot 0 is current and runs
+// until t_end or `limit` steps; slot 1 is stopped until the first step
+Ctl initial_ctl(double t, double t_end, long long limit) {
+  Ctl h{};
+  h.slot[0].t = t;
+  h.slot[0].t_end = t_end;
+  const double inf = INFINITY;
+  for (int kk = 0; kk < NDT; ++kk) std::memcpy(&h.slot[0].dtmin[kk], &inf, sizeof inf);
+  h.slot[0].step = 0;
+  h.slot[0].limit = limit;
+  h.slot[0].done = (limit <= 0 || !(t < t_end)) ? 1 : 0;
+  h.slot[1] = h.slot[0];
+  h.slot[1].step = -1;
+  h.slot[1].done = 1;
+  return h;
+}
+
+int cur_slot(const Ctl &k) { return k.slot[1].step > k.slot[0].step ? 1 : 0; }
+
+// the time step a slot describes, with the device's arithmetic
+double host_slot_dt(const Grid &g, const Slot &s) {
+  unsigned long long b = s.dtmin[0];
+  for (int k = 1; k < NDT; ++k) b = s.dtmin[k] < b ? s.dtmin[k] : b;
+  double dtmin;
+  std::memcpy(&dtmin, &b, sizeof dtmin);
+  double dt = g.fixed_dt > 0.0 ? g.fixed_dt : g.cfl * dtmin;
+  if (s.t_end - s.t <= dt) dt = s.t_end - s.t;
+  return dt;
+}
+
+int err_code(int bits, const char **msg) {
+  if (bits & ERR_NAN) { *msg = "non-finite value in the state"; return LR_ENAN; }
+  if (bits & ERR_DT) { *msg = "time step not positive or not finite"; return LR_EDT; }
+  if (bits & ERR_VOLCF) { *msg = "flux-consistent Lagrangian volume <= 0"; return LR_ENEGATIVE; }
+  if (bits & ERR_NODEMASS) { *msg = "nodal mass <= 0 after remap"; return LR_ENEGATIVE; }
+  if (bits & ERR_NEG) { *msg = "negative partial volume, mass or energy"; return LR_ENEGATIVE; }
+  if (bits & ERR_MIXCAP) { *msg = "mixed-cell list capacity exceeded"; return LR_ENOMEM; }
+  return LR_OK;
+}
+
+// node tiles cover nodes [0, nx] x [0, ny], cell tiles cells [0, nx) x [0, ny)
+void tile_maps(const Grid &g, int prob, std::vector<BlockMap> &nm, std::vector<BlockMap> &cm) {
+  for (int j = 0; j <= g.ny; j += TY)
+    for (int i = 0; i <= g.nx; i += TX) nm.push_back({prob, i, j, 0});
+  for (int j = 0; j < g.ny; j += TY)
+    for (int i = 0; i < g.nx; i += TX) cm.push_back({prob, i, j, 0});
+}
+
+// initial state from the FP64 staging array [k | rho | e | ux | uy]:
+// conserved totals in buffer 0, sound speed, CFL bound into slot 0
+template <typename R>
+void launch_init(const Prob<R> &P, const double *dk, hipStream_t s) {
+  const Grid &g = P.g;
+  const size_t C = (size_t)g.nx * g.ny, N = (size_t)(g.nx + 1) * (g.ny + 1);
+  const unsigned cb = (unsigned)((C + 255) / 256), nb = (unsigned)((N + 255) / 256);
+  k_init_state<R><<<cb, 256, 0, s>>>(P, dk, dk + g.nmat * C, dk + 2 * g.nmat * C);
+  k_init_vel<R><<<nb, 256, 0, s>>>(P, dk + 3 * g.nmat * C, dk + 3 * g.nmat * C + N);
+  k_sound<R><<<cb, 256, 0, s>>>(P, 0);
+  k_dt_bound<R><<<nb, 256, 0, s>>>(P, 0);
+}
+
+// fields of the state in buffer `buf` into host arrays, through `scratch`
+// (device, at least max(nmat*C, N) doubles)
+template <typename R>
+int fields_out(const Prob<R> &P, int buf, unsigned mask, double *const *out, double *scratch,
+               hipStream_t s, std::string &err) {
+  const Grid &g = P.g;
+  const size_t C = (size_t)g.nx * g.ny, N = (size_t)(g.nx + 1) * (g.ny + 1);
+  int slot = 0;
+  for (unsigned bit = 1; bit <= LR_F_IE; bit <<= 1) {
+    if (!(mask & bit)) continue;
+    double *o = out[slot++];
+    if (!o) {
+      err = "null output pointer";
+      return LR_EINVAL;
+    }
+    const bool node = bit == LR_F_UX || bit == LR_F_UY;
+    const bool per = bit == LR_F_K || bit == LR_F_RHOA || bit == LR_F_EA || bit == LR_F_PA ||
+                     bit == LR_F_VOL || bit == LR_F_MASS || bit == LR_F_IE;
+    const size_t n = node ? N : (per ? g.nmat * C : C);
+    k_fields<R><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(P, buf, bit, scratch);
+    HIP_TRY(err, hipGetLastError());
+    HIP_TRY(err, hipMemcpyAsync(o, scratch, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(err, hipStreamSynchronize(s));
+  return LR_OK;
+}
+
+template <typename R>
+int totals_out(const Prob<R> &P, int buf, double *out, hipStream_t s, std::string &err) {
+  const Grid &g = P.g;
+  const int N = (g.nx + 1) * (g.ny + 1);
+  const int nb = (N + 255) / 256, nq = 3 * g.nmat + 3;
+  double *part = nullptr;
+  HIP_TRY(err, hipMalloc(&part, ((size_t)nq * nb + nq) * sizeof(double)));
+  k_totals_partial<R><<<nb, 256, 0, s>>>(P, buf, part);
+  k_totals_final<<<1, 64, 0, s>>>(g.nmat, nb, part, part + (size_t)nq * nb);
+  const hipError_t e1 = hipMemcpyAsync(out, part + (size_t)nq * nb, nq * sizeof(double),
+                                       hipMemcpyDeviceToHost, s);
+  const hipError_t e2 = hipStreamSynchronize(s);
+  (void)hipFree(part);
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    err = "totals failed";
+    return LR_EDEVICE;
+  }
+  return LR_OK;
+}
+
+}  // namespace
+
+// ============================================================ single problem
 struct lr_ctx {
   lr_opts o{};
   Grid g{};
@@ -19,7 +272,6 @@ struct lr_ctx {
   bool have_state = false;
   std::string err;
   double *scratch = nullptr;  // staging for outputs
-  size_t scratch_n = 0;
   // kernel timing (lr_profile): event marks of the steps of one chunk
   bool prof = false;
   std::vector<hipEvent_t> ev;
@@ -29,8 +281,6 @@ struct lr_ctx {
 };
 
 namespace {
-
-constexpr int kChunk = 16;  // steps launched between completion checks
 
 int set_err(lr_ctx *c, int code, const std::string &msg) {
   if (c) c->err = msg;
@@ -43,7 +293,7 @@ int set_err(lr_ctx *c, int code, const std::string &msg) {
       return set_err((c), LR_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
   } while (0)
 
-template <class T>
+template <typename T>
 int dalloc(lr_ctx *c, T **p, size_t n) {
   void *q = nullptr;
   if (hipMalloc(&q, (n ? n : 1) * sizeof(T)) != hipSuccess) return LR_ENOMEM;
@@ -52,63 +302,27 @@ int dalloc(lr_ctx *c, T **p, size_t n) {
   return LR_OK;
 }
 
+bool fp32(const lr_ctx *c) { return c->o.precision == LR_FP32; }
+
 template <typename R>
 int alloc_prob(lr_ctx *c, Prob<R> &P) {
-  const Grid &g = c->g;
-  const size_t C = (size_t)g.nx * g.ny, N = (size_t)(g.nx + 1) * (g.ny + 1), m = g.nmat;
-  const size_t nX = (size_t)(g.nx + 1) * g.ny, nY = (size_t)g.nx * (g.ny + 1);
-  P = Prob<R>{};
-  P.g = g;
-  P.flip = 0;
-  int rc = LR_OK;
-  for (int b = 0; b < 2; ++b) {
-    rc |= dalloc(c, &P.V[b], m * C);
-    rc |= dalloc(c, &P.M[b], m * C);
-    rc |= dalloc(c, &P.E[b], m * C);
-  }
-  rc |= dalloc(c, &P.ux, N); rc |= dalloc(c, &P.uy, N);
-  rc |= dalloc(c, &P.uhx, N); rc |= dalloc(c, &P.uhy, N);
-  rc |= dalloc(c, &P.uLx, N); rc |= dalloc(c, &P.uLy, N); rc |= dalloc(c, &P.mp, N);
-  rc |= dalloc(c, &P.eL, m * C);
-  rc |= dalloc(c, &P.cs, C);
-  rc |= dalloc(c, &P.MX, nX); rc |= dalloc(c, &P.MY, nY); rc |= dalloc(c, &P.MC, N);
-  rc |= dalloc(c, &P.mix_cell, C); rc |= dalloc(c, &P.mix_slot, C);
-  P.mix_cap = (int)C;
-  rc |= dalloc(c, &P.mix_W, C * 8 * m);
-  if (c->o.stages) {
-    rc |= dalloc(c, &P.dbg.Q, C); rc |= dalloc(c, &P.dbg.S, C); rc |= dalloc(c, &P.dbg.VL, C);
-    rc |= dalloc(c, &P.dbg.Ph, m * C); rc |= dalloc(c, &P.dbg.volcf, C);
-    rc |= dalloc(c, &P.dbg.rhocf, m * C);
-    rc |= dalloc(c, &P.dbg.Wpx, m * nX); rc |= dalloc(c, &P.dbg.Wpy, m * nY);
-    rc |= dalloc(c, &P.dbg.Wpc, m * N);
-  }
-  if (rc != LR_OK) return LR_ENOMEM;
-  P.ctl = c->ctl;
-  // wall regions are never written: keep them zero
-  HIP_CHECK(c, hipMemsetAsync(P.MX, 0, nX * sizeof(R), c->own));
-  HIP_CHECK(c, hipMemsetAsync(P.MY, 0, nY * sizeof(R), c->own));
-  HIP_CHECK(c, hipMemsetAsync(P.MC, 0, N * sizeof(R), c->own));
-  if (P.dbg.Wpx) {
-    HIP_CHECK(c, hipMemsetAsync(P.dbg.Wpx, 0, m * nX * sizeof(R), c->own));
-    HIP_CHECK(c, hipMemsetAsync(P.dbg.Wpy, 0, m * nY * sizeof(R), c->own));
-    HIP_CHECK(c, hipMemsetAsync(P.dbg.Wpc, 0, m * N * sizeof(R), c->own));
-  }
-  void *d = nullptr;
-  if (hipMalloc(&d, sizeof(Prob<R>)) != hipSuccess) return LR_ENOMEM;
-  c->allocs.push_back(d);
+  const size_t bytes = carve_prob(P, nullptr, c->g, c->o.stages != 0, c->ctl);
+  char *mem = nullptr;
+  if (dalloc(c, &mem, bytes)) return LR_ENOMEM;
+  carve_prob(P, mem, c->g, c->o.stages != 0, c->ctl);
+  const int rc = clear_prob(P, c->own, c->err);
+  if (rc) return rc;
+  Prob<R> *d = nullptr;
+  if (dalloc(c, &d, 1)) return LR_ENOMEM;
   c->dprob = d;
   HIP_CHECK(c, hipMemcpyAsync(d, &P, sizeof(Prob<R>), hipMemcpyHostToDevice, c->own));
-  c->step = step_fn<R>(g.nmat);
+  c->step = step_fn<R>(c->g.nmat);
   return LR_OK;
 }
 
 int build_maps(lr_ctx *c) {
-  const Grid &g = c->g;
   std::vector<BlockMap> nm, cm;
-  for (int j = 0; j <= g.ny; j += TY)
-    for (int i = 0; i <= g.nx; i += TX) nm.push_back({0, i, j, 0});
-  for (int j = 0; j < g.ny; j += TY)
-    for (int i = 0; i < g.nx; i += TX) cm.push_back({0, i, j, 0});
+  tile_maps(c->g, 0, nm, cm);
   c->node_blocks = (int)nm.size();
   c->cell_blocks = (int)cm.size();
   if (dalloc(c, &c->node_map, nm.size()) || dalloc(c, &c->cell_map, cm.size())) return LR_ENOMEM;
@@ -118,34 +332,16 @@ int build_maps(lr_ctx *c) {
   return LR_OK;
 }
 
-bool fp32(const lr_ctx *c) { return c->o.precision == LR_FP32; }
-
 int read_ctl(lr_ctx *c) {
   HIP_CHECK(c, hipMemcpyAsync(c->hctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
   HIP_CHECK(c, hipStreamSynchronize(c->stream));
   return LR_OK;
 }
-int cur_slot(const Ctl &k) { return k.slot[1].step > k.slot[0].step ? 1 : 0; }
 
-// the time step a slot describes, with the device's arithmetic
-double host_slot_dt(const Grid &g, const Slot &s) {
-  unsigned long long b = s.dtmin[0];
-  for (int k = 1; k < NDT; ++k) b = s.dtmin[k] < b ? s.dtmin[k] : b;
-  double dtmin;
-  std::memcpy(&dtmin, &b, sizeof dtmin);
-  double dt = g.fixed_dt > 0.0 ? g.fixed_dt : g.cfl * dtmin;
-  if (s.t_end - s.t <= dt) dt = s.t_end - s.t;
-  return dt;
-}
-
-int err_code(lr_ctx *c, int bits) {
-  if (bits & ERR_NAN) return set_err(c, LR_ENAN, "non-finite value in the state");
-  if (bits & ERR_DT) return set_err(c, LR_EDT, "time step not positive or not finite");
-  if (bits & ERR_VOLCF) return set_err(c, LR_ENEGATIVE, "flux-consistent Lagrangian volume <= 0");
-  if (bits & ERR_NODEMASS) return set_err(c, LR_ENEGATIVE, "nodal mass <= 0 after remap");
-  if (bits & ERR_NEG) return set_err(c, LR_ENEGATIVE, "negative partial volume, mass or energy");
-  if (bits & ERR_MIXCAP) return set_err(c, LR_ENOMEM, "mixed-cell list capacity exceeded");
-  return LR_OK;
+int ctx_err(lr_ctx *c, int bits) {
+  const char *msg = "";
+  const int rc = err_code(bits, &msg);
+  return rc ? set_err(c, rc, msg) : LR_OK;
 }
 
 int collect_profile(lr_ctx *c) {
@@ -171,7 +367,7 @@ int run_steps(lr_ctx *c, double t_end, long long max_steps) {
   int gpar = cur_slot(*c->hctl);
   k_start<<<1, 1, 0, c->stream>>>(c->ctl, t_end, max_steps);
   HIP_CHECK(c, hipGetLastError());
-  const Launch L{c->dprob, c->node_map, c->cell_map, c->node_blocks, c->cell_blocks};
+  const Launch L{c->dprob, c->node_map, c->cell_map, c->node_blocks, c->cell_blocks, false};
   for (;;) {
     rc = read_ctl(c);
     if (rc) return rc;
@@ -190,62 +386,24 @@ int run_steps(lr_ctx *c, double t_end, long long max_steps) {
     }
     HIP_CHECK(c, hipGetLastError());
   }
-  return err_code(c, c->hctl->err);
+  return ctx_err(c, c->hctl->err);
 }
 
-template <typename R>
-void launch_set_state(lr_ctx *c, Prob<R> &P, const double *dk) {
-  const Grid &g = c->g;
-  const int C = g.nx * g.ny, N = (g.nx + 1) * (g.ny + 1);
-  k_init_state<R><<<(C + 255) / 256, 256, 0, c->stream>>>(P, dk, dk + (size_t)g.nmat * C,
-                                                          dk + 2 * (size_t)g.nmat * C);
-  k_init_vel<R><<<(N + 255) / 256, 256, 0, c->stream>>>(P, dk + 3 * (size_t)g.nmat * C,
-                                                       dk + 3 * (size_t)g.nmat * C + N);
-  k_sound<R><<<(C + 255) / 256, 256, 0, c->stream>>>(P, 0);
-  k_dt_bound<R><<<(N + 255) / 256, 256, 0, c->stream>>>(P, 0);
-}
-
-template <typename R>
-int get_fields_impl(lr_ctx *c, Prob<R> &P, int buf, unsigned mask, double *const *out) {
-  const Grid &g = c->g;
-  const size_t C = (size_t)g.nx * g.ny, N = (size_t)(g.nx + 1) * (g.ny + 1);
-  int slot = 0;
-  for (unsigned bit = 1; bit <= LR_F_IE; bit <<= 1) {
-    if (!(mask & bit)) continue;
-    double *o = out[slot++];
-    if (!o) return set_err(c, LR_EINVAL, "null output pointer");
-    const bool node = bit == LR_F_UX || bit == LR_F_UY;
-    const bool per = bit == LR_F_K || bit == LR_F_RHOA || bit == LR_F_EA || bit == LR_F_PA ||
-                     bit == LR_F_VOL || bit == LR_F_MASS || bit == LR_F_IE;
-    const size_t n = node ? N : (per ? g.nmat * C : C);
-    k_fields<R><<<(unsigned)((N + 255) / 256), 256, 0, c->stream>>>(P, buf, bit, c->scratch);
-    HIP_CHECK(c, hipGetLastError());
-    HIP_CHECK(c, hipMemcpyAsync(o, c->scratch, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  }
+// the state staged as FP64 [k | rho | e | ux | uy] in device memory becomes
+// the problem's state at time t
+int ctx_init_from_stage(lr_ctx *c, double t, const double *dk) {
+  *c->hctl = initial_ctl(t, t, 0);
+  HIP_CHECK(c, hipMemcpyAsync(c->ctl, c->hctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+  if (fp32(c)) launch_init<float>(c->pf, dk, c->stream);
+  else launch_init<double>(c->pd, dk, c->stream);
+  HIP_CHECK(c, hipGetLastError());
   HIP_CHECK(c, hipStreamSynchronize(c->stream));
+  c->have_state = true;
   return LR_OK;
 }
 
 template <typename R>
-int totals_impl(lr_ctx *c, Prob<R> &P, int buf, double *out) {
-  const Grid &g = c->g;
-  const int N = (g.nx + 1) * (g.ny + 1);
-  const int nb = (N + 255) / 256, nq = 3 * g.nmat + 3;
-  double *part = nullptr;
-  HIP_CHECK(c, hipMalloc(&part, ((size_t)nq * nb + nq) * sizeof(double)));
-  k_totals_partial<R><<<nb, 256, 0, c->stream>>>(P, buf, part);
-  k_totals_final<<<1, 64, 0, c->stream>>>(g.nmat, nb, part, part + (size_t)nq * nb);
-  const hipError_t e1 = hipMemcpyAsync(out, part + (size_t)nq * nb, nq * sizeof(double),
-                                       hipMemcpyDeviceToHost, c->stream);
-  const hipError_t e2 = hipStreamSynchronize(c->stream);
-  (void)hipFree(part);
-  if (e1 != hipSuccess || e2 != hipSuccess) return set_err(c, LR_EDEVICE, "totals failed");
-  return LR_OK;
-}
-
-// copy `count` elements of a device array of R into out as doubles
-template <typename R>
-int copy_out(lr_ctx *c, const R *src, size_t count, double *out) {
+int debug_copy(lr_ctx *c, const R *src, size_t count, double *out) {
   if (!src) return set_err(c, LR_ESTATE, "stage not kept: create the context with opts.stages = 1");
   std::vector<R> h(count);
   HIP_CHECK(c, hipMemcpyAsync(h.data(), src, count * sizeof(R), hipMemcpyDeviceToHost, c->stream));
@@ -266,28 +424,28 @@ int debug_impl(lr_ctx *c, Prob<R> &P, const std::string &n, double *out) {
   const double dt = host_slot_dt(g, k.slot[cur ^ 1]);
   if (n == "dt") { out[0] = dt; return LR_OK; }
   if (n == "t") { out[0] = k.slot[cur].t; return LR_OK; }
-  if (n == "Q") return copy_out(c, P.dbg.Q, C, out);
-  if (n == "S") return copy_out(c, P.dbg.S, C, out);
-  if (n == "VL") return copy_out(c, P.dbg.VL, C, out);
-  if (n == "P_half") return copy_out(c, P.dbg.Ph, m * C, out);
-  if (n == "volcf") return copy_out(c, P.dbg.volcf, C, out);
-  if (n == "rhocf") return copy_out(c, P.dbg.rhocf, m * C, out);
-  if (n == "eL") return copy_out(c, P.eL, m * C, out);
-  if (n == "mp") return copy_out(c, P.mp, N, out);
-  if (n == "uhx") return copy_out(c, P.uhx, N, out);
-  if (n == "uhy") return copy_out(c, P.uhy, N, out);
-  if (n == "uLx") return copy_out(c, P.uLx, N, out);
-  if (n == "uLy") return copy_out(c, P.uLy, N, out);
-  if (n == "muX") return copy_out(c, P.MX, nX, out);
-  if (n == "muY") return copy_out(c, P.MY, nY, out);
-  if (n == "Wpx") return copy_out(c, P.dbg.Wpx, m * nX, out);
-  if (n == "Wpy") return copy_out(c, P.dbg.Wpy, m * nY, out);
-  if (n == "Wpc") return copy_out(c, P.dbg.Wpc, m * N, out);
+  if (n == "Q") return debug_copy(c, P.dbg.Q, C, out);
+  if (n == "S") return debug_copy(c, P.dbg.S, C, out);
+  if (n == "VL") return debug_copy(c, P.dbg.VL, C, out);
+  if (n == "P_half") return debug_copy(c, P.dbg.Ph, m * C, out);
+  if (n == "volcf") return debug_copy(c, P.dbg.volcf, C, out);
+  if (n == "rhocf") return debug_copy(c, P.dbg.rhocf, m * C, out);
+  if (n == "eL") return debug_copy(c, P.eL, m * C, out);
+  if (n == "mp") return debug_copy(c, P.mp, N, out);
+  if (n == "uhx") return debug_copy(c, P.uhx, N, out);
+  if (n == "uhy") return debug_copy(c, P.uhy, N, out);
+  if (n == "uLx") return debug_copy(c, P.uLx, N, out);
+  if (n == "uLy") return debug_copy(c, P.uLy, N, out);
+  if (n == "muX") return debug_copy(c, P.MX, nX, out);
+  if (n == "muY") return debug_copy(c, P.MY, nY, out);
+  if (n == "Wpx") return debug_copy(c, P.dbg.Wpx, m * nX, out);
+  if (n == "Wpy") return debug_copy(c, P.dbg.Wpy, m * nY, out);
+  if (n == "Wpc") return debug_copy(c, P.dbg.Wpc, m * N, out);
   if (n == "dpx" || n == "dpy" || n == "muD" || n == "muA") {
     std::vector<double> hx(N), hy(N), fc(N);
-    rc = copy_out(c, P.uhx, N, hx.data());
-    if (!rc) rc = copy_out(c, P.uhy, N, hy.data());
-    if (!rc) rc = copy_out(c, P.MC, N, fc.data());
+    rc = debug_copy(c, P.uhx, N, hx.data());
+    if (!rc) rc = debug_copy(c, P.uhy, N, hy.data());
+    if (!rc) rc = debug_copy(c, P.MC, N, fc.data());
     if (rc) return rc;
     for (size_t p = 0; p < N; ++p) {
       const R dxr = R(dt) * R(hx[p]), dyr = R(dt) * R(hy[p]);
@@ -329,35 +487,17 @@ int lr_create(int nx, int ny, int nmat, const lr_eos *eos, const int bc[4], cons
               lr_ctx **out) {
   if (!out) return LR_EINVAL;
   *out = nullptr;
-  if (nx < 2 || ny < 2 || nmat < 1 || nmat > LR_MAXMAT || !eos) return LR_EINVAL;
-  if ((long long)nx * ny > (1ll << 28)) return LR_EINVAL;
-  if (bc)
-    for (int s = 0; s < 4; ++s)
-      if (bc[s] != LR_BC_REFLECT) return LR_EINVAL;
-  for (int a = 0; a < nmat; ++a)
-    if (!(eos[a].gamma > 1.0) || eos[a].pinf != 0.0) return LR_EINVAL;
   lr_opts o;
   if (opts) o = *opts;
   else lr_default_opts(&o);
-  if (!(o.x1 > o.x0) || !(o.y1 > o.y0) || !(o.cfl > 0) || (o.recon_order != 1 && o.recon_order != 2) ||
-      !(o.k_eps >= 0) || o.fixed_dt < 0 || (o.precision != LR_FP64 && o.precision != LR_FP32))
-    return LR_EINVAL;
+  Grid g;
+  if (make_grid(nx, ny, nmat, eos, bc, o, g) != LR_OK) return LR_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return LR_EDEVICE;
   lr_ctx *c = new (std::nothrow) lr_ctx();
   if (!c) return LR_ENOMEM;
   c->o = o;
-  Grid &g = c->g;
-  g.nx = nx; g.ny = ny; g.nmat = nmat;
-  g.recon_order = o.recon_order; g.kinematic = o.kinematic ? 1 : 0;
-  g.dx = (o.x1 - o.x0) / nx; g.dy = (o.y1 - o.y0) / ny; g.A = g.dx * g.dy;
-  g.Lx = o.x1 - o.x0; g.Ly = o.y1 - o.y0;
-  g.cfl = o.cfl; g.a1 = o.a1; g.a2 = o.a2; g.k_eps = o.k_eps; g.fixed_dt = o.fixed_dt;
-  // FP32 rounding leaves residues of about 1e-7 of a cell behind a material
-  // that moved out: presence and negativity thresholds above that level
-  g.neg_tol = o.precision == LR_FP32 ? 1e-5 : 1e-10;
-  if (o.precision == LR_FP32 && g.k_eps < 1e-6) g.k_eps = 1e-6;
-  for (int a = 0; a < nmat; ++a) g.gamma[a] = eos[a].gamma;
+  c->g = g;
   if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) {
     lr_destroy(c);
     return LR_EDEVICE;
@@ -368,9 +508,8 @@ int lr_create(int nx, int ny, int nmat, const lr_eos *eos, const int bc[4], cons
     rc = LR_ENOMEM;
   if (rc == LR_OK) rc = fp32(c) ? alloc_prob<float>(c, c->pf) : alloc_prob<double>(c, c->pd);
   if (rc == LR_OK) rc = build_maps(c);
-  const size_t N = (size_t)(nx + 1) * (ny + 1), nX = (size_t)(nx + 1) * ny;
-  c->scratch_n = std::max((size_t)nmat * std::max(N, nX), (size_t)4096);
-  if (rc == LR_OK) rc = dalloc(c, &c->scratch, c->scratch_n);
+  const size_t N = (size_t)(nx + 1) * (ny + 1), C = (size_t)nx * ny;
+  if (rc == LR_OK) rc = dalloc(c, &c->scratch, std::max((size_t)nmat * C, N));
   if (rc == LR_OK && hipStreamSynchronize(c->own) != hipSuccess) rc = LR_EDEVICE;
   if (rc != LR_OK) {
     lr_destroy(c);
@@ -394,51 +533,69 @@ int lr_set_state(lr_ctx *c, double t, const double *k, const double *rho, const 
   const int nm = g.nmat;
   const size_t C = (size_t)g.nx * g.ny, N = (size_t)(g.nx + 1) * (g.ny + 1);
   if (!std::isfinite(t)) return set_err(c, LR_EINVAL, "t not finite");
-  for (size_t q = 0; q < C; ++q) {
-    double ks = 0.0;
-    for (int a = 0; a < nm; ++a) {
-      const size_t h = a * C + q;
-      if (!std::isfinite(k[h]) || !std::isfinite(rho[h]) || !std::isfinite(e[h]))
-        return set_err(c, LR_ENAN, "non-finite input");
-      if (k[h] < 0.0 || k[h] > 1.0) return set_err(c, LR_ESTATE, "volume fraction outside [0,1]");
-      if (k[h] > 0.0 && (!(rho[h] > 0.0) || e[h] < 0.0))
-        return set_err(c, LR_ESTATE, "rho <= 0 or e < 0 where k > 0");
-      ks += k[h];
-    }
-    if (std::fabs(ks - 1.0) > 1e-12) return set_err(c, LR_ESTATE, "volume fractions do not sum to 1");
-  }
-  for (size_t p = 0; p < N; ++p)
-    if (!std::isfinite(ux[p]) || !std::isfinite(uy[p])) return set_err(c, LR_ENAN, "non-finite velocity");
+  const char *msg = "";
+  const int chk = check_state_host(g, k, rho, e, ux, uy, &msg);
+  if (chk) return set_err(c, chk, msg);
   double *dk = nullptr;
   if (hipMalloc(&dk, (3 * nm * C + 2 * N) * sizeof(double)) != hipSuccess)
     return set_err(c, LR_ENOMEM, "staging");
   hipStream_t s = c->stream;
   int rc = LR_OK;
-  Ctl h{};
-  h.slot[0].t = t;
-  h.slot[0].t_end = t;
-  const double inf = INFINITY;
-  for (int kk = 0; kk < NDT; ++kk) std::memcpy(&h.slot[0].dtmin[kk], &inf, sizeof inf);
-  h.slot[0].step = 0;
-  h.slot[0].done = 1;
-  h.slot[1] = h.slot[0];
-  h.slot[1].step = -1;
-  *c->hctl = h;
   if (hipMemcpyAsync(dk, k, nm * C * sizeof(double), hipMemcpyHostToDevice, s) ||
       hipMemcpyAsync(dk + nm * C, rho, nm * C * sizeof(double), hipMemcpyHostToDevice, s) ||
       hipMemcpyAsync(dk + 2 * nm * C, e, nm * C * sizeof(double), hipMemcpyHostToDevice, s) ||
       hipMemcpyAsync(dk + 3 * nm * C, ux, N * sizeof(double), hipMemcpyHostToDevice, s) ||
-      hipMemcpyAsync(dk + 3 * nm * C + N, uy, N * sizeof(double), hipMemcpyHostToDevice, s) ||
-      hipMemcpyAsync(c->ctl, c->hctl, sizeof(Ctl), hipMemcpyHostToDevice, s)) {
+      hipMemcpyAsync(dk + 3 * nm * C + N, uy, N * sizeof(double), hipMemcpyHostToDevice, s))
     rc = set_err(c, LR_EDEVICE, "upload failed");
-  } else {
-    if (fp32(c)) launch_set_state<float>(c, c->pf, dk);
-    else launch_set_state<double>(c, c->pd, dk);
-    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
-      rc = set_err(c, LR_EDEVICE, "initialisation kernels failed");
-  }
+  else
+    rc = ctx_init_from_stage(c, t, dk);
+  (void)hipStreamSynchronize(s);
   (void)hipFree(dk);
-  if (rc == LR_OK) c->have_state = true;
+  return rc;
+}
+
+int lr_set_state_device(lr_ctx *c, double t, const void *k, const void *rho, const void *e,
+                        const void *ux, const void *uy, int dtype) {
+  if (!c || !k || !rho || !e || !ux || !uy || (dtype != LR_F64 && dtype != LR_F32)) return LR_EINVAL;
+  if (!std::isfinite(t)) return set_err(c, LR_EINVAL, "t not finite");
+  const Grid &g = c->g;
+  const int nm = g.nmat;
+  const size_t C = (size_t)g.nx * g.ny, N = (size_t)(g.nx + 1) * (g.ny + 1);
+  const size_t nd = 3 * nm * C + 2 * N;
+  double *dk = nullptr;
+  if (hipMalloc(&dk, nd * sizeof(double) + 256) != hipSuccess) return set_err(c, LR_ENOMEM, "staging");
+  int *bits = reinterpret_cast<int *>(dk + nd);
+  hipStream_t s = c->stream;
+  const void *src[5] = {k, rho, e, ux, uy};
+  const size_t cnt[5] = {nm * C, nm * C, nm * C, N, N};
+  size_t off = 0;
+  int rc = LR_OK;
+  for (int a = 0; a < 5; ++a) {
+    const unsigned nb = (unsigned)((cnt[a] + 255) / 256);
+    if (dtype == LR_F64)
+      k_to_f64<double><<<nb, 256, 0, s>>>(static_cast<const double *>(src[a]), dk + off, (long long)cnt[a]);
+    else
+      k_to_f64<float><<<nb, 256, 0, s>>>(static_cast<const float *>(src[a]), dk + off, (long long)cnt[a]);
+    off += cnt[a];
+  }
+  int hbits = 0;
+  const size_t n = std::max(C, N);
+  if (hipGetLastError() != hipSuccess || hipMemsetAsync(bits, 0, sizeof(int), s) != hipSuccess) {
+    rc = set_err(c, LR_EDEVICE, "staging copy failed");
+  } else {
+    k_check_state<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(nm, (int)C, (int)N, dk, bits);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(&hbits, bits, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      rc = set_err(c, LR_EDEVICE, "state check failed");
+  }
+  if (rc == LR_OK && (hbits & 1)) rc = set_err(c, LR_ENAN, "non-finite input");
+  else if (rc == LR_OK && (hbits & 2))
+    rc = set_err(c, LR_ESTATE, "volume fractions outside [0,1] or not summing to 1");
+  else if (rc == LR_OK && (hbits & 4)) rc = set_err(c, LR_ESTATE, "rho <= 0 or e < 0 where k > 0");
+  if (rc == LR_OK) rc = ctx_init_from_stage(c, t, dk);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(dk);
   return rc;
 }
 
@@ -475,8 +632,8 @@ int lr_get_fields(lr_ctx *c, unsigned mask, double *const *out) {
   int rc = read_ctl(c);
   if (rc) return rc;
   const int buf = cur_slot(*c->hctl);
-  return fp32(c) ? get_fields_impl<float>(c, c->pf, buf, mask, out)
-                 : get_fields_impl<double>(c, c->pd, buf, mask, out);
+  return fp32(c) ? fields_out<float>(c->pf, buf, mask, out, c->scratch, c->stream, c->err)
+                 : fields_out<double>(c->pd, buf, mask, out, c->scratch, c->stream, c->err);
 }
 
 int lr_totals(lr_ctx *c, double *out) {
@@ -485,7 +642,8 @@ int lr_totals(lr_ctx *c, double *out) {
   int rc = read_ctl(c);
   if (rc) return rc;
   const int buf = cur_slot(*c->hctl);
-  return fp32(c) ? totals_impl<float>(c, c->pf, buf, out) : totals_impl<double>(c, c->pd, buf, out);
+  return fp32(c) ? totals_out<float>(c->pf, buf, out, c->stream, c->err)
+                 : totals_out<double>(c->pd, buf, out, c->stream, c->err);
 }
 
 int lr_debug_get(lr_ctx *c, const char *name, double *out) {

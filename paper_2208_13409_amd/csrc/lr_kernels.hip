@@ -137,7 +137,7 @@ __device__ void mixed_region_partials(const Prob<R> &P, const R *Vs, int i, int 
   int np = 0;
 #pragma unroll
   for (int m = 0; m < NM; ++m) {
-    V[m] = double(Vs[m * C + q]);
+    V[m] = double(ldg(Vs + (m * C + q)));
     pr[m] = V[m] > g.k_eps * g.A;
     if (pr[m]) {
       ++np;
@@ -157,7 +157,7 @@ __device__ void mixed_region_partials(const Prob<R> &P, const R *Vs, int i, int 
 #pragma unroll
       for (int aa = -1; aa <= 1; ++aa)
         k[bb + 1][aa + 1] =
-            double(Vs[m * C + refl_cell(j + bb, ny) * nx + refl_cell(i + aa, nx)]) / g.A;
+            double(ldg(Vs + (m * C + refl_cell(j + bb, ny) * nx + refl_cell(i + aa, nx)))) / g.A;
     gx = ((k[0][2] + 2.0 * k[1][2] + k[2][2]) - (k[0][0] + 2.0 * k[1][0] + k[2][0])) / (8.0 * g.dx);
     gy = ((k[2][0] + 2.0 * k[2][1] + k[2][2]) - (k[0][0] + 2.0 * k[0][1] + k[0][2])) / (8.0 * g.dy);
   };
@@ -252,19 +252,17 @@ __device__ void mixed_region_partials(const Prob<R> &P, const R *Vs, int i, int 
     }
   }
 #pragma unroll
-  for (int m = 0; m < NM; ++m) Wout[s * NM + m] = out ? W[m] : 0.0;
+  for (int m = 0; m < NM; ++m) stg(Wout + (s * NM + m), out ? W[m] : 0.0);
 }
 
 // =========================================================== k_lagrange
 template <typename R, int NM>
-__global__ void __launch_bounds__(NTHREADS) k_lagrange(const Prob<R> *probs, const BlockMap *map,
-                                                      int gpar) {
-  const BlockMap bm = map[blockIdx.x];
+__device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockMap bm, int gpar) {
   const Prob<R> &P = probs[bm.prob];
   const Grid &g = P.g;
   const int par = gpar ^ P.flip;
   Slot &S = P.ctl->slot[par];
-  if (S.done || P.ctl->err) return;
+  if (ldg(&S.done) || ldg(&P.ctl->err)) return;
   bool last;
   const R dt = R(slot_dt(g, S, last));
   const int nx = g.nx, ny = g.ny, C = nx * ny;
@@ -296,7 +294,7 @@ __global__ void __launch_bounds__(NTHREADS) k_lagrange(const Prob<R> *probs, con
       int np = 0;
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
-        const R V = Vs[m * C + q], M = Ms[m * C + q], E = Es[m * C + q];
+        const R V = ldg(Vs + (m * C + q)), M = ldg(Ms + (m * C + q)), E = ldg(Es + (m * C + q));
         Mm[m] = M;
         k[m] = V / A;
         pr[m] = present(g, V);
@@ -313,13 +311,13 @@ __global__ void __launch_bounds__(NTHREADS) k_lagrange(const Prob<R> *probs, con
         const R rhoc = Msum / A;
         const R c2 = rhoc > R(0) ? rc2 / rhoc : R(0);
         const R cc = c2 > R(0) ? sqrt(c2) : R(0);
-        const R div = (P.ux[br] + P.ux[tr] - P.ux[bl] - P.ux[tl]) / (R(2) * Dx) +
-                      (P.uy[tl] + P.uy[tr] - P.uy[bl] - P.uy[br]) / (R(2) * Dy);
+        const R div = (ldg(P.ux + br) + ldg(P.ux + tr) - ldg(P.ux + bl) - ldg(P.ux + tl)) / (R(2) * Dx) +
+                      (ldg(P.uy + tl) + ldg(P.uy + tr) - ldg(P.uy + bl) - ldg(P.uy + br)) / (R(2) * Dy);
         const R L = sqrt(A);
         if (div < R(0)) Qc = rhoc * (R(g.a1) * L * cc * fabs(div) + R(g.a2) * L * L * div * div);
         const R h = R(0.5) * dt;
-        const R hblx = h * P.ux[bl], hbly = h * P.uy[bl], hbrx = h * P.ux[br], hbry = h * P.uy[br];
-        const R htlx = h * P.ux[tl], htly = h * P.uy[tl], htrx = h * P.ux[tr], htry = h * P.uy[tr];
+        const R hblx = h * ldg(P.ux + bl), hbly = h * ldg(P.uy + bl), hbrx = h * ldg(P.ux + br), hbry = h * ldg(P.uy + br);
+        const R htlx = h * ldg(P.ux + tl), htly = h * ldg(P.uy + tl), htrx = h * ldg(P.ux + tr), htry = h * ldg(P.uy + tr);
         R Pch = R(0);
         if constexpr (sizeof(R) == 8) {
           const R Vh = quad_area(hblx, hbly, Dx + hbrx, hbry, htlx, Dy + htly, Dx + htrx, Dy + htry);
@@ -356,14 +354,14 @@ __global__ void __launch_bounds__(NTHREADS) k_lagrange(const Prob<R> *probs, con
       sMc[b][a] = Msum;
       sQ[b][a] = Qc;
       if (owned) {
-        if (P.dbg.Q) P.dbg.Q[q] = Qc;
-        if (P.dbg.S) P.dbg.S[q] = Sc;
+        if (P.dbg.Q) stg(P.dbg.Q + q, Qc);
+        if (P.dbg.S) stg(P.dbg.S + q, Sc);
         if (P.dbg.Ph)
-          for (int m = 0; m < NM; ++m) P.dbg.Ph[m * C + q] = g.kinematic ? R(0) : sPh[m][b][a];
+          for (int m = 0; m < NM; ++m) stg(P.dbg.Ph + (m * C + q), g.kinematic ? R(0) : sPh[m][b][a]);
       }
     }
     if (mixed_owned) s_mix[atomicAdd(&s_nmix, 1)] = (i - I0) + (j - J0) * TX;
-    else if (owned) P.mix_slot[j * nx + i] = -1;
+    else if (owned) stg(P.mix_slot + (j * nx + i), -1);
   }
   __syncthreads();
   // one global list position range per tile
@@ -377,7 +375,7 @@ __global__ void __launch_bounds__(NTHREADS) k_lagrange(const Prob<R> *probs, con
     const int p = J * (nx + 1) + I;
     const R mp = R(0.25) * (sMc[b][a] + sMc[b][a + 1] + sMc[b + 1][a] + sMc[b + 1][a + 1]);
     R uhx, uhy, uLx, uLy;
-    const R ux = P.ux[p], uy = P.uy[p];
+    const R ux = ldg(P.ux + p), uy = ldg(P.uy + p);
     if (g.kinematic) {
       uhx = uLx = ux;
       uhy = uLy = uy;
@@ -398,11 +396,11 @@ __global__ void __launch_bounds__(NTHREADS) k_lagrange(const Prob<R> *probs, con
     sdx[b][a] = dt * uhx;
     sdy[b][a] = dt * uhy;
     if (a < TX && b < TY) {
-      P.uhx[p] = uhx;
-      P.uhy[p] = uhy;
-      P.uLx[p] = uLx;
-      P.uLy[p] = uLy;
-      P.mp[p] = mp;
+      stg(P.uhx + p, uhx);
+      stg(P.uhy + p, uhy);
+      stg(P.uLx + p, uLx);
+      stg(P.uLy + p, uLy);
+      stg(P.mp + p, mp);
     }
   }
   __syncthreads();
@@ -420,10 +418,10 @@ __global__ void __launch_bounds__(NTHREADS) k_lagrange(const Prob<R> *probs, con
       R VL = R(0), dVL = R(0);
       if constexpr (sizeof(R) == 8) VL = quad_area(blx, bly, Dx + brx, bry, tlx, Dy + tly, Dx + trx, Dy + try_);
       else dVL = quad_area_change(Dx, Dy, blx, bly, brx, bry, tlx, tly, trx, try_);
-      if (P.dbg.VL) P.dbg.VL[q] = sizeof(R) == 8 ? VL : A + dVL;
+      if (P.dbg.VL) stg(P.dbg.VL + q, sizeof(R) == 8 ? VL : A + dVL);
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
-        const R V = Vs[m * C + q], M = Ms[m * C + q], E = Es[m * C + q];
+        const R V = ldg(Vs + (m * C + q)), M = ldg(Ms + (m * C + q)), E = ldg(Es + (m * C + q));
         const R e = M > R(0) ? E / M : R(0);
         R eL = e;
         if (!g.kinematic && present(g, V)) {
@@ -436,7 +434,7 @@ __global__ void __launch_bounds__(NTHREADS) k_lagrange(const Prob<R> *probs, con
             eL = e - (Ph + Qc) * (k * dVL / M);
           }
         }
-        P.eL[m * C + q] = eL;
+        stg(P.eL + (m * C + q), eL);
       }
     }
   }
@@ -454,13 +452,23 @@ __global__ void __launch_bounds__(NTHREADS) k_lagrange(const Prob<R> *probs, con
                                    sdy[b + 1][a + 1], P.mix_W + (size_t)pos * 8 * NM);
     if (tid % 8 == 0) {
       if (ok) {
-        P.mix_cell[pos] = q;
-        P.mix_slot[q] = pos;
+        stg(P.mix_cell + pos, q);
+        stg(P.mix_slot + q, pos);
       } else {
-        P.mix_slot[q] = -1;
+        stg(P.mix_slot + q, -1);
         atomicOr(&P.ctl->err, ERR_MIXCAP);
       }
     }
+  }
+}
+
+// one block per tile of the map; a grid smaller than the map walks it
+template <typename R, int NM>
+__global__ void __launch_bounds__(NTHREADS) k_lagrange(const Prob<R> *probs, const BlockMap *map,
+                                                  int nmap, int gpar) {
+  for (int b = blockIdx.x; b < nmap; b += gridDim.x) {
+    lagrange_tile<R, NM>(probs, map[b], gpar);
+    __syncthreads();  // the next tile reuses the LDS
   }
 }
 
@@ -478,20 +486,18 @@ struct RemapShared {
 };
 
 template <typename R, int NM>
-__global__ void __launch_bounds__(NTHREADS) k_remap(const Prob<R> *probs, const BlockMap *map,
-                                                   int gpar) {
+__device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap bm, int gpar) {
   using SH = RemapShared<R, NM>;
   __shared__ SH sh;
-  const BlockMap bm = map[blockIdx.x];
   const Prob<R> &P = probs[bm.prob];
   const Grid &g = P.g;
   Ctl *ctl = P.ctl;
   const int par = gpar ^ P.flip;
   const Slot &S = ctl->slot[par];
   const int i0 = bm.i0, j0 = bm.j0, tid = threadIdx.x;
-  if (S.done || ctl->err) {
+  if (ldg(&S.done) || ldg(&ctl->err)) {
     // keep the other slot stopped too, so that later launches also return
-    if (i0 == 0 && j0 == 0 && tid == 0) ctl->slot[par ^ 1].done = 1;
+    if (i0 == 0 && j0 == 0 && tid == 0) stg(&ctl->slot[par ^ 1].done, 1);
     return;
   }
   bool last;
@@ -505,13 +511,15 @@ __global__ void __launch_bounds__(NTHREADS) k_remap(const Prob<R> *probs, const 
   // the first tile of the problem prepares the next step's slot
   if (i0 == 0 && j0 == 0 && tid == 0) {
     Slot &N = ctl->slot[par ^ 1];
-    N.t = last ? S.t_end : S.t + dtd;
-    N.t_end = S.t_end;
-    N.step = S.step + 1;
-    N.limit = S.limit;
-    for (int k = 0; k < NDT; ++k) N.dtmin[k] = (unsigned long long)__double_as_longlong(INFINITY);
-    N.nmix = 0;
-    N.done = (last || N.step >= N.limit) ? 1 : 0;
+    const long long step = ldg(&S.step) + 1, limit = ldg(&S.limit);
+    const double t = ldg(&S.t), t_end = ldg(&S.t_end);
+    stg(&N.t, last ? t_end : t + dtd);
+    stg(&N.t_end, t_end);
+    stg(&N.step, step);
+    stg(&N.limit, limit);
+    for (int k = 0; k < NDT; ++k) stg(&N.dtmin[k], (unsigned long long)__double_as_longlong(INFINITY));
+    stg(&N.nmix, 0);
+    stg(&N.done, (last || step >= limit) ? 1 : 0);
     if (!(dtd > 0.0) || !isfinite(dtd)) atomicOr(&ctl->err, ERR_DT);
   }
 
@@ -521,7 +529,7 @@ __global__ void __launch_bounds__(NTHREADS) k_remap(const Prob<R> *probs, const 
     const int I = i0 - 2 + a, J = j0 - 2 + b;
     if (I > nx + 2 || J > ny + 2) continue;
     const int rI = refl_node(I, nx), rJ = refl_node(J, ny), p = rJ * (nx + 1) + rI;
-    R dx = dt * P.uhx[p], dy = dt * P.uhy[p];
+    R dx = dt * ldg(P.uhx + p), dy = dt * ldg(P.uhy + p);
     if (rI != I) dx = -dx;
     if (rJ != J) dy = -dy;
     sh.ndx[b][a] = dx;
@@ -563,21 +571,21 @@ __global__ void __launch_bounds__(NTHREADS) k_remap(const Prob<R> *probs, const 
     int np = 0, pm = -1;
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
-      const R V = Vs[m * C + q], M = Ms[m * C + q];
+      const R V = ldg(Vs + (m * C + q)), M = ldg(Ms + (m * C + q));
       const bool pr = present(g, V);
       if (pr) {
         ++np;
         pm = m;
       }
       sh.rcf[m][b][a] = pr ? M / ((V / A) * v) : R(0);
-      sh.el[m][b][a] = P.eL[m * C + q];
+      sh.el[m][b][a] = ldg(P.eL + (m * C + q));
     }
     sh.pure[b][a] = np == 1 ? pm : -1;
     if (ri == i && rj == j && a >= 2 && b >= 2 && a < TX + 2 && b < TY + 2) {
       if (!(v > R(0))) atomicOr(&ctl->err, ERR_VOLCF);
-      if (P.dbg.volcf) P.dbg.volcf[q] = v;
+      if (P.dbg.volcf) stg(P.dbg.volcf + q, v);
       if (P.dbg.rhocf)
-        for (int m = 0; m < NM; ++m) P.dbg.rhocf[m * C + q] = sh.rcf[m][b][a];
+        for (int m = 0; m < NM; ++m) stg(P.dbg.rhocf + (m * C + q), sh.rcf[m][b][a]);
     }
   }
   __syncthreads();
@@ -624,13 +632,13 @@ __global__ void __launch_bounds__(NTHREADS) k_remap(const Prob<R> *probs, const 
 #pragma unroll
       for (int m = 0; m < NM; ++m) W[s][m] = (pm == m && r.role[s] > 0) ? r.vol[s] : R(0);
     if (pm < 0) {
-      const int ms = P.mix_slot[q];
+      const int ms = ldg(P.mix_slot + q);
       if (ms >= 0 && ms < P.mix_cap) {
         const double *src = P.mix_W + (size_t)ms * 8 * NM;
 #pragma unroll
         for (int s = 0; s < 8; ++s)
 #pragma unroll
-          for (int m = 0; m < NM; ++m) W[s][m] = r.role[s] > 0 ? R(src[s * NM + m]) : R(0);
+          for (int m = 0; m < NM; ++m) W[s][m] = r.role[s] > 0 ? R(ldg(src + (s * NM + m))) : R(0);
       }
     }
     // order-2 values of the pure material, with the positivity guard
@@ -643,7 +651,7 @@ __global__ void __launch_bounds__(NTHREADS) k_remap(const Prob<R> *probs, const 
         if (m == pm) {
           rD = sh.rcf[m][cb][ca];
           eD = sh.el[m][cb][ca];
-          Mpm = Ms[m * C + q];
+          Mpm = ldg(Ms + (m * C + q));
         }
       const R dxL = sh.wx[cb][ca], dyL = sh.wy[cb][ca];
       const R xD = sh.xc[cb][ca], yD = sh.yc[cb][ca];
@@ -762,9 +770,9 @@ __global__ void __launch_bounds__(NTHREADS) k_remap(const Prob<R> *probs, const 
       bool bad_nan = false;
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
-        const R M0 = Ms[m * C + q];
+        const R M0 = ldg(Ms + (m * C + q));
         Acc<R> V, M, E;
-        V.init((Vs[m * C + q] / A) * v);
+        V.init((ldg(Vs + (m * C + q)) / A) * v);
         M.init(M0);
         E.init(M0 * sh.el[m][cb][ca]);
 #pragma unroll
@@ -779,9 +787,9 @@ __global__ void __launch_bounds__(NTHREADS) k_remap(const Prob<R> *probs, const 
         Vn[m] = V.get();
         Mn[m] = M.get();
         En[m] = E.get();
-        Vd[m * C + q] = Vn[m];
-        Md[m * C + q] = Mn[m];
-        Ed[m * C + q] = En[m];
+        stg(Vd + (m * C + q), Vn[m]);
+        stg(Md + (m * C + q), Mn[m]);
+        stg(Ed + (m * C + q), En[m]);
         Msa += fabs(Mn[m]);
         Esa += fabs(En[m]);
         if (!isfinite(Vn[m]) || !isfinite(Mn[m]) || !isfinite(En[m])) bad_nan = true;
@@ -804,7 +812,7 @@ __global__ void __launch_bounds__(NTHREADS) k_remap(const Prob<R> *probs, const 
       else if (bad_neg) atomicOr(&ctl->err, ERR_NEG);
       const R rhoc = Msum / A;
       const R c2 = rhoc > R(0) ? rc2 / rhoc : R(0);
-      P.cs[q] = c2 > R(0) ? sqrt(c2) : R(0);
+      stg(P.cs + q, c2 > R(0) ? sqrt(c2) : R(0));
       // total mass flux of the regions this cell owns (left face, bottom face,
       // bottom-left corner) for the momentum remap; walls are zero
       R mx = R(0), my = R(0), mc = R(0);
@@ -814,18 +822,28 @@ __global__ void __launch_bounds__(NTHREADS) k_remap(const Prob<R> *probs, const 
         my += sh.fy[NM + m][rs[2]];
         mc += sh.fc[NM + m][rs[4]];
       }
-      P.MX[j * (nx + 1) + i] = i > 0 ? mx : R(0);
-      P.MY[j * nx + i] = j > 0 ? my : R(0);
-      P.MC[j * (nx + 1) + i] = (i > 0 && j > 0) ? mc : R(0);
+      stg(P.MX + (j * (nx + 1) + i), i > 0 ? mx : R(0));
+      stg(P.MY + (j * nx + i), j > 0 ? my : R(0));
+      stg(P.MC + (j * (nx + 1) + i), (i > 0 && j > 0) ? mc : R(0));
       if (P.dbg.Wpx) {
         const int nX = (nx + 1) * ny, nY = nx * (ny + 1), nN = (nx + 1) * (ny + 1);
         for (int m = 0; m < NM; ++m) {
-          P.dbg.Wpx[m * nX + j * (nx + 1) + i] = i > 0 ? sh.fx[m][rs[0]] : R(0);
-          P.dbg.Wpy[m * nY + j * nx + i] = j > 0 ? sh.fy[m][rs[2]] : R(0);
-          P.dbg.Wpc[m * nN + j * (nx + 1) + i] = (i > 0 && j > 0) ? sh.fc[m][rs[4]] : R(0);
+          stg(P.dbg.Wpx + (m * nX + j * (nx + 1) + i), i > 0 ? sh.fx[m][rs[0]] : R(0));
+          stg(P.dbg.Wpy + (m * nY + j * nx + i), j > 0 ? sh.fy[m][rs[2]] : R(0));
+          stg(P.dbg.Wpc + (m * nN + j * (nx + 1) + i), (i > 0 && j > 0) ? sh.fc[m][rs[4]] : R(0));
         }
       }
     }
+  }
+}
+
+// one block per tile of the map; a grid smaller than the map walks it
+template <typename R, int NM>
+__global__ void __launch_bounds__(NTHREADS) k_remap(const Prob<R> *probs, const BlockMap *map,
+                                                  int nmap, int gpar) {
+  for (int b = blockIdx.x; b < nmap; b += gridDim.x) {
+    remap_tile<R, NM>(probs, map[b], gpar);
+    __syncthreads();  // the next tile reuses the LDS
   }
 }
 
@@ -846,7 +864,7 @@ __device__ __forceinline__ R mflux_x(const Prob<R> &P, int I, int j) {
   if (I < 0) { I = -I; sg = R(-1); }
   else if (I > nx) { I = 2 * nx - I; sg = R(-1); }
   if (I == 0 || I == nx) return R(0);
-  return sg * P.MX[j * (nx + 1) + I];
+  return sg * ldg(P.MX + (j * (nx + 1) + I));
 }
 template <typename R>
 __device__ __forceinline__ R mflux_y(const Prob<R> &P, int i, int J) {
@@ -856,22 +874,20 @@ __device__ __forceinline__ R mflux_y(const Prob<R> &P, int i, int J) {
   if (J < 0) { J = -J; sg = R(-1); }
   else if (J > ny) { J = 2 * ny - J; sg = R(-1); }
   if (J == 0 || J == ny) return R(0);
-  return sg * P.MY[J * nx + i];
+  return sg * ldg(P.MY + (J * nx + i));
 }
 
 template <typename R, int NM>
-__global__ void __launch_bounds__(NTHREADS) k_dual(const Prob<R> *probs, const BlockMap *map,
-                                                  int gpar) {
+__device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap bm, int gpar) {
   using SH = DualShared<R>;
   __shared__ SH sh;
-  const BlockMap bm = map[blockIdx.x];
   const Prob<R> &P = probs[bm.prob];
   const Grid &g = P.g;
   Ctl *ctl = P.ctl;
   const int par = gpar ^ P.flip;
   const Slot &S = ctl->slot[par];
   const int tid = threadIdx.x;
-  if (S.done || ctl->err) return;
+  if (ldg(&S.done) || ldg(&ctl->err)) return;
   bool last;
   const R dt = R(slot_dt(g, S, last));
   const int nx = g.nx, ny = g.ny;
@@ -885,7 +901,7 @@ __global__ void __launch_bounds__(NTHREADS) k_dual(const Prob<R> *probs, const B
       const int I = I0 - 2 + a, J = J0 - 2 + b;
       if (I > nx + 2 || J > ny + 2) continue;
       const int rI = refl_node(I, nx), rJ = refl_node(J, ny), p = rJ * (nx + 1) + rI;
-      R ulx = P.uLx[p], uly = P.uLy[p], dx = dt * P.uhx[p], dy = dt * P.uhy[p];
+      R ulx = ldg(P.uLx + p), uly = ldg(P.uLy + p), dx = dt * ldg(P.uhx + p), dy = dt * ldg(P.uhy + p);
       R X = R(rI) * Dx + dx, Y = R(rJ) * Dy + dy;
       if (rI != I) {
         ulx = -ulx;
@@ -934,7 +950,7 @@ __global__ void __launch_bounds__(NTHREADS) k_dual(const Prob<R> *probs, const B
       else if (rJ > ny) { rJ = 2 * ny - rJ; fy = true; }
       dg = an = R(0);
       if (rI == 0 || rI == nx || rJ == 0 || rJ == ny) return;
-      const R F = P.MC[rJ * (nx + 1) + rI];
+      const R F = ldg(P.MC + (rJ * (nx + 1) + rI));
       // kind from the real node's displacement (the staged node is mirrored)
       R ddx = sh.dx[M_(J)][L(I)], ddy = sh.dy[M_(J)][L(I)];
       if (fx) ddx = -ddx;
@@ -1027,14 +1043,14 @@ __global__ void __launch_bounds__(NTHREADS) k_dual(const Prob<R> *probs, const B
     const int I = I0 + a, J = J0 + b;
     if (I <= nx && J <= ny) {
       const int p = J * (nx + 1) + I;
-      R ux = P.ux[p], uy = P.uy[p];
+      R ux = ldg(P.ux + p), uy = ldg(P.uy + p);
       if (!g.kinematic) {
         const int hW = b * (TX + 1) + a, hE = hW + 1;
         const int hS = b * TX + a, hN = hS + TX;
         const int hSW = b * (TX + 1) + a, hNE = (b + 1) * (TX + 1) + a + 1;  // cells (I-1,J-1), (I,J)
         const int hNW = (b + 1) * (TX + 1) + a, hSE = b * (TX + 1) + a + 1;  // cells (I-1,J), (I,J-1)
-        R m = P.mp[p];
-        R mu = m * P.uLx[p], mv = m * P.uLy[p];
+        R m = ldg(P.mp + p);
+        R mu = m * ldg(P.uLx + p), mv = m * ldg(P.uLy + p);
         m += sh.fx[0][hW]; mu += sh.fx[1][hW]; mv += sh.fx[2][hW];
         m -= sh.fx[0][hE]; mu -= sh.fx[1][hE]; mv -= sh.fx[2][hE];
         m += sh.fy[0][hS]; mu += sh.fy[1][hS]; mv += sh.fy[2][hS];
@@ -1049,8 +1065,8 @@ __global__ void __launch_bounds__(NTHREADS) k_dual(const Prob<R> *probs, const B
         if (I == 0 || I == nx) ux = R(0);
         if (J == 0 || J == ny) uy = R(0);
         if (!isfinite(ux) || !isfinite(uy)) atomicOr(&ctl->err, ERR_NAN);
-        P.ux[p] = ux;
-        P.uy[p] = uy;
+        stg(P.ux + p, ux);
+        stg(P.uy + p, uy);
       }
       // node-wise CFL bound: the largest sound speed of the adjacent cells
       R cmax = R(0);
@@ -1060,13 +1076,23 @@ __global__ void __launch_bounds__(NTHREADS) k_dual(const Prob<R> *probs, const B
         for (int aa = -1; aa <= 0; ++aa) {
           const int ci = I + aa, cj = J + bb;
           if (ci < 0 || cj < 0 || ci >= nx || cj >= ny) continue;
-          cmax = fmax(cmax, P.cs[cj * nx + ci]);
+          cmax = fmax(cmax, ldg(P.cs + (cj * nx + ci)));
         }
       const double bound = fmin(double(Dx / (cmax + fabs(ux))), double(Dy / (cmax + fabs(uy))));
       cand = (unsigned long long)__double_as_longlong(bound);
     }
   }
   block_min_to_slot(cand, ctl->slot[par ^ 1]);
+}
+
+// one block per tile of the map; a grid smaller than the map walks it
+template <typename R, int NM>
+__global__ void __launch_bounds__(NTHREADS) k_dual(const Prob<R> *probs, const BlockMap *map,
+                                                  int nmap, int gpar) {
+  for (int b = blockIdx.x; b < nmap; b += gridDim.x) {
+    dual_tile<R, NM>(probs, map[b], gpar);
+    __syncthreads();  // the next tile reuses the LDS
+  }
 }
 
 // =========================================================== set-up kernels
@@ -1134,6 +1160,38 @@ __global__ void k_dt_bound(Prob<R> P, int slot) {
     cand = (unsigned long long)__double_as_longlong(bound);
   }
   block_min_to_slot(cand, P.ctl->slot[slot]);
+}
+
+// a device input of element type T copied into the FP64 staging array
+template <typename T>
+__global__ void k_to_f64(const T *src, double *dst, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = double(src[i]);
+}
+
+// the checks of a host-given state, on a staged one: [k | rho | e] per
+// material, then ux, uy; bits: 1 non-finite, 2 fractions outside [0,1] or
+// not summing to 1, 4 rho <= 0 or e < 0 where k > 0
+__global__ void k_check_state(int nmat, int C, int N, const double *dk, int *bits) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int b = 0;
+  if (i < C) {
+    double ks = 0.0;
+    for (int a = 0; a < nmat; ++a) {
+      const double k = dk[(size_t)a * C + i], rho = dk[(size_t)(nmat + a) * C + i],
+                   e = dk[(size_t)(2 * nmat + a) * C + i];
+      if (!isfinite(k) || !isfinite(rho) || !isfinite(e)) b |= 1;
+      if (k < 0.0 || k > 1.0) b |= 2;
+      if (k > 0.0 && (!(rho > 0.0) || e < 0.0)) b |= 4;
+      ks += k;
+    }
+    if (!(fabs(ks - 1.0) <= 1e-12)) b |= 2;
+  }
+  if (i < N) {
+    const double *u = dk + (size_t)3 * nmat * C;
+    if (!isfinite(u[i]) || !isfinite(u[N + i])) b |= 1;
+  }
+  if (b) atomicOr(bits, b);
 }
 
 // derived output fields of the state in buffer `buf`
@@ -1245,24 +1303,65 @@ __global__ void k_start(Ctl *ctl, double t_end, long long max_steps) {
 constexpr int kKernels = 3;
 const char *const kKernelNames[kKernels] = {"k_lagrange", "k_remap", "k_dual"};
 
+// one step's launches: the block maps of node and cell tiles of every
+// problem; `persistent` limits each grid to the blocks the device holds at
+// once (each block then walks the map)
 struct Launch {
   const void *probs;
   const BlockMap *node_map, *cell_map;
   int node_blocks, cell_blocks;
+  bool persistent;
 };
 
 template <typename R, int NM>
+struct Resident {  // blocks of each step kernel resident on the whole device
+  int n[kKernels] = {0, 0, 0};
+  Resident() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return;
+    const void *fn[kKernels] = {reinterpret_cast<const void *>(&k_lagrange<R, NM>),
+                                reinterpret_cast<const void *>(&k_remap<R, NM>),
+                                reinterpret_cast<const void *>(&k_dual<R, NM>)};
+    for (int k = 0; k < kKernels; ++k) {
+      int per = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn[k], NTHREADS, 0) == hipSuccess)
+        n[k] = per * cus;
+    }
+  }
+};
+
+template <typename R, int NM>
+const Resident<R, NM> &resident() {
+  static const Resident<R, NM> r;
+  return r;
+}
+// query the resident block counts before any stream capture needs them
+template <typename R>
+void warm_resident(int nmat) {
+  switch (nmat) {
+    case 1: (void)resident<R, 1>(); break;
+    case 2: (void)resident<R, 2>(); break;
+    case 3: (void)resident<R, 3>(); break;
+    default: (void)resident<R, 4>(); break;
+  }
+}
+
+template <typename R, int NM>
 void step_impl(const Launch &L, int gpar, hipStream_t s, hipEvent_t *ev) {
+  const Resident<R, NM> &res = resident<R, NM>();
   const Prob<R> *p = static_cast<const Prob<R> *>(L.probs);
+  auto grid = [&](int k, int n) { return (L.persistent && res.n[k] > 0 && res.n[k] < n) ? res.n[k] : n; };
   auto mark = [&](int k) {
     if (ev) (void)hipEventRecord(ev[k], s);
   };
   mark(0);
-  k_lagrange<R, NM><<<L.node_blocks, NTHREADS, 0, s>>>(p, L.node_map, gpar);
+  k_lagrange<R, NM><<<grid(0, L.node_blocks), NTHREADS, 0, s>>>(p, L.node_map, L.node_blocks, gpar);
   mark(1);
-  k_remap<R, NM><<<L.cell_blocks, NTHREADS, 0, s>>>(p, L.cell_map, gpar);
+  k_remap<R, NM><<<grid(1, L.cell_blocks), NTHREADS, 0, s>>>(p, L.cell_map, L.cell_blocks, gpar);
   mark(2);
-  k_dual<R, NM><<<L.node_blocks, NTHREADS, 0, s>>>(p, L.node_map, gpar);
+  k_dual<R, NM><<<grid(2, L.node_blocks), NTHREADS, 0, s>>>(p, L.node_map, L.node_blocks, gpar);
   mark(3);
 }
 using StepFn = void (*)(const Launch &, int, hipStream_t, hipEvent_t *);
@@ -1279,3 +1378,4 @@ StepFn step_fn(int nmat) {
 }  // namespace
 
 #include "lr_host.hpp"
+#include "lr_batch.hpp"

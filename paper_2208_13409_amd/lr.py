@@ -24,9 +24,14 @@ PER_MAT = {F_K, F_RHOA, F_EA, F_PA, F_VOL, F_MASS, F_IE}
 NODE = {F_UX, F_UY}
 FIELD_BITS = {"rho": F_RHO, "p": F_P, "e": F_E, "k": F_K, "rho_a": F_RHOA, "e_a": F_EA,
               "p_a": F_PA, "ux": F_UX, "uy": F_UY, "vol": F_VOL, "mass": F_MASS, "ie": F_IE}
-EXPORTS = ("lr_default_opts", "lr_create", "lr_bind_stream", "lr_set_state", "lr_step", "lr_run",
-           "lr_get_fields", "lr_totals", "lr_debug_get", "lr_last_error", "lr_destroy",
-           "lr_profile", "lr_profile_read", "lr_kernel_count", "lr_kernel_name")
+EXPORTS = ("lr_default_opts", "lr_create", "lr_bind_stream", "lr_set_state", "lr_set_state_device",
+           "lr_step", "lr_run", "lr_get_fields", "lr_totals", "lr_debug_get", "lr_last_error",
+           "lr_destroy", "lr_profile", "lr_profile_read", "lr_kernel_count", "lr_kernel_name",
+           "lr_batch_default_opts", "lr_batch_create", "lr_batch_bind_stream", "lr_batch_footprint",
+           "lr_batch_submit", "lr_batch_step", "lr_batch_poll", "lr_batch_status",
+           "lr_batch_get_fields", "lr_batch_totals", "lr_batch_release", "lr_batch_running",
+           "lr_batch_last_error", "lr_batch_destroy")
+LR_F64_IN, LR_F32_IN = 0, 1  # element types of lr_set_state_device
 
 
 class lr_eos(C.Structure):
@@ -39,6 +44,12 @@ class lr_opts(C.Structure):
                 ("a2", C.c_double), ("precision", C.c_int), ("recon_order", C.c_int),
                 ("kinematic", C.c_int), ("k_eps", C.c_double), ("fixed_dt", C.c_double),
                 ("stages", C.c_int)]
+
+
+class lr_batch_opts(C.Structure):
+    _fields_ = [("max_slots", C.c_int), ("pool_bytes", C.c_size_t), ("nmat", C.c_int),
+                ("precision", C.c_int), ("chunk_steps", C.c_int), ("use_graph", C.c_int),
+                ("persistent", C.c_int)]
 
 
 class LRError(RuntimeError):
@@ -55,6 +66,13 @@ def load():
     if not os.path.exists(SO_PATH):
         raise FileNotFoundError(f"{SO_PATH} is missing: run paper_2208_13409_amd/build.py "
                                 "(the HIP library is required; there is no fallback)")
+    # PyTorch ships its own HIP runtime under the same soname: loading it
+    # first makes the library bind to that one, so that one runtime owns the
+    # device and torch's streams and device pointers are valid here too
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(SO_PATH)
     P = C.POINTER
     dp = P(C.c_double)
@@ -78,9 +96,32 @@ def load():
     lib.lr_kernel_count.argtypes = []
     lib.lr_kernel_name.argtypes = [C.c_int]
     lib.lr_kernel_name.restype = C.c_char_p
-    for n in ("lr_create", "lr_bind_stream", "lr_set_state", "lr_step", "lr_run",
-              "lr_get_fields", "lr_totals", "lr_debug_get", "lr_profile", "lr_profile_read",
-              "lr_kernel_count"):
+    vp = C.c_void_p
+    lib.lr_set_state_device.argtypes = [vp, C.c_double, vp, vp, vp, vp, vp, C.c_int]
+    lib.lr_batch_default_opts.argtypes = [P(lr_batch_opts)]
+    lib.lr_batch_default_opts.restype = None
+    lib.lr_batch_create.argtypes = [P(lr_batch_opts), P(vp)]
+    lib.lr_batch_bind_stream.argtypes = [vp, vp]
+    lib.lr_batch_footprint.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
+    lib.lr_batch_footprint.restype = C.c_size_t
+    lib.lr_batch_submit.argtypes = [vp, C.c_int, C.c_int, P(lr_eos), P(lr_opts), C.c_double, C.c_long,
+                                    dp, dp, dp, dp, dp, P(C.c_long)]
+    lib.lr_batch_step.argtypes = [vp, P(C.c_int)]
+    lib.lr_batch_poll.argtypes = [vp, P(C.c_long), C.c_int, P(C.c_int)]
+    lib.lr_batch_status.argtypes = [vp, C.c_long, P(C.c_int), P(C.c_long), dp]
+    lib.lr_batch_get_fields.argtypes = [vp, C.c_long, C.c_uint, P(dp)]
+    lib.lr_batch_totals.argtypes = [vp, C.c_long, dp]
+    lib.lr_batch_release.argtypes = [vp, C.c_long]
+    lib.lr_batch_running.argtypes = [vp]
+    lib.lr_batch_last_error.argtypes = [vp]
+    lib.lr_batch_last_error.restype = C.c_char_p
+    lib.lr_batch_destroy.argtypes = [vp]
+    lib.lr_batch_destroy.restype = None
+    for n in ("lr_create", "lr_bind_stream", "lr_set_state", "lr_set_state_device", "lr_step",
+              "lr_run", "lr_get_fields", "lr_totals", "lr_debug_get", "lr_profile",
+              "lr_profile_read", "lr_kernel_count", "lr_batch_create", "lr_batch_bind_stream",
+              "lr_batch_submit", "lr_batch_step", "lr_batch_poll", "lr_batch_status",
+              "lr_batch_get_fields", "lr_batch_totals", "lr_batch_release", "lr_batch_running"):
         getattr(lib, n).restype = C.c_int
     _LIB = lib
     return lib
@@ -145,6 +186,17 @@ class Solver:
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (k, rho, e, ux, uy)]
         self._check(self.lib.lr_set_state(self.h, float(t), *[_dptr(a) for a in arrs]))
 
+    def set_state_device(self, t, k, rho, e, ux, uy):
+        """State from device tensors (torch, float64 or float32, contiguous),
+        copied on the context's stream."""
+        ts = (k, rho, e, ux, uy)
+        dt = {str(x.dtype) for x in ts}
+        if len(dt) != 1 or not all(x.is_cuda and x.is_contiguous() for x in ts):
+            raise ValueError("five contiguous device tensors of one dtype expected")
+        code = LR_F32_IN if "float32" in dt.pop() else LR_F64_IN
+        self._check(self.lib.lr_set_state_device(self.h, float(t), *[C.c_void_p(x.data_ptr()) for x in ts],
+                                                 code))
+
     def step(self):
         dt = C.c_double()
         self._check(self.lib.lr_step(self.h, C.byref(dt)))
@@ -161,24 +213,7 @@ class Solver:
         return rc, n.value, t.value
 
     def fields(self, *names):
-        mask = 0
-        for n_ in names:
-            mask |= FIELD_BITS[n_]
-        bufs, outs = {}, []
-        for bit in sorted(FIELD_BITS.values()):
-            if not mask & bit:
-                continue
-            if bit in PER_MAT:
-                shape = (self.nmat, self.ny, self.nx)
-            elif bit in NODE:
-                shape = (self.ny + 1, self.nx + 1)
-            else:
-                shape = (self.ny, self.nx)
-            bufs[bit] = np.zeros(shape)
-            outs.append(bufs[bit])
-        ptrs = (C.POINTER(C.c_double) * len(outs))(*[_dptr(b) for b in outs])
-        self._check(self.lib.lr_get_fields(self.h, mask, ptrs))
-        return {n_: bufs[FIELD_BITS[n_]] for n_ in names}
+        return _fields(self.lib.lr_get_fields, self.h, self.nx, self.ny, self.nmat, self._check, names)
 
     def totals(self):
         out = np.zeros(3 * self.nmat + 3)
@@ -206,3 +241,125 @@ class Solver:
         out = np.zeros(shapes.get(name, (ny + 1, nx + 1)))
         self._check(self.lib.lr_debug_get(self.h, name.encode(), _dptr(out)))
         return out
+
+
+def _fields(fn, h, nx, ny, nmat, check, names, *lead):
+    mask = 0
+    for n_ in names:
+        mask |= FIELD_BITS[n_]
+    bufs, outs = {}, []
+    for bit in sorted(FIELD_BITS.values()):
+        if not mask & bit:
+            continue
+        if bit in PER_MAT:
+            shape = (nmat, ny, nx)
+        elif bit in NODE:
+            shape = (ny + 1, nx + 1)
+        else:
+            shape = (ny, nx)
+        bufs[bit] = np.zeros(shape)
+        outs.append(bufs[bit])
+    ptrs = (C.POINTER(C.c_double) * len(outs))(*[_dptr(b) for b in outs])
+    check(fn(h, *lead, mask, ptrs))
+    return {n_: bufs[FIELD_BITS[n_]] for n_ in names}
+
+
+def lr_batch_default_opts():
+    o = lr_batch_opts()
+    load().lr_batch_default_opts(C.byref(o))
+    return o
+
+
+class Batch:
+    """Many problems stepped together (continuous batching); see lr_batch_* in
+    include/lr.h.  submit() returns a request id, or None when the batch has
+    no room now (LR_EAGAIN)."""
+
+    def __init__(self, nmat=2, precision=LR_FP32, max_slots=256, pool_bytes=4 << 30,
+                 chunk_steps=16, use_graph=True, persistent=True, stream=None):
+        self.lib = load()
+        o = lr_batch_default_opts()
+        o.max_slots, o.pool_bytes, o.nmat, o.precision = int(max_slots), int(pool_bytes), int(nmat), int(precision)
+        o.chunk_steps, o.use_graph, o.persistent = int(chunk_steps), int(bool(use_graph)), int(bool(persistent))
+        self.nmat, self.precision = int(nmat), int(precision)
+        h = C.c_void_p()
+        rc = self.lib.lr_batch_create(C.byref(o), C.byref(h))
+        if rc != LR_OK:
+            raise LRError(rc, "lr_batch_create failed")
+        self.h = h
+        self.shapes = {}
+        if stream is not None:
+            handle = getattr(stream, "cuda_stream", stream)
+            self._check(self.lib.lr_batch_bind_stream(self.h, C.c_void_p(handle)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lr_batch_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def _check(self, rc):
+        if rc != LR_OK:
+            raise LRError(rc, self.lib.lr_batch_last_error(self.h).decode())
+        return rc
+
+    def footprint(self, nx, ny):
+        return int(self.lib.lr_batch_footprint(int(nx), int(ny), self.nmat, self.precision))
+
+    def submit(self, prob, t_end, max_steps=1 << 40, cfl=0.5, a1=0.5, a2=1.0, recon_order=2,
+               kinematic=False, k_eps=1e-10, fixed_dt=0.0):
+        """prob: dict with nx, ny, gammas, domain, k, rho, e, ux, uy."""
+        o = lr_default_opts()
+        o.x0, o.x1, o.y0, o.y1 = map(float, prob["domain"])
+        o.cfl, o.a1, o.a2 = float(cfl), float(a1), float(a2)
+        o.recon_order, o.kinematic = int(recon_order), int(bool(kinematic))
+        o.k_eps, o.fixed_dt, o.precision = float(k_eps), float(fixed_dt), self.precision
+        gam = prob["gammas"]
+        if len(gam) != self.nmat:
+            raise LRError(LR_EINVAL, f"{len(gam)} materials in a batch of nmat={self.nmat}")
+        eos = (lr_eos * len(gam))(*[lr_eos(float(g), 0.0) for g in gam])
+        arrs = [np.ascontiguousarray(prob[n], dtype=np.float64) for n in ("k", "rho", "e", "ux", "uy")]
+        rid = C.c_long()
+        rc = self.lib.lr_batch_submit(self.h, int(prob["nx"]), int(prob["ny"]), eos, C.byref(o),
+                                      float(t_end), int(max_steps), *[_dptr(a) for a in arrs],
+                                      C.byref(rid))
+        if rc == LR_EAGAIN:
+            return None
+        self._check(rc)
+        self.shapes[rid.value] = (int(prob["nx"]), int(prob["ny"]))
+        return rid.value
+
+    def step(self):
+        """one chunk of steps; returns the number of problems still running"""
+        n = C.c_int()
+        self._check(self.lib.lr_batch_step(self.h, C.byref(n)))
+        return n.value
+
+    def poll(self, cap=4096):
+        ids = (C.c_long * cap)()
+        n = C.c_int()
+        self._check(self.lib.lr_batch_poll(self.h, ids, cap, C.byref(n)))
+        return [ids[i] for i in range(n.value)]
+
+    def status(self, rid):
+        rc, st, t = C.c_int(), C.c_long(), C.c_double()
+        self._check(self.lib.lr_batch_status(self.h, int(rid), C.byref(rc), C.byref(st), C.byref(t)))
+        return rc.value, st.value, t.value
+
+    def fields(self, rid, *names):
+        nx, ny = self.shapes[rid]
+        return _fields(self.lib.lr_batch_get_fields, self.h, nx, ny, self.nmat, self._check, names,
+                       C.c_long(int(rid)))
+
+    def totals(self, rid):
+        out = np.zeros(3 * self.nmat + 3)
+        self._check(self.lib.lr_batch_totals(self.h, int(rid), _dptr(out)))
+        return out
+
+    def release(self, rid):
+        self._check(self.lib.lr_batch_release(self.h, int(rid)))
+        self.shapes.pop(rid, None)
+
+    def running(self):
+        return int(self.lib.lr_batch_running(self.h))

@@ -19,7 +19,9 @@ def _declared(header):
 def test_header_declares_the_boundary():
     names = _declared("include/lr.h")
     for n in ("lr_create", "lr_set_state", "lr_step", "lr_run", "lr_get_fields", "lr_totals",
-              "lr_destroy", "lr_bind_stream", "lr_last_error", "lr_debug_get", "lr_default_opts"):
+              "lr_destroy", "lr_bind_stream", "lr_last_error", "lr_debug_get", "lr_default_opts",
+              "lr_set_state_device", "lr_batch_create", "lr_batch_submit", "lr_batch_step",
+              "lr_batch_poll", "lr_batch_get_fields", "lr_batch_release", "lr_batch_destroy"):
         assert n in names
 
 
@@ -38,8 +40,8 @@ def test_oracle_exports_the_same_calls():
     lib = load()
     for n in _declared("include/lr.h"):
         if n in ("lr_bind_stream", "lr_profile", "lr_profile_read", "lr_kernel_count",
-                 "lr_kernel_name"):
-            continue  # host-only oracle: no streams, no kernels to time
+                 "lr_kernel_name", "lr_set_state_device") or n.startswith("lr_batch_"):
+            continue  # host-only oracle: no streams, kernels, device inputs or batches
         assert hasattr(lib, n.replace("lr_", "lr_ref_", 1)), n
 
 
@@ -66,3 +68,29 @@ def test_argument_validation_without_device():
     o = lr.lr_default_opts()
     assert lib.lr_create(4, 4, 1, bad, None, ctypes.byref(o), ctypes.byref(h)) == lr.LR_EINVAL
     assert lib.lr_step(None, None) == lr.LR_EINVAL
+
+
+def test_binding_exports_list_matches_header():
+    from paper_2208_13409_amd import lr
+    assert sorted(lr.EXPORTS) == _declared("include/lr.h")
+
+
+def test_batch_argument_validation_without_device():
+    """Batch options are checked before any device call; the footprint is
+    host arithmetic and grows with the grid."""
+    from paper_2208_13409_amd import lr
+    lib = lr.load()
+    o = lr.lr_batch_default_opts()
+    assert o.chunk_steps % 2 == 0 and o.max_slots >= 1
+    h = ctypes.c_void_p()
+    o.chunk_steps = 3
+    assert lib.lr_batch_create(ctypes.byref(o), ctypes.byref(h)) == lr.LR_EINVAL
+    o = lr.lr_batch_default_opts()
+    o.nmat = 0
+    assert lib.lr_batch_create(ctypes.byref(o), ctypes.byref(h)) == lr.LR_EINVAL
+    f32 = lib.lr_batch_footprint(64, 64, 2, lr.LR_FP32)
+    f64 = lib.lr_batch_footprint(64, 64, 2, lr.LR_FP64)
+    big = lib.lr_batch_footprint(128, 128, 2, lr.LR_FP32)
+    assert 0 < f32 < f64 and 3.5 * f32 < big < 4.5 * f32
+    assert lib.lr_batch_footprint(1, 64, 2, lr.LR_FP32) == 0
+    assert lib.lr_batch_step(None, None) == lr.LR_EINVAL

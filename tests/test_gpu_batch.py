@@ -1,0 +1,205 @@
+"""Batched and device-input paths on the GPU, through the C-ABI.
+
+A problem stepped inside a batch runs the same kernels on its own data with
+its own time step, so its fields must equal those of the same problem run
+alone in a single context (compared exactly, with the FP64 oracle as a
+second reference for one member).  Covers graph replay and plain launches,
+persistent and one-block-per-tile grids, admission while others run,
+LR_EAGAIN when the pool or the slots are full, release and reuse, and
+problems that finish at different steps."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import RefSolver
+from paper_2208_13409_amd import inputs
+from paper_2208_13409_amd.lr import LR_EAGAIN, LR_FP32, LR_FP64, LR_OK, Batch, LRError, Solver
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("vol", "mass", "ie", "ux", "uy")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def problems(nmat=2, seeds=(11, 12, 13, 14), sizes=((40, 24), (72, 40), (33, 65), (96, 17))):
+    return [inputs.random_mixed(s, nx, ny, nmat=nmat) for s, (nx, ny) in zip(seeds, sizes)]
+
+
+def alone(p, precision, steps=None, t_end=None):
+    g = Solver(p["nx"], p["ny"], p["gammas"], p["domain"], precision=precision,
+               k_eps=1e-6 if precision == LR_FP32 else 1e-10)
+    g.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+    n, t = g.run(t_end if t_end is not None else 1e30, max_steps=steps if steps is not None else 1 << 40)
+    return g, n, t
+
+
+def drain(b):
+    """step until nothing runs; ids in the order they finished"""
+    done = []
+    for _ in range(100000):
+        left = b.step()
+        done += b.poll()
+        if left == 0:
+            break
+    return done + b.poll()
+
+
+def same_fields(a, b, tag):
+    for key in FIELDS:
+        d = np.abs(a[key] - b[key]).max()
+        assert d == 0.0, f"{tag} {key}: batch and alone differ by {d:.3e}"
+
+
+@pytest.mark.parametrize("precision,use_graph,persistent", [
+    (LR_FP64, True, True), (LR_FP64, False, False), (LR_FP32, True, True), (LR_FP32, False, True)])
+def test_batch_equals_alone(precision, use_graph, persistent):
+    ps = problems()
+    steps = [10, 24, 7, 18]  # different lengths: problems leave the launches at different chunks
+    say(f"batch equals alone: precision {precision} graph {use_graph} persistent {persistent}")
+    b = Batch(nmat=2, precision=precision, max_slots=8, pool_bytes=64 << 20, chunk_steps=4,
+              use_graph=use_graph, persistent=persistent)
+    kw = dict(k_eps=1e-6) if precision == LR_FP32 else {}
+    ids = [b.submit(p, 1e30, max_steps=n, **kw) for p, n in zip(ps, steps)]
+    assert all(i is not None for i in ids)
+    done = drain(b)
+    assert sorted(done) == sorted(ids)
+    for p, rid, n in zip(ps, ids, steps):
+        rc, st, t = b.status(rid)
+        assert rc == LR_OK and st == n, (rc, st)
+        g, na, ta = alone(p, precision, steps=n)
+        assert na == n and t == ta
+        same_fields(b.fields(rid, *FIELDS), g.fields(*FIELDS), p["name"])
+        np.testing.assert_array_equal(b.totals(rid), g.totals())
+
+
+def test_batch_member_matches_oracle():
+    p = inputs.random_mixed(21, 50, 30, nmat=3)
+    b = Batch(nmat=3, precision=LR_FP64, max_slots=4, pool_bytes=64 << 20, chunk_steps=6)
+    rid = b.submit(p, 1e30, max_steps=12)
+    drain(b)
+    r = RefSolver(p["nx"], p["ny"], p["gammas"], p["domain"])
+    r.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+    r.run(1e30, max_steps=12)
+    fb, fr = b.fields(rid, "vol", "mass", "ie", "rho", "p"), r.fields("vol", "mass", "ie", "rho", "p")
+    for key in ("vol", "mass", "ie"):
+        scale = np.abs(fr[key]).max()
+        assert np.abs(fb[key] - fr[key]).max() <= 1e-9 * scale, key
+    for key in ("rho", "p"):
+        assert np.abs(fb[key] - fr[key]).sum() / np.abs(fr[key]).sum() <= 1e-10, key
+
+
+def test_batch_t_end_lands_exactly():
+    p = inputs.sod(120, 4)
+    b = Batch(nmat=2, precision=LR_FP64, max_slots=2, pool_bytes=16 << 20, chunk_steps=8)
+    rid = b.submit(p, 0.05)
+    drain(b)
+    rc, st, t = b.status(rid)
+    g, n, ta = alone(p, LR_FP64, t_end=0.05)
+    assert rc == LR_OK and t == 0.05 and ta == 0.05 and st == n
+    same_fields(b.fields(rid, *FIELDS), g.fields(*FIELDS), "sod")
+
+
+def test_continuous_admission_and_release():
+    """Problems join while others run and reuse released slots and ranges;
+    each result equals the problem alone."""
+    ps = problems(seeds=(31, 32, 33, 34, 35, 36),
+                  sizes=((48, 32), (64, 64), (40, 40), (80, 24), (32, 96), (56, 56)))
+    b = Batch(nmat=2, precision=LR_FP32, max_slots=3, pool_bytes=64 << 20, chunk_steps=4)
+    steps = [12, 20, 8, 16, 12, 4]
+    pending = list(range(len(ps)))
+    ids = {}
+    finished = []
+    for _ in range(1000):
+        while pending:
+            k = pending[0]
+            rid = b.submit(ps[k], 1e30, max_steps=steps[k], k_eps=1e-6)
+            if rid is None:
+                break  # three slots taken
+            ids[rid] = k
+            pending.pop(0)
+        b.step()
+        for rid in b.poll():
+            k = ids[rid]
+            g, n, _ = alone(ps[k], LR_FP32, steps=steps[k])
+            same_fields(b.fields(rid, *FIELDS), g.fields(*FIELDS), f"request {k}")
+            b.release(rid)
+            finished.append(k)
+        if not pending and b.running() == 0:
+            break
+    assert sorted(finished) == list(range(len(ps)))
+
+
+def test_pool_full_is_eagain_then_fits_after_release():
+    p = inputs.random_mixed(41, 64, 64)
+    probe = Batch(nmat=2, precision=LR_FP32, max_slots=4, pool_bytes=1 << 20)
+    f = probe.footprint(64, 64)
+    probe.close()
+    b = Batch(nmat=2, precision=LR_FP32, max_slots=4, pool_bytes=f + f // 2, chunk_steps=2)
+    a = b.submit(p, 1e30, max_steps=4, k_eps=1e-6)
+    assert a is not None
+    assert b.submit(p, 1e30, max_steps=4, k_eps=1e-6) is None  # no range large enough
+    b.release(a)
+    c = b.submit(p, 1e30, max_steps=4, k_eps=1e-6)
+    assert c is not None and c != a
+    drain(b)
+    assert b.status(c)[0] == LR_OK
+
+
+def test_batch_rejects_bad_requests():
+    p = inputs.random_mixed(51, 16, 16)
+    b = Batch(nmat=2, precision=LR_FP64, max_slots=2, pool_bytes=16 << 20)
+    q = dict(p)
+    q["k"] = p["k"] * 0.5  # fractions no longer sum to 1
+    with pytest.raises(LRError):
+        b.submit(q, 1.0)
+    with pytest.raises(LRError):
+        b.submit(inputs.random_mixed(52, 16, 16, nmat=3), 1.0)  # nmat differs
+    rid = b.submit(p, 1.0, max_steps=0)  # nothing to do: finished at once
+    assert b.poll() == [rid] and b.status(rid)[0] == LR_OK and b.step() == 0
+    with pytest.raises(LRError):
+        b.status(rid + 100)
+
+
+def test_set_state_device_equals_host():
+    import torch
+    p = inputs.random_mixed(61, 37, 29, nmat=2)
+    a = Solver(p["nx"], p["ny"], p["gammas"], p["domain"])
+    a.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+    d = Solver(p["nx"], p["ny"], p["gammas"], p["domain"])
+    dev = [torch.tensor(np.ascontiguousarray(p[n]), dtype=torch.float64, device="cuda")
+           for n in ("k", "rho", "e", "ux", "uy")]
+    d.set_state_device(0.0, *dev)
+    for s in (a, d):
+        s.run(1e30, max_steps=6)
+    same_fields(d.fields(*FIELDS), a.fields(*FIELDS), "device input")
+    bad = [x.clone() for x in dev]
+    bad[0] *= 0.5
+    with pytest.raises(LRError) as e:
+        d.set_state_device(0.0, *bad)
+    assert e.value.code == -8
+    bad = [x.clone() for x in dev]
+    bad[3][3, 3] = float("nan")
+    with pytest.raises(LRError) as e:
+        d.set_state_device(0.0, *bad)
+    assert e.value.code == -5
+
+
+def test_set_state_device_float32_inputs():
+    """float32 device inputs are widened exactly: the same as the host call
+    with the float-rounded values (pure cells, so the fractions stay exact)."""
+    import torch
+    p = inputs.sod(64, 4)
+    names = ("k", "rho", "e", "ux", "uy")
+    f32 = [torch.tensor(np.ascontiguousarray(p[n]), dtype=torch.float32, device="cuda") for n in names]
+    d = Solver(p["nx"], p["ny"], p["gammas"], p["domain"])
+    d.set_state_device(0.0, *f32)
+    a = Solver(p["nx"], p["ny"], p["gammas"], p["domain"])
+    a.set_state(0.0, *[x.double().cpu().numpy() for x in f32])
+    for s in (a, d):
+        s.run(1e30, max_steps=5)
+    same_fields(d.fields(*FIELDS), a.fields(*FIELDS), "float32 device input")
