@@ -3,16 +3,23 @@
 
 A step is one pass of the whole hot path (CFL time step, staggered
 Lagrangian phase, DirectCF remap with VOF partial fluxes, momentum remap)
-over the grid.  The default workload is the three-material triple point,
-448 x 192 cells, FP64, synthetic initial state (no dataset); the metric is
-cell-updates per second = cells x steps / wall time of the timed steps, with
-the state resident in device memory.
+over the grid.  The headline workload is the three-material triple point,
+448 x 192 cells, FP64, one problem per context ("FP64 plain"), synthetic
+initial state (no dataset); the metric is cell-updates per second = cells x
+steps / wall time of the timed steps, with the state resident in device
+memory.  The same JSON line carries
 
-Prints one JSON line.  The "roofline" object is for the dominant kernel:
-its algorithmic bytes per launch (each array it must read or write touched
-once) over its average duration measured with HIP event pairs on the
-kernel's own stream.  "cpu_baseline" is the FP64 oracle timed on a bounded
-sample of the same workload on the host (one thread).
+  "fp32_batched": 256 seeded two-material shock-bubble problems (grids from
+      64x64 to 512x256) stepped together in FP32 by shared persistent
+      launches replayed from HIP graphs, over a fixed window of steps;
+  "serving": a seeded Poisson stream of four-quadrant Riemann problems
+      (grids 128^2..1024^2, FP32, t_end 0.25) served with continuous
+      batching; p50/p99 latency from arrival to result fields on the host;
+  "roofline": the dominant kernel of the plain step, its algorithmic bytes
+      per launch over its average duration measured with HIP event pairs on
+      the kernel's own stream;
+  "cpu_baseline": the FP64 oracle timed on a bounded sample of the plain
+      workload on the host (one thread).
 """
 import argparse
 import json
@@ -63,6 +70,61 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def batch_leg(n_problems, steps, chunk=8):
+    """FP32 shock-bubble batch: every problem runs one warm-up chunk, then
+    `steps` timed steps (all problems take the same number of steps)."""
+    from paper_2208_13409_amd import inputs
+    from paper_2208_13409_amd.lr import LR_FP32, Batch
+    probs = inputs.shock_bubble_batch(n_problems)
+    steps = max(chunk, (steps // chunk) * chunk)
+    probe = Batch(nmat=2, precision=LR_FP32, max_slots=1, pool_bytes=1 << 20)
+    pool = sum(probe.footprint(p["nx"], p["ny"]) for p in probs) + (64 << 20)
+    probe.close()
+    b = Batch(nmat=2, precision=LR_FP32, max_slots=len(probs), pool_bytes=pool, chunk_steps=chunk,
+              use_graph=True, persistent=True)
+    ids = [b.submit(p, 1e30, max_steps=chunk + steps, k_eps=1e-6) for p in probs]
+    assert all(i is not None for i in ids)
+    b.step()  # warm-up chunk (graph capture)
+    t0 = time.perf_counter()
+    chunks = 0
+    while b.step() > 0:
+        chunks += 1
+    wall = time.perf_counter() - t0
+    chunks += 1
+    for rid in ids:
+        rc, st, _ = b.status(rid)
+        assert rc == 0 and st == chunk + steps, (rid, rc, st)
+    cells = sum(p["nx"] * p["ny"] for p in probs)
+    value = cells * steps / wall
+    bpc = step_bytes(1, 1, 2, 4)
+    b.close()
+    return {"value": value, "unit": "cell-updates/s", "dtype": "f32",
+            "workload": f"shock_bubble_batch_{len(probs)}", "problems": len(probs), "cells": cells,
+            "steps": steps, "ms_per_step": wall * 1e3 / steps, "chunks": chunks,
+            "launch": "persistent grids, one HIP graph per chunk of "
+                      f"{chunk} steps, all problems in each launch",
+            "hbm_bytes_per_cell_update": bpc, "achieved_GBs": value * bpc / 1e9,
+            "frac_hbm": value * bpc / 1e9 / HBM_PEAK_GBS}
+
+
+def serve_leg(n_requests, rate):
+    from paper_2208_13409_amd import inputs
+    from paper_2208_13409_amd.lr import LR_FP32, Batch
+    from paper_2208_13409_amd.serve import serve
+    reqs = [inputs.four_quadrant(inputs.BASE_SEED + i) for i in range(n_requests)]
+    arrivals = inputs.poisson_arrivals(n_requests, rate=rate)
+    b = Batch(nmat=2, precision=LR_FP32, max_slots=64, pool_bytes=16 << 30, chunk_steps=8)
+    out = serve(b, reqs, arrivals)
+    b.close()
+    served = sum(c * s for c, s in zip(out["cells"], out["steps"]))
+    assert all(rc == 0 for rc in out["rc"])
+    return {"p50_s": out["p50"], "p99_s": out["p99"], "requests": n_requests, "rate_per_s": rate,
+            "cell_updates_per_s": out["cell_updates_per_s"], "wall_s": out["wall"],
+            "gpu_busy": out["busy"], "max_running": out["max_running"],
+            "offered_cell_updates_per_s": served / float(arrivals[-1]),
+            "workload": f"four_quadrant stream, first {n_requests} requests, FP32"}
+
+
 def cpu_baseline(p, steps):
     from oracle import RefSolver
     r = RefSolver(p["nx"], p["ny"], p["gammas"], p["domain"])
@@ -87,6 +149,12 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--batch-problems", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 8 device-to-device copies of MIB MiB (the reference kernel "
                          "that scales the HBM byte counters) and exit")
@@ -147,7 +215,7 @@ def main():
     step_us = sum(avg_us.values())
     value = cells * n / wall
     out = {
-        "metric": f"cell-updates/s per step ({args.precision.upper()} plain, 1 GPU)",
+        "metric": "cell-updates/s per step (FP32 batched vs FP64 plain, 1 GPU); p50/p99 solve latency",
         "value": value,
         "unit": "cell-updates/s",
         "n_gpus": 1,
@@ -171,6 +239,11 @@ def main():
                           "sum_kernel_us": step_us},
         "kernels_avg_us": avg_us,
     }
+    if not args.no_batch:
+        out["fp32_batched"] = batch_leg(args.batch_problems, args.batch_steps)
+        out["fp32_batched"]["vs_fp64_plain"] = out["fp32_batched"]["value"] / value
+    if not args.no_serve:
+        out["serving"] = serve_leg(args.serve_requests, args.serve_rate)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
     print(json.dumps(out), flush=True)

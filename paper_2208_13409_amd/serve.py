@@ -1,0 +1,82 @@
+"""Request loop serving many solves on one GPU with continuous batching.
+
+Requests arrive over time.  Each is admitted into a ``Batch`` as soon as a
+slot and a range of its device pool are free (admission by device-memory
+footprint: ``submit`` declines while the request does not fit).  It then
+runs in the shared launches with whatever else is running, and its result
+fields are copied to the host when it finishes, after which its slot and
+memory are released for the next one.  Latency is measured from a
+request's arrival to its fields being on the host.
+"""
+import collections
+import time
+
+import numpy as np
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=float), q)) if len(xs) else float("nan")
+
+
+def serve(batch, requests, arrivals, fields=("rho", "p"), keep=False):
+    """Serve ``requests`` (problem dicts with ``t_end``) arriving at
+    ``arrivals`` seconds after the start, in real time.
+
+    Returns a dict: per-request latency, steps and cells, the fields when
+    ``keep``, the wall time, the cell-updates served per second, the share of
+    the wall time spent stepping, and p50/p99 latency."""
+    n = len(requests)
+    order = sorted(range(n), key=lambda i: arrivals[i])
+    lat, steps, rcs = [None] * n, [0] * n, [None] * n
+    results = {}
+    queue = collections.deque()
+    ids = {}
+    nxt, done = 0, 0
+    busy = 0.0
+    max_running = 0
+    t0 = time.perf_counter()
+
+    def clock():
+        return time.perf_counter() - t0
+
+    while done < n:
+        now = clock()
+        while nxt < n and arrivals[order[nxt]] <= now:
+            queue.append(order[nxt])
+            nxt += 1
+        while queue:
+            i = queue[0]
+            rid = batch.submit(requests[i], requests[i]["t_end"])
+            if rid is None:
+                if batch.running() == 0 and not ids:
+                    raise RuntimeError(f"request {i} does not fit in an empty batch")
+                break
+            ids[rid] = i
+            queue.popleft()
+        running = batch.running()
+        max_running = max(max_running, running)
+        if running == 0 and not ids:
+            if nxt < n:  # idle until the next arrival
+                time.sleep(max(0.0, arrivals[order[nxt]] - clock()))
+            continue
+        tb = clock()
+        if running:
+            batch.step()
+        busy += clock() - tb
+        for rid in batch.poll():
+            i = ids.pop(rid)
+            rc, st, _ = batch.status(rid)
+            rcs[i], steps[i] = rc, st
+            out = batch.fields(rid, *fields) if rc == 0 else None
+            lat[i] = clock() - arrivals[i]
+            if keep:
+                results[i] = out
+            batch.release(rid)
+            done += 1
+    wall = clock()
+    cells = [r["nx"] * r["ny"] for r in requests]
+    served = float(sum(c * s for c, s in zip(cells, steps)))
+    return dict(latency=lat, steps=steps, rc=rcs, cells=cells, wall=wall,
+                cell_updates_per_s=served / wall if wall > 0 else float("nan"),
+                busy=busy / wall if wall > 0 else float("nan"), max_running=max_running,
+                p50=percentile(lat, 50), p99=percentile(lat, 99), results=results)
