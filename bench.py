@@ -10,8 +10,9 @@ steps / wall time of the timed steps, with the state resident in device
 memory.  The same JSON line carries
 
   "fp32_batched": 256 seeded two-material shock-bubble problems (grids from
-      64x64 to 512x256) stepped together in FP32 by shared persistent
-      launches replayed from HIP graphs, over a fixed window of steps;
+      64x64 to 512x256) stepped together in FP32, every launch covering the
+      tiles of all problems, each chunk of steps replayed from a HIP graph,
+      over a fixed window of steps;
   "serving": a seeded Poisson stream of four-quadrant Riemann problems
       (grids 128^2..1024^2, FP32, t_end 0.25) served with continuous
       batching; p50/p99 latency from arrival to result fields on the host;
@@ -81,7 +82,7 @@ def batch_leg(n_problems, steps, chunk=8):
     pool = sum(probe.footprint(p["nx"], p["ny"]) for p in probs) + (64 << 20)
     probe.close()
     b = Batch(nmat=2, precision=LR_FP32, max_slots=len(probs), pool_bytes=pool, chunk_steps=chunk,
-              use_graph=True, persistent=True)
+              use_graph=True, persistent=False)
     ids = [b.submit(p, 1e30, max_steps=chunk + steps, k_eps=1e-6) for p in probs]
     assert all(i is not None for i in ids)
     b.step()  # warm-up chunk (graph capture)
@@ -101,8 +102,8 @@ def batch_leg(n_problems, steps, chunk=8):
     return {"value": value, "unit": "cell-updates/s", "dtype": "f32",
             "workload": f"shock_bubble_batch_{len(probs)}", "problems": len(probs), "cells": cells,
             "steps": steps, "ms_per_step": wall * 1e3 / steps, "chunks": chunks,
-            "launch": "persistent grids, one HIP graph per chunk of "
-                      f"{chunk} steps, all problems in each launch",
+            "launch": "one block per tile of every problem in each launch, one HIP graph "
+                      f"per chunk of {chunk} steps",
             "hbm_bytes_per_cell_update": bpc, "achieved_GBs": value * bpc / 1e9,
             "frac_hbm": value * bpc / 1e9 / HBM_PEAK_GBS}
 

@@ -149,8 +149,7 @@ const char *lr_kernel_name(int i);
 /* ------------------------------------------------------------------ batch
  * Many independent problems of different grid sizes stepped together: each
  * kernel of a step is one launch over the tiles of every running problem of
- * the batch (a grid no larger than the device holds at once, each block
- * walking the tile list), optionally replayed from a HIP graph.  Problems
+ * the batch, optionally replayed from a HIP graph.  Problems
  * are admitted while others run (continuous batching): a submitted problem
  * takes a free slot and a range of the batch's device pool, starts with the
  * next chunk of steps and leaves the launches when it finishes; its state
@@ -165,7 +164,8 @@ typedef struct {
   int precision;        /* LR_FP64 or LR_FP32                                     */
   int chunk_steps;      /* steps per lr_batch_step (even, >= 2); default 16      */
   int use_graph;        /* 1: replay each chunk from a captured HIP graph        */
-  int persistent;       /* 1: grids limited to the blocks resident on the device */
+  int persistent;       /* 1: grids limited to the blocks resident on the device, each
+                           block walking the tile list; 0 (default): one block per tile */
 } lr_batch_opts;
 typedef struct lr_batch lr_batch;
 

@@ -266,7 +266,7 @@ void lr_batch_default_opts(lr_batch_opts *o) {
   o->precision = LR_FP32;
   o->chunk_steps = kChunk;
   o->use_graph = 1;
-  o->persistent = 1;
+  o->persistent = 0;
 }
 
 void lr_batch_destroy(lr_batch *b) {

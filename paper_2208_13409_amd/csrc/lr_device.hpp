@@ -93,6 +93,21 @@ __device__ __forceinline__ void stg(T *p, T v) {
   *(__attribute__((address_space(1))) T *)p = v;
 }
 
+// ---------------------------------------------------------------- arithmetic
+// Quotient in the bulk precision: IEEE division in FP64; in FP32 the
+// hardware reciprocal (1 ulp) times the numerator, within 2 ulp of the
+// rounded quotient, instead of the ten-instruction correctly rounded
+// sequence.  The FP64 islands keep IEEE division, and so do quotients by a
+// value that may be a float denormal (the reciprocal would overflow).
+template <typename R>
+__device__ __forceinline__ R qdiv(R a, R b) {
+  return a / b;
+}
+template <>
+__device__ __forceinline__ float qdiv<float>(float a, float b) {
+  return a * __builtin_amdgcn_rcpf(b);
+}
+
 // ---------------------------------------------------------------- indexing
 __device__ __forceinline__ int refl_cell(int i, int n) {
   return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i);
@@ -106,7 +121,7 @@ __device__ __forceinline__ int refl_node(int I, int n) {
 // 2 dm dp / (dm + dp); otherwise 0 (the limiter of §2.1.1 written out).
 template <typename R>
 __device__ __forceinline__ R van_leer(R dm, R dp) {
-  return (dm * dp > R(0)) ? R(2) * dm * dp / (dm + dp) : R(0);
+  return (dm * dp > R(0)) ? qdiv(R(2) * dm * dp, dm + dp) : R(0);
 }
 
 // ---------------------------------------------------------------- geometry
@@ -154,7 +169,7 @@ __device__ __forceinline__ FaceGeo<R> face_geo(R da_n, R da_t, R db_n, R db_t, R
   const R thi = D + fmin(R(0), db_t);
   R h = thi - tlo;
   if (h < R(0)) h = R(0);
-  const R slope = (db_n - da_n) / ((D + db_t) - da_t);
+  const R slope = qdiv(db_n - da_n, (D + db_t) - da_t);
   const R nlo = da_n + (tlo - da_t) * slope;
   const R nhi = da_n + (thi - da_t) * slope;
   FaceGeo<R> g;

@@ -296,11 +296,12 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
       for (int m = 0; m < NM; ++m) {
         const R V = ldg(Vs + (m * C + q)), M = ldg(Ms + (m * C + q)), E = ldg(Es + (m * C + q));
         Mm[m] = M;
-        k[m] = V / A;
+        k[m] = qdiv(V, A);
         pr[m] = present(g, V);
         np += pr[m];
+        // an absent material's mass can be a float denormal: IEEE quotient
         e[m] = M > R(0) ? E / M : R(0);
-        rho[m] = pr[m] ? M / V : R(0);
+        rho[m] = pr[m] ? qdiv(M, V) : R(0);
         Pa[m] = pr[m] ? R(g.gamma[m] - 1.0) * rho[m] * e[m] : R(0);
         if (pr[m]) rc2 += k[m] * R(g.gamma[m]) * Pa[m];
         Msum += M;
@@ -308,11 +309,11 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
       mixed_owned = owned && np >= 2;
       R Qc = R(0), Sc = R(0);
       if (!g.kinematic) {
-        const R rhoc = Msum / A;
-        const R c2 = rhoc > R(0) ? rc2 / rhoc : R(0);
+        const R rhoc = qdiv(Msum, A);
+        const R c2 = rhoc > R(0) ? qdiv(rc2, rhoc) : R(0);
         const R cc = c2 > R(0) ? sqrt(c2) : R(0);
-        const R div = (ldg(P.ux + br) + ldg(P.ux + tr) - ldg(P.ux + bl) - ldg(P.ux + tl)) / (R(2) * Dx) +
-                      (ldg(P.uy + tl) + ldg(P.uy + tr) - ldg(P.uy + bl) - ldg(P.uy + br)) / (R(2) * Dy);
+        const R div = qdiv(ldg(P.ux + br) + ldg(P.ux + tr) - ldg(P.ux + bl) - ldg(P.ux + tl), R(2) * Dx) +
+                      qdiv(ldg(P.uy + tl) + ldg(P.uy + tr) - ldg(P.uy + bl) - ldg(P.uy + br), R(2) * Dy);
         const R L = sqrt(A);
         if (div < R(0)) Qc = rhoc * (R(g.a1) * L * cc * fabs(div) + R(g.a2) * L * L * div * div);
         const R h = R(0.5) * dt;
@@ -340,8 +341,8 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
           for (int m = 0; m < NM; ++m) {
             R Ph = R(0);
             if (pr[m]) {
-              const R e_h = e[m] - (Pa[m] + Qc) * (k[m] * dV / Mm[m]);
-              const R rho_h = Mm[m] / (k[m] * (A + dV));
+              const R e_h = e[m] - (Pa[m] + Qc) * qdiv(k[m] * dV, Mm[m]);
+              const R rho_h = qdiv(Mm[m], k[m] * (A + dV));
               Ph = R(g.gamma[m] - 1.0) * rho_h * e_h;
               Pch += k[m] * Ph;
             }
@@ -381,11 +382,11 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
       uhy = uLy = uy;
     } else {
       const R sSW = sS[b][a], sSE = sS[b][a + 1], sNW = sS[b + 1][a], sNE = sS[b + 1][a + 1];
-      const R gx = ((sSE + sNE) - (sSW + sNW)) / (R(2) * Dx);
-      const R gy = ((sNW + sNE) - (sSW + sSE)) / (R(2) * Dy);
-      const R rho_p = mp / A;
-      uhx = ux - R(0.5) * dt * gx / rho_p;
-      uhy = uy - R(0.5) * dt * gy / rho_p;
+      const R gx = qdiv((sSE + sNE) - (sSW + sNW), R(2) * Dx);
+      const R gy = qdiv((sNW + sNE) - (sSW + sSE), R(2) * Dy);
+      const R rho_p = qdiv(mp, A);
+      uhx = ux - qdiv(R(0.5) * dt * gx, rho_p);
+      uhy = uy - qdiv(R(0.5) * dt * gy, rho_p);
       if (I == 0 || I == nx) uhx = R(0);
       if (J == 0 || J == ny) uhy = R(0);
       uLx = R(2) * uhx - ux;
@@ -422,16 +423,16 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
         const R V = ldg(Vs + (m * C + q)), M = ldg(Ms + (m * C + q)), E = ldg(Es + (m * C + q));
-        const R e = M > R(0) ? E / M : R(0);
+        const R e = M > R(0) ? E / M : R(0);  // M may be a denormal trace: IEEE quotient
         R eL = e;
         if (!g.kinematic && present(g, V)) {
-          const R k = V / A;
+          const R k = qdiv(V, A);
           const R Ph = sPh[m][b + 1][a + 1];
           if constexpr (sizeof(R) == 8) {
             const R rho = M / V, rhoL = M / (k * VL);
             eL = e - (Ph + Qc) * (R(1) / rhoL - R(1) / rho);
           } else {
-            eL = e - (Ph + Qc) * (k * dVL / M);
+            eL = e - (Ph + Qc) * qdiv(k * dVL, M);
           }
         }
         stg(P.eL + (m * C + q), eL);
@@ -462,13 +463,19 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
   }
 }
 
-// one block per tile of the map; a grid smaller than the map walks it
-template <typename R, int NM>
+// one block per tile of the map (LOOP false: grid = map), or a grid smaller
+// than the map whose blocks walk it (LOOP true; a separate instantiation,
+// since the loop keeps values live across tiles and costs registers)
+template <typename R, int NM, bool LOOP>
 __global__ void __launch_bounds__(NTHREADS) k_lagrange(const Prob<R> *probs, const BlockMap *map,
                                                   int nmap, int gpar) {
-  for (int b = blockIdx.x; b < nmap; b += gridDim.x) {
-    lagrange_tile<R, NM>(probs, map[b], gpar);
-    __syncthreads();  // the next tile reuses the LDS
+  if constexpr (LOOP) {
+    for (int b = blockIdx.x; b < nmap; b += gridDim.x) {
+      lagrange_tile<R, NM>(probs, map[b], gpar);
+      __syncthreads();  // the next tile reuses the LDS
+    }
+  } else {
+    if (blockIdx.x < nmap) lagrange_tile<R, NM>(probs, map[blockIdx.x], gpar);
   }
 }
 
@@ -577,7 +584,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
         ++np;
         pm = m;
       }
-      sh.rcf[m][b][a] = pr ? M / ((V / A) * v) : R(0);
+      sh.rcf[m][b][a] = pr ? qdiv(M, qdiv(V, A) * v) : R(0);
       sh.el[m][b][a] = ldg(P.eL + (m * C + q));
     }
     sh.pure[b][a] = np == 1 ? pm : -1;
@@ -695,8 +702,9 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
               rm = sh.rcf[m][bmn][am]; rp = sh.rcf[m][bp][ap];
               em = sh.el[m][bmn][am]; ep = sh.el[m][bp][ap];
             }
-          vr[s] = rD + R(0.5) * van_leer((rD - rm) / lm, (rp - rD) / lp) * off;
-          ve[s] = eD + R(0.5) * van_leer((eD - em) / lm, (ep - eD) / lp) * off;
+          const R ilm = qdiv(R(1), lm), ilp = qdiv(R(1), lp);
+          vr[s] = rD + R(0.5) * van_leer((rD - rm) * ilm, (rp - rD) * ilp) * off;
+          ve[s] = eD + R(0.5) * van_leer((eD - em) * ilm, (ep - eD) * ilp) * off;
         }
         R Ws = R(0);
 #pragma unroll
@@ -772,7 +780,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       for (int m = 0; m < NM; ++m) {
         const R M0 = ldg(Ms + (m * C + q));
         Acc<R> V, M, E;
-        V.init((ldg(Vs + (m * C + q)) / A) * v);
+        V.init(qdiv(ldg(Vs + (m * C + q)), A) * v);
         M.init(M0);
         E.init(M0 * sh.el[m][cb][ca]);
 #pragma unroll
@@ -801,17 +809,17 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
         const R tol = R(-g.neg_tol);
         if (Vn[m] < tol * A || Mn[m] < tol * Msa || En[m] < tol * Esa) bad_neg = true;
         if (present(g, Vn[m])) {
-          const R rho = Mn[m] / Vn[m];
-          const R e = Mn[m] > R(0) ? En[m] / Mn[m] : R(0);
+          const R rho = qdiv(Mn[m], Vn[m]);
+          const R e = Mn[m] > R(0) ? qdiv(En[m], Mn[m]) : R(0);
           const R Pm = R(g.gamma[m] - 1.0) * rho * e;
-          rc2 += (Vn[m] / A) * R(g.gamma[m]) * Pm;
+          rc2 += qdiv(Vn[m], A) * R(g.gamma[m]) * Pm;
         }
         Msum += Mn[m];
       }
       if (bad_nan) atomicOr(&ctl->err, ERR_NAN);
       else if (bad_neg) atomicOr(&ctl->err, ERR_NEG);
-      const R rhoc = Msum / A;
-      const R c2 = rhoc > R(0) ? rc2 / rhoc : R(0);
+      const R rhoc = qdiv(Msum, A);
+      const R c2 = rhoc > R(0) ? qdiv(rc2, rhoc) : R(0);
       stg(P.cs + q, c2 > R(0) ? sqrt(c2) : R(0));
       // total mass flux of the regions this cell owns (left face, bottom face,
       // bottom-left corner) for the momentum remap; walls are zero
@@ -837,13 +845,19 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   }
 }
 
-// one block per tile of the map; a grid smaller than the map walks it
-template <typename R, int NM>
+// one block per tile of the map (LOOP false: grid = map), or a grid smaller
+// than the map whose blocks walk it (LOOP true; a separate instantiation,
+// since the loop keeps values live across tiles and costs registers)
+template <typename R, int NM, bool LOOP>
 __global__ void __launch_bounds__(NTHREADS) k_remap(const Prob<R> *probs, const BlockMap *map,
                                                   int nmap, int gpar) {
-  for (int b = blockIdx.x; b < nmap; b += gridDim.x) {
-    remap_tile<R, NM>(probs, map[b], gpar);
-    __syncthreads();  // the next tile reuses the LDS
+  if constexpr (LOOP) {
+    for (int b = blockIdx.x; b < nmap; b += gridDim.x) {
+      remap_tile<R, NM>(probs, map[b], gpar);
+      __syncthreads();  // the next tile reuses the LDS
+    }
+  } else {
+    if (blockIdx.x < nmap) remap_tile<R, NM>(probs, map[blockIdx.x], gpar);
   }
 }
 
@@ -933,8 +947,9 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
       const int ma = la - sa, mb = lb - sb, pa = la + sa, pb = lb + sb;
       const R lm = (sh.X[lb][la] - sh.X[mb][ma]) * vx + (sh.Y[lb][la] - sh.Y[mb][ma]) * vy;
       const R lp = (sh.X[pb][pa] - sh.X[lb][la]) * vx + (sh.Y[pb][pa] - sh.Y[lb][la]) * vy;
-      const R su = van_leer((u - sh.ulx[mb][ma]) / lm, (sh.ulx[pb][pa] - u) / lp);
-      const R sv = van_leer((v - sh.uly[mb][ma]) / lm, (sh.uly[pb][pa] - v) / lp);
+      const R ilm = qdiv(R(1), lm), ilp = qdiv(R(1), lp);
+      const R su = van_leer((u - sh.ulx[mb][ma]) * ilm, (sh.ulx[pb][pa] - u) * ilp);
+      const R sv = van_leer((v - sh.uly[mb][ma]) * ilm, (sh.uly[pb][pa] - v) * ilp);
       u += su * off;
       v += sv * off;
     };
@@ -1060,8 +1075,8 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
         m += sh.fa[0][hNW]; mu += sh.fa[1][hNW]; mv += sh.fa[2][hNW];
         m -= sh.fa[0][hSE]; mu -= sh.fa[1][hSE]; mv -= sh.fa[2][hSE];
         if (!(m > R(0))) atomicOr(&ctl->err, ERR_NODEMASS);
-        ux = mu / m;
-        uy = mv / m;
+        ux = qdiv(mu, m);
+        uy = qdiv(mv, m);
         if (I == 0 || I == nx) ux = R(0);
         if (J == 0 || J == ny) uy = R(0);
         if (!isfinite(ux) || !isfinite(uy)) atomicOr(&ctl->err, ERR_NAN);
@@ -1085,13 +1100,19 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
   block_min_to_slot(cand, ctl->slot[par ^ 1]);
 }
 
-// one block per tile of the map; a grid smaller than the map walks it
-template <typename R, int NM>
+// one block per tile of the map (LOOP false: grid = map), or a grid smaller
+// than the map whose blocks walk it (LOOP true; a separate instantiation,
+// since the loop keeps values live across tiles and costs registers)
+template <typename R, int NM, bool LOOP>
 __global__ void __launch_bounds__(NTHREADS) k_dual(const Prob<R> *probs, const BlockMap *map,
                                                   int nmap, int gpar) {
-  for (int b = blockIdx.x; b < nmap; b += gridDim.x) {
-    dual_tile<R, NM>(probs, map[b], gpar);
-    __syncthreads();  // the next tile reuses the LDS
+  if constexpr (LOOP) {
+    for (int b = blockIdx.x; b < nmap; b += gridDim.x) {
+      dual_tile<R, NM>(probs, map[b], gpar);
+      __syncthreads();  // the next tile reuses the LDS
+    }
+  } else {
+    if (blockIdx.x < nmap) dual_tile<R, NM>(probs, map[blockIdx.x], gpar);
   }
 }
 
@@ -1321,9 +1342,9 @@ struct Resident {  // blocks of each step kernel resident on the whole device
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return;
-    const void *fn[kKernels] = {reinterpret_cast<const void *>(&k_lagrange<R, NM>),
-                                reinterpret_cast<const void *>(&k_remap<R, NM>),
-                                reinterpret_cast<const void *>(&k_dual<R, NM>)};
+    const void *fn[kKernels] = {reinterpret_cast<const void *>(&k_lagrange<R, NM, true>),
+                                reinterpret_cast<const void *>(&k_remap<R, NM, true>),
+                                reinterpret_cast<const void *>(&k_dual<R, NM, true>)};
     for (int k = 0; k < kKernels; ++k) {
       int per = 0;
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn[k], NTHREADS, 0) == hipSuccess)
@@ -1356,12 +1377,22 @@ void step_impl(const Launch &L, int gpar, hipStream_t s, hipEvent_t *ev) {
   auto mark = [&](int k) {
     if (ev) (void)hipEventRecord(ev[k], s);
   };
+  const bool loop = L.persistent && res.n[0] > 0 && res.n[1] > 0 && res.n[2] > 0;
   mark(0);
-  k_lagrange<R, NM><<<grid(0, L.node_blocks), NTHREADS, 0, s>>>(p, L.node_map, L.node_blocks, gpar);
+  if (loop)
+    k_lagrange<R, NM, true><<<grid(0, L.node_blocks), NTHREADS, 0, s>>>(p, L.node_map, L.node_blocks, gpar);
+  else
+    k_lagrange<R, NM, false><<<L.node_blocks, NTHREADS, 0, s>>>(p, L.node_map, L.node_blocks, gpar);
   mark(1);
-  k_remap<R, NM><<<grid(1, L.cell_blocks), NTHREADS, 0, s>>>(p, L.cell_map, L.cell_blocks, gpar);
+  if (loop)
+    k_remap<R, NM, true><<<grid(1, L.cell_blocks), NTHREADS, 0, s>>>(p, L.cell_map, L.cell_blocks, gpar);
+  else
+    k_remap<R, NM, false><<<L.cell_blocks, NTHREADS, 0, s>>>(p, L.cell_map, L.cell_blocks, gpar);
   mark(2);
-  k_dual<R, NM><<<grid(2, L.node_blocks), NTHREADS, 0, s>>>(p, L.node_map, L.node_blocks, gpar);
+  if (loop)
+    k_dual<R, NM, true><<<grid(2, L.node_blocks), NTHREADS, 0, s>>>(p, L.node_map, L.node_blocks, gpar);
+  else
+    k_dual<R, NM, false><<<L.node_blocks, NTHREADS, 0, s>>>(p, L.node_map, L.node_blocks, gpar);
   mark(3);
 }
 using StepFn = void (*)(const Launch &, int, hipStream_t, hipEvent_t *);

@@ -276,7 +276,7 @@ class Batch:
     no room now (LR_EAGAIN)."""
 
     def __init__(self, nmat=2, precision=LR_FP32, max_slots=256, pool_bytes=4 << 30,
-                 chunk_steps=16, use_graph=True, persistent=True, stream=None):
+                 chunk_steps=16, use_graph=True, persistent=False, stream=None):
         self.lib = load()
         o = lr_batch_default_opts()
         o.max_slots, o.pool_bytes, o.nmat, o.precision = int(max_slots), int(pool_bytes), int(nmat), int(precision)
