@@ -480,17 +480,52 @@ __global__ void __launch_bounds__(NTHREADS) k_lagrange(const Prob<R> *probs, con
 }
 
 // =========================================================== k_remap
+// Region-centred: every flux region the tile needs is formed once.
+//   P1 node displacements d = dt u^{n+1/2} (2-deep halo, mirrored)
+//   P2 signed volume of every x- and y-face region (the sign bit gives the
+//      donor side: clear = the donor is on the -x / -y side)
+//   P3 cell records (2-deep halo): Vol^{lagCF} from the region volumes,
+//      rho^{lagCF}_a, e^{lag}_a, Lagrangian centre and widths, purity
+//   P4 order-2 values (rho, e) of each region whose donor is pure, in the
+//      donor's frame (§2.1.1, §3.3; order 1 next to another material, §4.2)
+//   P5 positivity guard per donor: its order-2 outflow mass and energy
+//   P6 nine-point update of the owned cells, the fluxes formed from the
+//      donor's record, the region values and, for mixed donors, the FP64
+//      partial volumes (§4.4)
 template <typename R, int NM>
 struct RemapShared {
   static constexpr int NNX = TX + 5, NNY = TY + 5;  // nodes [i0-2, i0+TX+2]
   static constexpr int NCX = TX + 4, NCY = TY + 4;  // cell records [i0-2, i0+TX+1]
-  static constexpr int NXF = (TX + 1) * TY, NYF = TX * (TY + 1), NCN = (TX + 1) * (TY + 1);
+  // face volumes: x-faces [i0-2, i0+TX+2] x rows [j0-2, j0+TY+1], y-faces
+  // [i0-2, i0+TX+1] x [j0-2, j0+TY+2]
+  static constexpr int XW = TX + 5, XH = TY + 4, YW = TX + 4, YH = TY + 5;
+  // region values for donors in [i0-1, i0+TX] x [j0-1, j0+TY]: x-faces
+  // [i0-1, i0+TX+1] x [j0-1, j0+TY], y-faces [i0-1, i0+TX] x [j0-1, j0+TY+1],
+  // corners at nodes [i0-1, i0+TX+1] x [j0-1, j0+TY+1]
+  static constexpr int VXW = TX + 3, VXH = TY + 2, VYW = TX + 2, VYH = TY + 3;
+  static constexpr int VCW = TX + 3, VCH = TY + 3;
+  static constexpr int NV = VXW * VXH + VYW * VYH + VCW * VCH;
   R ndx[NNY][NNX], ndy[NNY][NNX];
+  R xv[XH][XW], yv[YH][YW];
   R vcf[NCY][NCX], xc[NCY][NCX], yc[NCY][NCX], wx[NCY][NCX], wy[NCY][NCX];
-  int pure[NCY][NCX];
+  int pure[NCY][NCX];  // material of a pure cell, -1 mixed; +16 once P5 keeps order 2
   R rcf[NM][NCY][NCX], el[NM][NCY][NCX];
-  R fx[3 * NM][NXF], fy[3 * NM][NYF], fc[3 * NM][NCN];
+  R vr[NV], ve[NV];  // x-faces, then y-faces, then corners
 };
+
+// the donor-frame region s (W, E, S, N, BL, BR, TL, TR) of region `kind`
+// (0 x-face, 1 y-face, 2 corner) at (I, J), its donor cell and its index in
+// the region-value arrays; `neg` is the sign bit of the signed volume (faces)
+// or of the node's x-displacement (corners)
+struct RegionRef {
+  int di, dj, s;
+};
+__device__ __forceinline__ RegionRef region_donor(int kind, int I, int J, bool neg, bool mainc) {
+  if (kind == 0) return neg ? RegionRef{I, J, 0} : RegionRef{I - 1, J, 1};
+  if (kind == 1) return neg ? RegionRef{I, J, 2} : RegionRef{I, J - 1, 3};
+  if (mainc) return neg ? RegionRef{I, J, 4} : RegionRef{I - 1, J - 1, 7};
+  return neg ? RegionRef{I, J - 1, 6} : RegionRef{I - 1, J, 5};
+}
 
 template <typename R, int NM>
 __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap bm, int gpar) {
@@ -530,7 +565,11 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
     if (!(dtd > 0.0) || !isfinite(dtd)) atomicOr(&ctl->err, ERR_DT);
   }
 
-  // ---- stage 1: node displacements d = dt u^{n+1/2}, mirrored at walls
+  // local indices: nodes and x-faces from (i0-2, j0-2), records likewise
+  auto NA = [&](int I) { return I - (i0 - 2); };
+  auto NB = [&](int J) { return J - (j0 - 2); };
+
+  // ---- P1: node displacements d = dt u^{n+1/2}, mirrored at walls
   for (int l = tid; l < SH::NNX * SH::NNY; l += NTHREADS) {
     const int a = l % SH::NNX, b = l / SH::NNX;
     const int I = i0 - 2 + a, J = j0 - 2 + b;
@@ -544,25 +583,60 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   }
   __syncthreads();
 
-  // ---- stage 2: cell records (flux-consistent Lagrangian volume and density,
-  // Lagrangian centre and widths, purity); ghost cells mirror the real ones
+  // ---- P2: signed face volumes (real faces only: ghost records use the
+  // real cell's faces)
+  for (int l = tid; l < SH::XW * SH::XH + SH::YW * SH::YH; l += NTHREADS) {
+    if (l < SH::XW * SH::XH) {
+      const int a = l % SH::XW, b = l / SH::XW;
+      const int I = i0 - 2 + a, j = j0 - 2 + b;
+      if (I < 0 || I > nx || j < 0 || j >= ny) continue;
+      const FaceGeo<R> f = face_geo(sh.ndx[b][a], sh.ndy[b][a], sh.ndx[b + 1][a], sh.ndy[b + 1][a], Dy);
+      const R v = fabs(f.w * f.h);
+      sh.xv[b][a] = f.w >= R(0) ? v : -v;
+    } else {
+      const int k = l - SH::XW * SH::XH;
+      const int a = k % SH::YW, b = k / SH::YW;
+      const int i = i0 - 2 + a, J = j0 - 2 + b;
+      if (i < 0 || i >= nx || J < 0 || J > ny) continue;
+      const FaceGeo<R> f = face_geo(sh.ndy[b][a], sh.ndx[b][a], sh.ndy[b][a + 1], sh.ndx[b][a + 1], Dx);
+      const R v = fabs(f.w * f.h);
+      sh.yv[b][a] = f.w >= R(0) ? v : -v;
+    }
+  }
+  __syncthreads();
+
+  // ---- P3: cell records; ghost cells mirror the real ones
   for (int l = tid; l < SH::NCX * SH::NCY; l += NTHREADS) {
     const int a = l % SH::NCX, b = l / SH::NCX;
     const int i = i0 - 2 + a, j = j0 - 2 + b;
     if (i > nx + 1 || j > ny + 1) continue;
     const int ri = refl_cell(i, nx), rj = refl_cell(j, ny), q = rj * nx + ri;
-    const int na = ri - (i0 - 2), nb = rj - (j0 - 2);  // local node of the real cell's BL node
+    const int na = NA(ri), nb = NB(rj);  // local node of the real cell's BL node
     const R blx = sh.ndx[nb][na], bly = sh.ndy[nb][na], brx = sh.ndx[nb][na + 1],
             bry = sh.ndy[nb][na + 1];
     const R tlx = sh.ndx[nb + 1][na], tly = sh.ndy[nb + 1][na], trx = sh.ndx[nb + 1][na + 1],
             try_ = sh.ndy[nb + 1][na + 1];
-    CellRegions<R> r;
-    cell_regions(Dx, Dy, blx, bly, brx, bry, tlx, tly, trx, try_, r);
+    // Vol^{lagCF} = A + outflow - inflow over W, E, S, N, BL, BR, TL, TR
     R v = A;
+    {
+      const R xw = sh.xv[nb][na], xe = sh.xv[nb][na + 1], ys = sh.yv[nb][na], yn = sh.yv[nb + 1][na];
+      if (signbit(xw)) v += fabs(xw); else v -= fabs(xw);
+      if (!signbit(xe)) v += fabs(xe); else v -= fabs(xe);
+      if (signbit(ys)) v += fabs(ys); else v -= fabs(ys);
+      if (!signbit(yn)) v += fabs(yn); else v -= fabs(yn);
+      const R cx[4] = {blx, brx, tlx, trx}, cy[4] = {bly, bry, tly, try_};
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      if (r.role[s] > 0) v += r.vol[s];
-      else if (r.role[s] < 0) v -= r.vol[s];
+      for (int c = 0; c < 4; ++c) {
+        const bool sx = cx[c] >= R(0), sy = cy[c] >= R(0);
+        const R vol = fabs(cx[c] * cy[c]);
+        int role;
+        if (c == 0) role = (sx == sy) ? (sx ? -1 : 1) : 0;       // cell is NE of its BL node
+        else if (c == 1) role = (sx != sy) ? (sx ? 1 : -1) : 0;  // NW of its BR node
+        else if (c == 2) role = (sx != sy) ? (sx ? -1 : 1) : 0;  // SE of its TL node
+        else role = (sx == sy) ? (sx ? 1 : -1) : 0;              // SW of its TR node
+        if (role > 0) v += vol;
+        else if (role < 0) v -= vol;
+      }
     }
     R xc = R(0.25) * ((R(ri) * Dx + blx) + (R(ri + 1) * Dx + brx) + (R(ri) * Dx + tlx) +
                       (R(ri + 1) * Dx + trx));
@@ -597,181 +671,241 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   }
   __syncthreads();
 
-  // ---- stage 3: every donor of the tile and its halo writes its outflow
-  // regions into LDS (those a tile cell receives or gives)
   const R nrm = sqrt(Dx * Dx + Dy * Dy);
-  for (int l = tid; l < (TX + 2) * (TY + 2); l += NTHREADS) {
-    const int da = l % (TX + 2), db = l / (TX + 2);
-    const int i = i0 - 1 + da, j = j0 - 1 + db;
-    if (i < 0 || j < 0 || i >= nx || j >= ny) continue;  // ghosts give only wall regions
-    const int q = j * nx + i;
-    const int ca = da + 1, cb = db + 1;  // record index of the donor
-    const int na = da + 1, nb = db + 1;  // node index of its BL node
-    const R nd_x[4] = {sh.ndx[nb][na], sh.ndx[nb][na + 1], sh.ndx[nb + 1][na], sh.ndx[nb + 1][na + 1]};
-    const R nd_y[4] = {sh.ndy[nb][na], sh.ndy[nb][na + 1], sh.ndy[nb + 1][na], sh.ndy[nb + 1][na + 1]};
-    CellRegions<R> r;
-    cell_regions(Dx, Dy, nd_x[0], nd_y[0], nd_x[1], nd_y[1], nd_x[2], nd_y[2], nd_x[3], nd_y[3], r);
-    // local slots of the donor's 8 regions (-1: not kept by this tile)
-    int slot[8];
-    {
-      const int I = i - i0, J = j - j0;
-      auto xs = [&](int fi, int fj) { return (fi >= 0 && fi <= TX && fj >= 0 && fj < TY) ? fj * (TX + 1) + fi : -1; };
-      auto ys = [&](int fi, int fj) { return (fi >= 0 && fi < TX && fj >= 0 && fj <= TY) ? fj * TX + fi : -1; };
-      auto cs = [&](int fi, int fj) { return (fi >= 0 && fi <= TX && fj >= 0 && fj <= TY) ? fj * (TX + 1) + fi : -1; };
-      slot[0] = xs(I, J);
-      slot[1] = xs(I + 1, J);
-      slot[2] = ys(I, J);
-      slot[3] = ys(I, J + 1);
-      slot[4] = cs(I, J);
-      slot[5] = cs(I + 1, J);
-      slot[6] = cs(I, J + 1);
-      slot[7] = cs(I + 1, J + 1);
+  const bool o2 = g.recon_order == 2;
+  // in-tile window of the donors whose regions the tile needs
+  auto donor_in = [&](int di, int dj) {
+    return di >= i0 - 1 && di <= i0 + TX && dj >= j0 - 1 && dj <= j0 + TY && di >= 0 && dj >= 0 &&
+           di < nx && dj < ny;
+  };
+  // region (kind, I, J) -> index in vr/ve
+  auto vidx = [&](int kind, int I, int J) {
+    if (kind == 0) return (J - (j0 - 1)) * SH::VXW + (I - (i0 - 1));
+    if (kind == 1) return SH::VXW * SH::VXH + (J - (j0 - 1)) * SH::VYW + (I - (i0 - 1));
+    return SH::VXW * SH::VXH + SH::VYW * SH::VYH + (J - (j0 - 1)) * SH::VCW + (I - (i0 - 1));
+  };
+  // donor-frame region s of donor (di, dj) -> (kind, I, J) of the region
+  auto region_of = [&](int di, int dj, int s, int &kind, int &I, int &J) {
+    switch (s) {
+      case 0: kind = 0; I = di; J = dj; break;
+      case 1: kind = 0; I = di + 1; J = dj; break;
+      case 2: kind = 1; I = di; J = dj; break;
+      case 3: kind = 1; I = di; J = dj + 1; break;
+      case 4: kind = 2; I = di; J = dj; break;
+      case 5: kind = 2; I = di + 1; J = dj; break;
+      case 6: kind = 2; I = di; J = dj + 1; break;
+      default: kind = 2; I = di + 1; J = dj + 1; break;
     }
-    bool any = false;
-#pragma unroll
-    for (int s = 0; s < 8; ++s) any = any || (r.role[s] > 0 && slot[s] >= 0);
-    if (!any) continue;
-    const int pm = sh.pure[cb][ca];
-    // partial volumes
-    R W[8][NM];
-#pragma unroll
-    for (int s = 0; s < 8; ++s)
-#pragma unroll
-      for (int m = 0; m < NM; ++m) W[s][m] = (pm == m && r.role[s] > 0) ? r.vol[s] : R(0);
-    if (pm < 0) {
-      const int ms = ldg(P.mix_slot + q);
-      if (ms >= 0 && ms < P.mix_cap) {
-        const double *src = P.mix_W + (size_t)ms * 8 * NM;
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-#pragma unroll
-          for (int m = 0; m < NM; ++m) W[s][m] = r.role[s] > 0 ? R(ldg(src + (s * NM + m))) : R(0);
+  };
+  // signed volume of region (kind, I, J) (real position); for corners the
+  // sign is that of the node's x-displacement and *mainc its kind
+  auto region_vol = [&](int kind, int I, int J, bool &mainc) {
+    mainc = false;
+    if (kind == 0) return sh.xv[NB(J)][NA(I)];
+    if (kind == 1) return sh.yv[NB(J)][NA(I)];
+    const R cdx = sh.ndx[NB(J)][NA(I)], cdy = sh.ndy[NB(J)][NA(I)];
+    mainc = corner_main(cdx, cdy);
+    const R v = fabs(cdx * cdy);
+    return cdx >= R(0) ? v : -v;
+  };
+
+  // ---- P4: order-2 values of the regions with a pure donor in the window
+  if (o2) {
+    for (int l = tid; l < SH::NV; l += NTHREADS) {
+      int kind, I, J;
+      if (l < SH::VXW * SH::VXH) {
+        kind = 0; I = i0 - 1 + l % SH::VXW; J = j0 - 1 + l / SH::VXW;
+        if (I < 0 || I > nx || J < 0 || J >= ny) continue;
+      } else if (l < SH::VXW * SH::VXH + SH::VYW * SH::VYH) {
+        const int k = l - SH::VXW * SH::VXH;
+        kind = 1; I = i0 - 1 + k % SH::VYW; J = j0 - 1 + k / SH::VYW;
+        if (I < 0 || I >= nx || J < 0 || J > ny) continue;
+      } else {
+        const int k = l - SH::VXW * SH::VXH - SH::VYW * SH::VYH;
+        kind = 2; I = i0 - 1 + k % SH::VCW; J = j0 - 1 + k / SH::VCW;
+        if (I < 0 || I > nx || J < 0 || J > ny) continue;
       }
-    }
-    // order-2 values of the pure material, with the positivity guard
-    R vr[8], ve[8];
-    bool use2 = false;
-    if (pm >= 0 && g.recon_order == 2) {
-      R rD = R(0), eD = R(0), Mpm = R(0);
+      bool mainc;
+      const R sv = region_vol(kind, I, J, mainc);
+      const RegionRef rf = region_donor(kind, I, J, signbit(sv), mainc);
+      if (!donor_in(rf.di, rf.dj)) continue;
+      const int ca = rf.di - (i0 - 2), cb = rf.dj - (j0 - 2);
+      const int pm = sh.pure[cb][ca];
+      if (pm < 0) continue;
+      R rD = R(0), eD = R(0);
 #pragma unroll
       for (int m = 0; m < NM; ++m)
         if (m == pm) {
           rD = sh.rcf[m][cb][ca];
           eD = sh.el[m][cb][ca];
-          Mpm = ldg(Ms + (m * C + q));
         }
+      R vr = rD, ve = eD;
+      const int na = NA(rf.di), nb = NB(rf.dj);  // donor's BL node
       const R dxL = sh.wx[cb][ca], dyL = sh.wy[cb][ca];
-      const R xD = sh.xc[cb][ca], yD = sh.yc[cb][ca];
+      const int s = rf.s;
+      int si, sj;
+      R vx, vy, off;
+      if (s < 2) {
+        const R sg = s == 0 ? R(-1) : R(1);
+        const R lo = sh.ndx[nb][na + (s == 1)], hi = sh.ndx[nb + 1][na + (s == 1)];
+        si = 1; sj = 0; vx = R(1); vy = R(0);
+        off = sg * dxL - R(0.5) * (lo + hi);
+      } else if (s < 4) {
+        const R sg = s == 2 ? R(-1) : R(1);
+        const R lo = sh.ndy[nb + (s == 3)][na], hi = sh.ndy[nb + (s == 3)][na + 1];
+        si = 0; sj = 1; vx = R(0); vy = R(1);
+        off = sg * dyL - R(0.5) * (lo + hi);
+      } else {
+        const int cn = s - 4;  // BL, BR, TL, TR node of the donor
+        const R cdx = sh.ndx[nb + (cn >> 1)][na + (cn & 1)], cdy = sh.ndy[nb + (cn >> 1)][na + (cn & 1)];
+        const R sx = cdx >= R(0) ? R(1) : R(-1);
+        if (corner_main(cdx, cdy)) {
+          si = 1; sj = 1; vx = Dx / nrm; vy = Dy / nrm;
+          off = (sx * dxL - cdx) * vx + (sx * dyL - cdy) * vy;
+        } else {
+          si = 1; sj = -1; vx = Dx / nrm; vy = -Dy / nrm;
+          off = (sx * dxL - cdx) * vx + (-sx * dyL - cdy) * vy;
+        }
+      }
+      const int am = ca - si, bmn = cb - sj, ap = ca + si, bp = cb + sj;
+      if (sh.pure[bmn][am] == pm && sh.pure[bp][ap] == pm) {
+        const R xD = sh.xc[cb][ca], yD = sh.yc[cb][ca];
+        const R lm = (xD - sh.xc[bmn][am]) * vx + (yD - sh.yc[bmn][am]) * vy;
+        const R lp = (sh.xc[bp][ap] - xD) * vx + (sh.yc[bp][ap] - yD) * vy;
+        R rm = R(0), rp = R(0), em = R(0), ep = R(0);
+#pragma unroll
+        for (int m = 0; m < NM; ++m)
+          if (m == pm) {
+            rm = sh.rcf[m][bmn][am]; rp = sh.rcf[m][bp][ap];
+            em = sh.el[m][bmn][am]; ep = sh.el[m][bp][ap];
+          }
+        const R ilm = qdiv(R(1), lm), ilp = qdiv(R(1), lp);
+        vr = rD + R(0.5) * van_leer((rD - rm) * ilm, (rp - rD) * ilp) * off;
+        ve = eD + R(0.5) * van_leer((eD - em) * ilm, (ep - eD) * ilp) * off;
+      }
+      sh.vr[l] = vr;
+      sh.ve[l] = ve;
+    }
+    __syncthreads();
+
+    // ---- P5: positivity guard of each pure donor of the window: order 2
+    // is kept unless it would send out more mass or energy than it holds
+    for (int l = tid; l < (TX + 2) * (TY + 2); l += NTHREADS) {
+      const int di = i0 - 1 + l % (TX + 2), dj = j0 - 1 + l / (TX + 2);
+      if (di >= nx || dj >= ny || di < 0 || dj < 0) continue;
+      const int ca = di - (i0 - 2), cb = dj - (j0 - 2);
+      const int pm = sh.pure[cb][ca];
+      if (pm < 0) continue;
+      R eD = R(0), Mpm = R(0);
+#pragma unroll
+      for (int m = 0; m < NM; ++m)
+        if (m == pm) {
+          eD = sh.el[m][cb][ca];
+          Mpm = ldg(Ms + (m * C + dj * nx + di));
+        }
       R Mout = R(0), Eout = R(0);
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
-        vr[s] = rD;
-        ve[s] = eD;
-        if (r.role[s] <= 0) continue;
-        int si, sj;
-        R vx, vy, off;
-        if (s < 2) {
-          const R sg = s == 0 ? R(-1) : R(1);
-          const R lo = s == 0 ? nd_x[0] : nd_x[1], hi = s == 0 ? nd_x[2] : nd_x[3];
-          si = 1; sj = 0; vx = R(1); vy = R(0);
-          off = sg * dxL - R(0.5) * (lo + hi);
-        } else if (s < 4) {
-          const R sg = s == 2 ? R(-1) : R(1);
-          const R lo = s == 2 ? nd_y[0] : nd_y[2], hi = s == 2 ? nd_y[1] : nd_y[3];
-          si = 0; sj = 1; vx = R(0); vy = R(1);
-          off = sg * dyL - R(0.5) * (lo + hi);
-        } else {
-          const R cdx = nd_x[s - 4], cdy = nd_y[s - 4];
-          const R sx = cdx >= R(0) ? R(1) : R(-1);
-          if (corner_main(cdx, cdy)) {
-            si = 1; sj = 1; vx = Dx / nrm; vy = Dy / nrm;
-            off = (sx * dxL - cdx) * vx + (sx * dyL - cdy) * vy;
-          } else {
-            si = 1; sj = -1; vx = Dx / nrm; vy = -Dy / nrm;
-            off = (sx * dxL - cdx) * vx + (-sx * dyL - cdy) * vy;
-          }
-        }
-        const int am = ca - si, bmn = cb - sj, ap = ca + si, bp = cb + sj;
-        if (sh.pure[bmn][am] == pm && sh.pure[bp][ap] == pm) {
-          const R lm = (xD - sh.xc[bmn][am]) * vx + (yD - sh.yc[bmn][am]) * vy;
-          const R lp = (sh.xc[bp][ap] - xD) * vx + (sh.yc[bp][ap] - yD) * vy;
-          R rm = R(0), rp = R(0), em = R(0), ep = R(0);
-#pragma unroll
-          for (int m = 0; m < NM; ++m)
-            if (m == pm) {
-              rm = sh.rcf[m][bmn][am]; rp = sh.rcf[m][bp][ap];
-              em = sh.el[m][bmn][am]; ep = sh.el[m][bp][ap];
-            }
-          const R ilm = qdiv(R(1), lm), ilp = qdiv(R(1), lp);
-          vr[s] = rD + R(0.5) * van_leer((rD - rm) * ilm, (rp - rD) * ilp) * off;
-          ve[s] = eD + R(0.5) * van_leer((eD - em) * ilm, (ep - eD) * ilp) * off;
-        }
-        R Ws = R(0);
-#pragma unroll
-        for (int m = 0; m < NM; ++m)
-          if (m == pm) Ws = W[s][m];
-        const R mu = vr[s] * Ws;
+        int kind, I, J;
+        region_of(di, dj, s, kind, I, J);
+        bool mainc;
+        const R sv = region_vol(kind, I, J, mainc);
+        const RegionRef rf = region_donor(kind, I, J, signbit(sv), mainc);
+        if (rf.di != di || rf.dj != dj || rf.s != s) continue;  // not an outflow of this donor
+        const int vi = vidx(kind, I, J);
+        const R mu = sh.vr[vi] * fabs(sv);
         Mout += mu;
-        Eout += mu * ve[s];
+        Eout += mu * sh.ve[vi];
       }
-      use2 = !(Mout > Mpm || Eout > Mpm * eD);
+      if (!(Mout > Mpm || Eout > Mpm * eD)) sh.pure[cb][ca] = pm + 16;
     }
-    // fluxes of the kept outflow regions, signed along the region orientation
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      if (r.role[s] <= 0 || slot[s] < 0) continue;
-      const R sg = (s == 0 || s == 2 || s == 4 || s == 6) ? R(-1) : R(1);
-      R *F;
-      int cnt;
-      if (s < 2) { F = &sh.fx[0][0]; cnt = SH::NXF; }
-      else if (s < 4) { F = &sh.fy[0][0]; cnt = SH::NYF; }
-      else { F = &sh.fc[0][0]; cnt = SH::NCN; }
-#pragma unroll
-      for (int m = 0; m < NM; ++m) {
-        const R w = W[s][m];
-        R rho = sh.rcf[m][cb][ca], e = sh.el[m][cb][ca];
-        if (use2 && m == pm) {
-          rho = vr[s];
-          e = ve[s];
-        }
-        const R mu = w > R(0) ? rho * w : R(0);
-        const R ep = w > R(0) ? mu * e : R(0);
-        F[m * cnt + slot[s]] = sg * w;
-        F[(NM + m) * cnt + slot[s]] = sg * mu;
-        F[(2 * NM + m) * cnt + slot[s]] = sg * ep;
-      }
-    }
+    __syncthreads();
   }
-  __syncthreads();
 
-  // ---- stage 4: nine-point update of the tile's cells
+  // ---- P6: nine-point update of the tile's cells
   {
     const int a = tid % TX, b = tid / TX;
     const int i = i0 + a, j = j0 + b;
     if (i < nx && j < ny) {
       const int q = j * nx + i;
-      const int ca = a + 2, cb = b + 2, na = a + 2, nb = b + 2;
-      // region slots and signs (+: into this cell); walls carry nothing
-      int rs[8];
+      const int ca = a + 2, cb = b + 2;
+      // regions W, E, S, N (faces) and the corners at BL, BR, TL, TR;
+      // sign +: into this cell along the region's orientation; walls and
+      // corners of the other diagonal carry nothing
+      const int rk[8] = {0, 0, 1, 1, 2, 2, 2, 2};
+      const int rI[8] = {i, i + 1, i, i, i, i + 1, i, i + 1};
+      const int rJ[8] = {j, j, j, j + 1, j, j, j + 1, j + 1};
+      R F[8][3 * NM];
       R sgn[8];
-      const R *Fb[8];
-      int cnt[8];
-      rs[0] = b * (TX + 1) + a;  Fb[0] = &sh.fx[0][0]; cnt[0] = SH::NXF; sgn[0] = i > 0 ? R(1) : R(0);
-      rs[1] = rs[0] + 1;         Fb[1] = &sh.fx[0][0]; cnt[1] = SH::NXF; sgn[1] = i < nx - 1 ? R(-1) : R(0);
-      rs[2] = b * TX + a;        Fb[2] = &sh.fy[0][0]; cnt[2] = SH::NYF; sgn[2] = j > 0 ? R(1) : R(0);
-      rs[3] = rs[2] + TX;        Fb[3] = &sh.fy[0][0]; cnt[3] = SH::NYF; sgn[3] = j < ny - 1 ? R(-1) : R(0);
-      const int ci[4] = {0, 1, 0, 1}, cj[4] = {0, 0, 1, 1};
-      const R cs4[4] = {R(1), R(-1), R(1), R(-1)};
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int I = i + ci[s], J = j + cj[s];
-        rs[4 + s] = (b + cj[s]) * (TX + 1) + a + ci[s];
-        Fb[4 + s] = &sh.fc[0][0];
-        cnt[4 + s] = SH::NCN;
-        const bool wall = I == 0 || I == nx || J == 0 || J == ny;
-        const bool mainc = corner_main(sh.ndx[nb + cj[s]][na + ci[s]], sh.ndy[nb + cj[s]][na + ci[s]]);
-        const bool mine = (s == 0 || s == 3) ? mainc : !mainc;
-        sgn[4 + s] = (!wall && mine) ? cs4[s] : R(0);
+      for (int s = 0; s < 8; ++s) {
+        bool mainc;
+        const R sv = region_vol(rk[s], rI[s], rJ[s], mainc);
+        // the flux of the bottom-left corner (either diagonal) also goes to
+        // the momentum remap, so it is formed even when this cell is not
+        // one of its two cells
+        bool need;
+        if (s == 0) sgn[s] = i > 0 ? R(1) : R(0);
+        else if (s == 1) sgn[s] = i < nx - 1 ? R(-1) : R(0);
+        else if (s == 2) sgn[s] = j > 0 ? R(1) : R(0);
+        else if (s == 3) sgn[s] = j < ny - 1 ? R(-1) : R(0);
+        if (s < 4) {
+          need = sgn[s] != R(0);
+        } else {
+          const int I = rI[s], J = rJ[s];
+          const bool wall = I == 0 || I == nx || J == 0 || J == ny;
+          const bool mine = (s == 4 || s == 7) ? mainc : !mainc;
+          sgn[s] = (!wall && mine) ? ((s == 4 || s == 6) ? R(1) : R(-1)) : R(0);
+          need = s == 4 ? !wall : sgn[s] != R(0);
+        }
+#pragma unroll
+        for (int k = 0; k < 3 * NM; ++k) F[s][k] = R(0);
+        if (!need) continue;
+        const bool neg = signbit(sv);
+        const RegionRef rf = region_donor(rk[s], rI[s], rJ[s], neg, mainc);
+        const R dir = neg ? R(-1) : R(1);
+        const R w = fabs(sv);
+        const int da = rf.di - (i0 - 2), db = rf.dj - (j0 - 2);
+        const int pq = sh.pure[db][da];
+        if (pq >= 0) {
+          const int pm = pq & 15;
+          R rho = R(0), e = R(0);
+#pragma unroll
+          for (int m = 0; m < NM; ++m)
+            if (m == pm) {
+              rho = sh.rcf[m][db][da];
+              e = sh.el[m][db][da];
+            }
+          if (o2 && pq >= 16) {
+            const int vi = vidx(rk[s], rI[s], rJ[s]);
+            rho = sh.vr[vi];
+            e = sh.ve[vi];
+          }
+          const R mu = w > R(0) ? rho * w : R(0);
+          const R ep = w > R(0) ? mu * e : R(0);
+#pragma unroll
+          for (int m = 0; m < NM; ++m)
+            if (m == pm) {
+              F[s][m] = dir * w;
+              F[s][NM + m] = dir * mu;
+              F[s][2 * NM + m] = dir * ep;
+            }
+        } else {
+          const int dq = rf.dj * nx + rf.di;
+          const int ms = ldg(P.mix_slot + dq);
+          if (ms >= 0 && ms < P.mix_cap) {
+            const double *src = P.mix_W + (size_t)ms * 8 * NM + rf.s * NM;
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+              const R wm = R(ldg(src + m));
+              const R mu = wm > R(0) ? sh.rcf[m][db][da] * wm : R(0);
+              const R ep = wm > R(0) ? mu * sh.el[m][db][da] : R(0);
+              F[s][m] = dir * wm;
+              F[s][NM + m] = dir * mu;
+              F[s][2 * NM + m] = dir * ep;
+            }
+          }
+        }
       }
       const R v = sh.vcf[cb][ca];
       R Vn[NM], Mn[NM], En[NM], Msa = R(0), Esa = R(0);
@@ -786,9 +920,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
           if (sgn[s] == R(0)) continue;
-          const R *F = Fb[s];
-          const int c = cnt[s], h = rs[s];
-          const R w = F[m * c + h], mu = F[(NM + m) * c + h], ep = F[(2 * NM + m) * c + h];
+          const R w = F[s][m], mu = F[s][NM + m], ep = F[s][2 * NM + m];
           if (sgn[s] > R(0)) { V.add(w); M.add(mu); E.add(ep); }
           else { V.add(-w); M.add(-mu); E.add(-ep); }
         }
@@ -826,9 +958,9 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       R mx = R(0), my = R(0), mc = R(0);
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
-        mx += sh.fx[NM + m][rs[0]];
-        my += sh.fy[NM + m][rs[2]];
-        mc += sh.fc[NM + m][rs[4]];
+        mx += F[0][NM + m];
+        my += F[2][NM + m];
+        mc += F[4][NM + m];
       }
       stg(P.MX + (j * (nx + 1) + i), i > 0 ? mx : R(0));
       stg(P.MY + (j * nx + i), j > 0 ? my : R(0));
@@ -836,9 +968,9 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       if (P.dbg.Wpx) {
         const int nX = (nx + 1) * ny, nY = nx * (ny + 1), nN = (nx + 1) * (ny + 1);
         for (int m = 0; m < NM; ++m) {
-          stg(P.dbg.Wpx + (m * nX + j * (nx + 1) + i), i > 0 ? sh.fx[m][rs[0]] : R(0));
-          stg(P.dbg.Wpy + (m * nY + j * nx + i), j > 0 ? sh.fy[m][rs[2]] : R(0));
-          stg(P.dbg.Wpc + (m * nN + j * (nx + 1) + i), (i > 0 && j > 0) ? sh.fc[m][rs[4]] : R(0));
+          stg(P.dbg.Wpx + (m * nX + j * (nx + 1) + i), i > 0 ? F[0][m] : R(0));
+          stg(P.dbg.Wpy + (m * nY + j * nx + i), j > 0 ? F[2][m] : R(0));
+          stg(P.dbg.Wpc + (m * nN + j * (nx + 1) + i), (i > 0 && j > 0) ? F[4][m] : R(0));
         }
       }
     }
@@ -866,7 +998,14 @@ template <typename R>
 struct DualShared {
   static constexpr int NX_ = TX + 4, NY_ = TY + 4;  // nodes [I0-2, I0+TX+1]
   static constexpr int NXF = (TX + 1) * TY, NYF = TX * (TY + 1), NCN = (TX + 1) * (TY + 1);
+  // primal mass fluxes around the tile, mirrored at walls: x-faces
+  // [I0-1, I0+TX] x rows [J0-1, J0+TY-1]; y-faces columns [I0-1, I0+TX-1] x
+  // [J0-1, J0+TY]; (main, anti) corner fluxes at nodes [I0-1, I0+TX] x [J0-1, J0+TY]
+  static constexpr int PXW = TX + 2, PXH = TY + 1, PYW = TX + 1, PYH = TY + 2;
+  static constexpr int PCW = TX + 2, PCH = TY + 2;
+  static constexpr int NSTAGE = NX_ * NY_ + PXW * PXH + PYW * PYH + PCW * PCH;
   R ulx[NY_][NX_], uly[NY_][NX_], dx[NY_][NX_], dy[NY_][NX_], X[NY_][NX_], Y[NY_][NX_];
+  R mx[PXH][PXW], my[PYH][PYW], cd[PCH][PCW], ca[PCH][PCW];
   R fx[3][NXF], fy[3][NYF], fd[3][NCN], fa[3][NCN];
 };
 
@@ -890,6 +1029,27 @@ __device__ __forceinline__ R mflux_y(const Prob<R> &P, int i, int J) {
   if (J == 0 || J == ny) return R(0);
   return sg * ldg(P.MY + (J * nx + i));
 }
+// (main, anti) corner mass flux at node (I,J), I in [-1, nx+1], J in
+// [-1, ny+1], mirrored at walls; the kind comes from the real node's
+// displacement d = dt u^{n+1/2}
+template <typename R>
+__device__ __forceinline__ void corner_mu(const Prob<R> &P, R dt, int I, int J, R &dg, R &an) {
+  const int nx = P.g.nx, ny = P.g.ny;
+  bool fx = false, fy = false;
+  int rI = I, rJ = J;
+  if (rI < 0) { rI = -rI; fx = true; }
+  else if (rI > nx) { rI = 2 * nx - rI; fx = true; }
+  if (rJ < 0) { rJ = -rJ; fy = true; }
+  else if (rJ > ny) { rJ = 2 * ny - rJ; fy = true; }
+  dg = an = R(0);
+  if (rI == 0 || rI == nx || rJ == 0 || rJ == ny) return;
+  const int p = rJ * (nx + 1) + rI;
+  const R F = ldg(P.MC + p);
+  if (corner_main(dt * ldg(P.uhx + p), dt * ldg(P.uhy + p))) dg = F;
+  else an = F;
+  if (fy) { const R t = dg; dg = an; an = t; }
+  if (fx) { const R t = dg; dg = -an; an = -t; }
+}
 
 template <typename R, int NM>
 __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap bm, int gpar) {
@@ -909,30 +1069,57 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
   const R Dx = R(g.dx), Dy = R(g.dy);
 
   if (!g.kinematic) {
-    // ---- stage 1: node data mirrored at walls
-    for (int l = tid; l < SH::NX_ * SH::NY_; l += NTHREADS) {
-      const int a = l % SH::NX_, b = l / SH::NX_;
-      const int I = I0 - 2 + a, J = J0 - 2 + b;
-      if (I > nx + 2 || J > ny + 2) continue;
-      const int rI = refl_node(I, nx), rJ = refl_node(J, ny), p = rJ * (nx + 1) + rI;
-      R ulx = ldg(P.uLx + p), uly = ldg(P.uLy + p), dx = dt * ldg(P.uhx + p), dy = dt * ldg(P.uhy + p);
-      R X = R(rI) * Dx + dx, Y = R(rJ) * Dy + dy;
-      if (rI != I) {
-        ulx = -ulx;
-        dx = -dx;
-        X = (I < 0 ? R(0) : R(2.0 * g.Lx)) - X;
+    // ---- stage 1: node data and the primal mass fluxes around the tile,
+    // mirrored at walls, in one pass over all staged items
+    for (int l = tid; l < SH::NSTAGE; l += NTHREADS) {
+      if (l < SH::NX_ * SH::NY_) {
+        const int a = l % SH::NX_, b = l / SH::NX_;
+        const int I = I0 - 2 + a, J = J0 - 2 + b;
+        if (I > nx + 2 || J > ny + 2) continue;
+        const int rI = refl_node(I, nx), rJ = refl_node(J, ny), p = rJ * (nx + 1) + rI;
+        R ulx = ldg(P.uLx + p), uly = ldg(P.uLy + p), dx = dt * ldg(P.uhx + p), dy = dt * ldg(P.uhy + p);
+        R X = R(rI) * Dx + dx, Y = R(rJ) * Dy + dy;
+        if (rI != I) {
+          ulx = -ulx;
+          dx = -dx;
+          X = (I < 0 ? R(0) : R(2.0 * g.Lx)) - X;
+        }
+        if (rJ != J) {
+          uly = -uly;
+          dy = -dy;
+          Y = (J < 0 ? R(0) : R(2.0 * g.Ly)) - Y;
+        }
+        sh.ulx[b][a] = ulx;
+        sh.uly[b][a] = uly;
+        sh.dx[b][a] = dx;
+        sh.dy[b][a] = dy;
+        sh.X[b][a] = X;
+        sh.Y[b][a] = Y;
+        continue;
       }
-      if (rJ != J) {
-        uly = -uly;
-        dy = -dy;
-        Y = (J < 0 ? R(0) : R(2.0 * g.Ly)) - Y;
+      int k = l - SH::NX_ * SH::NY_;
+      if (k < SH::PXW * SH::PXH) {
+        const int a = k % SH::PXW, b = k / SH::PXW;
+        const int I = I0 - 1 + a, j = J0 - 1 + b;
+        sh.mx[b][a] = (I <= nx + 1 && j <= ny) ? mflux_x(P, I, j) : R(0);
+        continue;
       }
-      sh.ulx[b][a] = ulx;
-      sh.uly[b][a] = uly;
-      sh.dx[b][a] = dx;
-      sh.dy[b][a] = dy;
-      sh.X[b][a] = X;
-      sh.Y[b][a] = Y;
+      k -= SH::PXW * SH::PXH;
+      if (k < SH::PYW * SH::PYH) {
+        const int a = k % SH::PYW, b = k / SH::PYW;
+        const int i = I0 - 1 + a, J = J0 - 1 + b;
+        sh.my[b][a] = (i <= nx && J <= ny + 1) ? mflux_y(P, i, J) : R(0);
+        continue;
+      }
+      k -= SH::PYW * SH::PYH;
+      {
+        const int a = k % SH::PCW, b = k / SH::PCW;
+        const int I = I0 - 1 + a, J = J0 - 1 + b;
+        R dg = R(0), an = R(0);
+        if (I <= nx + 1 && J <= ny + 1) corner_mu(P, dt, I, J, dg, an);
+        sh.cd[b][a] = dg;
+        sh.ca[b][a] = an;
+      }
     }
     __syncthreads();
     auto L = [&](int I) { return I - (I0 - 2); };
@@ -955,97 +1142,77 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
     };
     auto wxd = [&](int la, int lb) { return Dx + R(0.5) * (sh.dx[lb][la + 1] - sh.dx[lb][la - 1]); };
     auto wyd = [&](int la, int lb) { return Dy + R(0.5) * (sh.dy[lb + 1][la] - sh.dy[lb - 1][la]); };
-    // (main, anti) corner mass flux at node (I,J), mirrored at walls
-    auto corner_mu = [&](int I, int J, R &dg, R &an) {
-      bool fx = false, fy = false;
-      int rI = I, rJ = J;
-      if (rI < 0) { rI = -rI; fx = true; }
-      else if (rI > nx) { rI = 2 * nx - rI; fx = true; }
-      if (rJ < 0) { rJ = -rJ; fy = true; }
-      else if (rJ > ny) { rJ = 2 * ny - rJ; fy = true; }
-      dg = an = R(0);
-      if (rI == 0 || rI == nx || rJ == 0 || rJ == ny) return;
-      const R F = ldg(P.MC + (rJ * (nx + 1) + rI));
-      // kind from the real node's displacement (the staged node is mirrored)
-      R ddx = sh.dx[M_(J)][L(I)], ddy = sh.dy[M_(J)][L(I)];
-      if (fx) ddx = -ddx;
-      if (fy) ddy = -ddy;
-      if (corner_main(ddx, ddy)) dg = F;
-      else an = F;
-      if (fy) { const R t = dg; dg = an; an = t; }
-      if (fx) { const R t = dg; dg = -an; an = -t; }
-    };
     const R nrmv = sqrt(Dx * Dx + Dy * Dy);
 
-    // ---- stage 2: dual regions of the tile, each computed once
-    for (int l = tid; l < SH::NXF; l += NTHREADS) {  // dual x-face (I,J): nodes (I-1,J)-(I,J)
-      const int a = l % (TX + 1), b = l / (TX + 1);
-      const int I = I0 + a, J = J0 + b;
-      if (I > nx + 1 || J > ny) continue;
-      const R phi = R(0.25) * (mflux_x(P, I - 1, J - 1) + mflux_x(P, I, J - 1) +
-                               mflux_x(P, I - 1, J) + mflux_x(P, I, J));
-      const int D = phi > R(0) ? I - 1 : I;
-      const R sg = phi > R(0) ? R(1) : R(-1);
-      const R df = R(0.5) * (sh.dx[M_(J)][L(I - 1)] + sh.dx[M_(J)][L(I)]);
-      const R off = R(0.5) * (sg * wxd(L(D), M_(J)) - df);
-      R u, v;
-      recon(L(D), M_(J), 1, 0, R(1), R(0), off, u, v);
-      sh.fx[0][l] = phi;
-      sh.fx[1][l] = phi * u;
-      sh.fx[2][l] = phi * v;
-    }
-    for (int l = tid; l < SH::NYF; l += NTHREADS) {  // dual y-face (I,J): nodes (I,J-1)-(I,J)
-      const int a = l % TX, b = l / TX;
-      const int I = I0 + a, J = J0 + b;
-      if (I > nx || J > ny + 1) continue;
-      const R phi = R(0.25) * (mflux_y(P, I - 1, J - 1) + mflux_y(P, I, J - 1) +
-                               mflux_y(P, I - 1, J) + mflux_y(P, I, J));
-      const int D = phi > R(0) ? J - 1 : J;
-      const R sg = phi > R(0) ? R(1) : R(-1);
-      const R df = R(0.5) * (sh.dy[M_(J - 1)][L(I)] + sh.dy[M_(J)][L(I)]);
-      const R off = R(0.5) * (sg * wyd(L(I), M_(D)) - df);
-      R u, v;
-      recon(L(I), M_(D), 0, 1, R(0), R(1), off, u, v);
-      sh.fy[0][l] = phi;
-      sh.fy[1][l] = phi * u;
-      sh.fy[2][l] = phi * v;
-    }
-    for (int l = tid; l < SH::NCN; l += NTHREADS) {  // dual corners at cell (i,j)
-      const int a = l % (TX + 1), b = l / (TX + 1);
-      const int i = I0 - 1 + a, j = J0 - 1 + b;
-      if (i > nx || j > ny) continue;
-      R d00, a00, d10, a10, d01, a01, d11, a11;
-      corner_mu(i, j, d00, a00);
-      corner_mu(i + 1, j, d10, a10);
-      corner_mu(i, j + 1, d01, a01);
-      corner_mu(i + 1, j + 1, d11, a11);
-      const R dcx = R(0.25) * (sh.dx[M_(j)][L(i)] + sh.dx[M_(j)][L(i + 1)] + sh.dx[M_(j + 1)][L(i)] +
-                               sh.dx[M_(j + 1)][L(i + 1)]);
-      const R dcy = R(0.25) * (sh.dy[M_(j)][L(i)] + sh.dy[M_(j)][L(i + 1)] + sh.dy[M_(j + 1)][L(i)] +
-                               sh.dy[M_(j + 1)][L(i + 1)]);
-      {  // main diagonal: (i,j) -> (i+1,j+1)
-        const R phi = R(0.25) * (d00 + d10 + d01 + d11);
+    // ---- stage 2: every dual region of the tile once: x-faces, y-faces,
+    // then the corners, in one pass
+    for (int l = tid; l < SH::NXF + SH::NYF + SH::NCN; l += NTHREADS) {
+      if (l < SH::NXF) {  // dual x-face (I,J): nodes (I-1,J)-(I,J)
+        const int a = l % (TX + 1), b = l / (TX + 1);
+        const int I = I0 + a, J = J0 + b;
+        if (I > nx + 1 || J > ny) continue;
+        const R phi = R(0.25) * (sh.mx[b][a] + sh.mx[b][a + 1] + sh.mx[b + 1][a] + sh.mx[b + 1][a + 1]);
+        const int D = phi > R(0) ? I - 1 : I;
         const R sg = phi > R(0) ? R(1) : R(-1);
-        const int DI = phi > R(0) ? i : i + 1, DJ = phi > R(0) ? j : j + 1;
-        const R vx = Dx / nrmv, vy = Dy / nrmv;
-        R u, v, off = R(0);
-        if (o2) off = R(0.5) * ((sg * wxd(L(DI), M_(DJ)) - dcx) * vx + (sg * wyd(L(DI), M_(DJ)) - dcy) * vy);
-        recon(L(DI), M_(DJ), 1, 1, vx, vy, off, u, v);
-        sh.fd[0][l] = phi;
-        sh.fd[1][l] = phi * u;
-        sh.fd[2][l] = phi * v;
-      }
-      {  // anti-diagonal: (i,j+1) -> (i+1,j)
-        const R phi = R(0.25) * (a00 + a10 + a01 + a11);
+        const R df = R(0.5) * (sh.dx[M_(J)][L(I - 1)] + sh.dx[M_(J)][L(I)]);
+        const R off = R(0.5) * (sg * wxd(L(D), M_(J)) - df);
+        R u, v;
+        recon(L(D), M_(J), 1, 0, R(1), R(0), off, u, v);
+        sh.fx[0][l] = phi;
+        sh.fx[1][l] = phi * u;
+        sh.fx[2][l] = phi * v;
+      } else if (l < SH::NXF + SH::NYF) {  // dual y-face (I,J): nodes (I,J-1)-(I,J)
+        const int k = l - SH::NXF;
+        const int a = k % TX, b = k / TX;
+        const int I = I0 + a, J = J0 + b;
+        if (I > nx || J > ny + 1) continue;
+        const R phi = R(0.25) * (sh.my[b][a] + sh.my[b][a + 1] + sh.my[b + 1][a] + sh.my[b + 1][a + 1]);
+        const int D = phi > R(0) ? J - 1 : J;
         const R sg = phi > R(0) ? R(1) : R(-1);
-        const int DI = phi > R(0) ? i : i + 1, DJ = phi > R(0) ? j + 1 : j;
-        const R vx = Dx / nrmv, vy = -Dy / nrmv;
-        R u, v, off = R(0);
-        if (o2) off = R(0.5) * ((sg * wxd(L(DI), M_(DJ)) - dcx) * vx + (-sg * wyd(L(DI), M_(DJ)) - dcy) * vy);
-        recon(L(DI), M_(DJ), 1, -1, vx, vy, off, u, v);
-        sh.fa[0][l] = phi;
-        sh.fa[1][l] = phi * u;
-        sh.fa[2][l] = phi * v;
+        const R df = R(0.5) * (sh.dy[M_(J - 1)][L(I)] + sh.dy[M_(J)][L(I)]);
+        const R off = R(0.5) * (sg * wyd(L(I), M_(D)) - df);
+        R u, v;
+        recon(L(I), M_(D), 0, 1, R(0), R(1), off, u, v);
+        sh.fy[0][k] = phi;
+        sh.fy[1][k] = phi * u;
+        sh.fy[2][k] = phi * v;
+      } else {  // dual corners at cell (i,j)
+        const int k = l - SH::NXF - SH::NYF;
+        const int a = k % (TX + 1), b = k / (TX + 1);
+        const int i = I0 - 1 + a, j = J0 - 1 + b;
+        if (i > nx || j > ny) continue;
+        // corner pairs at the cell's nodes (i..i+1, j..j+1): staged at [b..b+1][a..a+1]
+        const R d00 = sh.cd[b][a], a00 = sh.ca[b][a], d10 = sh.cd[b][a + 1], a10 = sh.ca[b][a + 1];
+        const R d01 = sh.cd[b + 1][a], a01 = sh.ca[b + 1][a], d11 = sh.cd[b + 1][a + 1],
+                a11 = sh.ca[b + 1][a + 1];
+        const R dcx = R(0.25) * (sh.dx[M_(j)][L(i)] + sh.dx[M_(j)][L(i + 1)] + sh.dx[M_(j + 1)][L(i)] +
+                                 sh.dx[M_(j + 1)][L(i + 1)]);
+        const R dcy = R(0.25) * (sh.dy[M_(j)][L(i)] + sh.dy[M_(j)][L(i + 1)] + sh.dy[M_(j + 1)][L(i)] +
+                                 sh.dy[M_(j + 1)][L(i + 1)]);
+        {  // main diagonal: (i,j) -> (i+1,j+1)
+          const R phi = R(0.25) * (d00 + d10 + d01 + d11);
+          const R sg = phi > R(0) ? R(1) : R(-1);
+          const int DI = phi > R(0) ? i : i + 1, DJ = phi > R(0) ? j : j + 1;
+          const R vx = Dx / nrmv, vy = Dy / nrmv;
+          R u, v, off = R(0);
+          if (o2) off = R(0.5) * ((sg * wxd(L(DI), M_(DJ)) - dcx) * vx + (sg * wyd(L(DI), M_(DJ)) - dcy) * vy);
+          recon(L(DI), M_(DJ), 1, 1, vx, vy, off, u, v);
+          sh.fd[0][k] = phi;
+          sh.fd[1][k] = phi * u;
+          sh.fd[2][k] = phi * v;
+        }
+        {  // anti-diagonal: (i,j+1) -> (i+1,j)
+          const R phi = R(0.25) * (a00 + a10 + a01 + a11);
+          const R sg = phi > R(0) ? R(1) : R(-1);
+          const int DI = phi > R(0) ? i : i + 1, DJ = phi > R(0) ? j + 1 : j;
+          const R vx = Dx / nrmv, vy = -Dy / nrmv;
+          R u, v, off = R(0);
+          if (o2) off = R(0.5) * ((sg * wxd(L(DI), M_(DJ)) - dcx) * vx + (-sg * wyd(L(DI), M_(DJ)) - dcy) * vy);
+          recon(L(DI), M_(DJ), 1, -1, vx, vy, off, u, v);
+          sh.fa[0][k] = phi;
+          sh.fa[1][k] = phi * u;
+          sh.fa[2][k] = phi * v;
+        }
       }
     }
     __syncthreads();
