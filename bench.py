@@ -38,13 +38,15 @@ W64 = 8
 def kernel_bytes(nx, ny, nmat, w=W64):
     """Algorithmic bytes per launch of each kernel: every array the kernel has
     to read or write, touched once (C cells, N nodes; the per-cell int of the
-    mixed-cell index is 4 bytes); the mixed-cell work inside k_lagrange
-    touches only the mixed cells and is not counted."""
+    mixed-cell index is 4 bytes); the interface work of the mixed cells
+    touches only those cells and is not counted."""
     C = nx * ny
     N = (nx + 1) * (ny + 1)
     return {
-        # reads V, M, E and u; writes u^{n+1/2}, u^{lag}, m_p, e^{lag}, mixed index
-        "k_lagrange": w * (3 * nmat * C + 2 * N + 5 * N + nmat * C) + 4 * C,
+        # reads V, M, E and u; writes u^{n+1/2}, u^{lag}, m_p, e^{lag}
+        "k_lagrange": w * (3 * nmat * C + 2 * N + 5 * N + nmat * C),
+        # reads V (classification); writes the mixed-cell index
+        "k_mixed": w * nmat * C + 4 * C,
         # reads u^{n+1/2}, V, M, e^{lag}, mixed index; writes V, M, E, sound
         # speed and the three region mass fluxes
         "k_remap": w * (2 * N + 3 * nmat * C + 3 * nmat * C + 4 * C) + 4 * C,

@@ -79,6 +79,8 @@ struct lr_batch {
   BlockMap *node_map = nullptr, *cell_map = nullptr;
   size_t node_cap = 0, cell_cap = 0;
   int node_blocks = 0, cell_blocks = 0;
+  int *plist = nullptr;  // device [max_slots]: slots of the running problems
+  int nprob = 0, mix_chunks = 16;
   bool maps_dirty = true;
   StepFn step = nullptr;
   std::vector<BatchReq> slots;
@@ -153,8 +155,14 @@ int grow_scratch(lr_batch *b, size_t n) {
 // block maps over the tiles of every running problem
 int rebuild_maps(lr_batch *b) {
   std::vector<BlockMap> nm, cm;
+  std::vector<int> pl;
+  long long cmax = 0;
   for (size_t s = 0; s < b->slots.size(); ++s)
-    if (b->slots[s].running) tile_maps(b->slots[s].g, (int)s, nm, cm);
+    if (b->slots[s].running) {
+      tile_maps(b->slots[s].g, (int)s, nm, cm);
+      pl.push_back((int)s);
+      cmax = std::max(cmax, (long long)b->slots[s].g.nx * b->slots[s].g.ny);
+    }
   if (nm.size() > b->node_cap || cm.size() > b->cell_cap) {
     HIP_B(b, hipStreamSynchronize(b->stream));
     if (b->node_map) (void)hipFree(b->node_map);
@@ -172,8 +180,11 @@ int rebuild_maps(lr_batch *b) {
     HIP_B(b, hipMemcpy(b->node_map, nm.data(), nm.size() * sizeof(BlockMap), hipMemcpyHostToDevice));
   if (!cm.empty())
     HIP_B(b, hipMemcpy(b->cell_map, cm.data(), cm.size() * sizeof(BlockMap), hipMemcpyHostToDevice));
+  if (!pl.empty()) HIP_B(b, hipMemcpy(b->plist, pl.data(), pl.size() * sizeof(int), hipMemcpyHostToDevice));
   b->node_blocks = (int)nm.size();
   b->cell_blocks = (int)cm.size();
+  b->nprob = (int)pl.size();
+  b->mix_chunks = mix_chunks_for(cmax);
   b->maps_dirty = false;
   b->graph_ok = false;
   return LR_OK;
@@ -218,7 +229,7 @@ int batch_admit(lr_batch *b, int s, BatchReq &q, Prob<R> &P, const double *const
 // run one chunk of steps of every running problem
 int batch_chunk(lr_batch *b) {
   const Launch L{b->dprobs, b->node_map, b->cell_map, b->node_blocks, b->cell_blocks,
-                 b->o.persistent != 0};
+                 b->plist,  b->nprob,    b->mix_chunks, b->o.persistent != 0};
   const int n = b->o.chunk_steps;
   if (!b->o.use_graph) {
     for (int st = 0; st < n; ++st) b->step(L, st & 1, b->stream, nullptr);
@@ -275,7 +286,7 @@ void lr_batch_destroy(lr_batch *b) {
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->stage_ev) (void)hipEventDestroy(b->stage_ev);
   for (void *p : {(void *)b->pool, b->dprobs, (void *)b->ctl, (void *)b->node_map,
-                  (void *)b->cell_map, (void *)b->dstage, (void *)b->scratch})
+                  (void *)b->cell_map, (void *)b->dstage, (void *)b->scratch, (void *)b->plist})
     if (p) (void)hipFree(p);
   if (b->hctl) (void)hipHostFree(b->hctl);
   if (b->hstage) (void)hipHostFree(b->hstage);
@@ -310,6 +321,7 @@ int lr_batch_create(const lr_batch_opts *opts, lr_batch **out) {
   if (rc == LR_OK && (hipMalloc((void **)&b->pool, b->o.pool_bytes) != hipSuccess ||
                       hipMalloc(&b->dprobs, b->prob_size * o.max_slots) != hipSuccess ||
                       hipMalloc((void **)&b->ctl, sizeof(Ctl) * o.max_slots) != hipSuccess ||
+                      hipMalloc((void **)&b->plist, sizeof(int) * o.max_slots) != hipSuccess ||
                       hipHostMalloc((void **)&b->hctl, sizeof(Ctl) * o.max_slots, hipHostMallocDefault) !=
                           hipSuccess))
     rc = LR_ENOMEM;

@@ -264,6 +264,7 @@ struct lr_ctx {
   void *dprob = nullptr;  // device copy of the problem descriptor
   BlockMap *node_map = nullptr, *cell_map = nullptr;
   int node_blocks = 0, cell_blocks = 0;
+  int *plist = nullptr;  // device {0}: the problem list of the mixed-cell launch
   StepFn step = nullptr;
   Ctl *ctl = nullptr;   // device
   Ctl *hctl = nullptr;  // pinned host mirror
@@ -325,7 +326,9 @@ int build_maps(lr_ctx *c) {
   tile_maps(c->g, 0, nm, cm);
   c->node_blocks = (int)nm.size();
   c->cell_blocks = (int)cm.size();
-  if (dalloc(c, &c->node_map, nm.size()) || dalloc(c, &c->cell_map, cm.size())) return LR_ENOMEM;
+  if (dalloc(c, &c->node_map, nm.size()) || dalloc(c, &c->cell_map, cm.size()) || dalloc(c, &c->plist, 1))
+    return LR_ENOMEM;
+  HIP_CHECK(c, hipMemsetAsync(c->plist, 0, sizeof(int), c->own));
   HIP_CHECK(c, hipMemcpyAsync(c->node_map, nm.data(), nm.size() * sizeof(BlockMap), hipMemcpyHostToDevice, c->own));
   HIP_CHECK(c, hipMemcpyAsync(c->cell_map, cm.data(), cm.size() * sizeof(BlockMap), hipMemcpyHostToDevice, c->own));
   HIP_CHECK(c, hipStreamSynchronize(c->own));
@@ -367,7 +370,8 @@ int run_steps(lr_ctx *c, double t_end, long long max_steps) {
   int gpar = cur_slot(*c->hctl);
   k_start<<<1, 1, 0, c->stream>>>(c->ctl, t_end, max_steps);
   HIP_CHECK(c, hipGetLastError());
-  const Launch L{c->dprob, c->node_map, c->cell_map, c->node_blocks, c->cell_blocks, false};
+  const Launch L{c->dprob,  c->node_map, c->cell_map, c->node_blocks, c->cell_blocks, c->plist, 1,
+                 mix_chunks_for((long long)c->g.nx * c->g.ny), false};
   for (;;) {
     rc = read_ctl(c);
     if (rc) return rc;

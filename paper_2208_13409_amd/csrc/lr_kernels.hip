@@ -2,22 +2,24 @@
 // step (B. Chaudet, arXiv:2208.13409), templated on the bulk precision R
 // (double, or float with FP64 islands) and the number of materials NM.
 //
-// A step is three launches, each over a whole batch of problems (a block map
-// gives every 256-thread block its problem and tile):
+// A step is four launches, each over a whole batch of problems (a block map
+// gives every 256-thread block its problem and tile; the mixed-cell kernel
+// has a grid of list chunks x problems):
 //   k_lagrange  node tiles: predictor per cell staged in LDS (EOS, Wilkins Q,
 //               Vol^{n+1/2}, P_a^{n+1/2}; §1.2, §4.1), nodal mass and gradient
 //               of P+Q, u^{n+1/2}, u^{lag}; corrector energies e_a^{lag} of the
-//               tile's cells; compacted list of mixed cells,
-//               and, for the tile's mixed cells only (FP64, eight lanes per
-//               cell): Youngs normal, interface on the rectangular
-//               approximation of the Lagrangian cell, partial volumes of the
-//               outflow regions, donor-side clipping (§4.4)
-//   k_remap     cell tiles: node displacements and cell records (Vol^{lagCF},
-//               rho^{lagCF}, centres, widths) staged in LDS with a two-cell
-//               halo; every donor of the tile and its halo computes its
-//               outflow face and corner regions once (reconstruction §2.1.1,
-//               §3.3, §4.2) into LDS; each cell then gathers its nine-point
-//               update (§2.3, §4.4); compensated sums in FP32
+//               tile's cells; the tile's mixed cells join a compact list
+//   k_mixed     the problems' compact lists of mixed cells (FP64, eight
+//               lanes per cell, spread over the device): Youngs normal,
+//               interface on the rectangular approximation of the Lagrangian
+//               cell, partial volumes of the outflow regions, donor-side
+//               clipping (§4.4)
+//   k_remap     cell tiles: node displacements, face volumes and cell records
+//               (Vol^{lagCF}, rho^{lagCF}, centres, widths) staged in LDS with
+//               a two-cell halo; each flux region's order-2 values formed once
+//               (reconstruction §2.1.1, §3.3, §4.2), the positivity guard per
+//               donor; each cell then gathers its nine-point update (§2.3,
+//               §4.4); compensated sums in FP32
 //   k_dual      node tiles: dual face and corner mass fluxes (1/4-averages),
 //               reconstructed velocities, each dual region once in LDS; nodal
 //               momentum update; wavefront-shuffle min of the next CFL bound
@@ -275,7 +277,7 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
   __shared__ R sS[CH][CW], sMc[CH][CW], sQ[CH][CW];
   __shared__ R sPh[NM][CH][CW];
   __shared__ R sdx[NH][NW], sdy[NH][NW];
-  __shared__ int s_mix[NTHREADS];  // the tile's mixed cells (local index a + b*TX)
+  __shared__ int s_mix[NTHREADS];  // the tile's mixed cells (cell index)
   __shared__ int s_nmix, s_mixbase;
   if (tid == 0) s_nmix = 0;
   __syncthreads();
@@ -285,13 +287,12 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
     const int a = l % CW, b = l / CW;
     const int i = I0 - 1 + a, j = J0 - 1 + b;
     const bool owned = i >= I0 && j >= J0 && i < nx && j < ny && a <= TX && b <= TY;
-    bool mixed_owned = false;
+    int np = 0;
     if (i <= nx && j <= ny) {
       const int ri = refl_cell(i, nx), rj = refl_cell(j, ny), q = rj * nx + ri;
       const int bl = rj * (nx + 1) + ri, br = bl + 1, tl = bl + nx + 1, tr = tl + 1;
       R Msum = R(0), rc2 = R(0), k[NM], e[NM], rho[NM], Pa[NM], Mm[NM];
       bool pr[NM];
-      int np = 0;
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
         const R V = ldg(Vs + (m * C + q)), M = ldg(Ms + (m * C + q)), E = ldg(Es + (m * C + q));
@@ -306,7 +307,6 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
         if (pr[m]) rc2 += k[m] * R(g.gamma[m]) * Pa[m];
         Msum += M;
       }
-      mixed_owned = owned && np >= 2;
       R Qc = R(0), Sc = R(0);
       if (!g.kinematic) {
         const R rhoc = qdiv(Msum, A);
@@ -361,12 +361,24 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
           for (int m = 0; m < NM; ++m) stg(P.dbg.Ph + (m * C + q), g.kinematic ? R(0) : sPh[m][b][a]);
       }
     }
-    if (mixed_owned) s_mix[atomicAdd(&s_nmix, 1)] = (i - I0) + (j - J0) * TX;
+    if (owned && np >= 2) s_mix[atomicAdd(&s_nmix, 1)] = j * nx + i;
     else if (owned) stg(P.mix_slot + (j * nx + i), -1);
   }
   __syncthreads();
-  // one global list position range per tile
+  // the tile's mixed cells join the problem's compact list (their interface
+  // work runs in the mixed-cell kernel, spread over the whole device)
   if (tid == 0) s_mixbase = s_nmix ? atomicAdd(&S.nmix, s_nmix) : 0;
+  __syncthreads();
+  for (int kk = tid; kk < s_nmix; kk += NTHREADS) {
+    const int q = s_mix[kk], pos = s_mixbase + kk;
+    if (pos < P.mix_cap) {
+      stg(P.mix_cell + pos, q);
+      stg(P.mix_slot + q, pos);
+    } else {
+      stg(P.mix_slot + q, -1);
+      atomicOr(&P.ctl->err, ERR_MIXCAP);
+    }
+  }
 
   // ---- stage 2: nodal mass, gradient of P+Q, u^{n+1/2}, u^{lag}
   for (int l = tid; l < NW * NH; l += NTHREADS) {
@@ -439,28 +451,6 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
       }
     }
   }
-  // ---- stage 4: VOF partial volumes of the tile's mixed cells (FP64),
-  // eight lanes per cell, one per flux region
-  const int nmix = s_nmix;
-  for (int kk = tid / 8; kk < nmix; kk += NTHREADS / 8) {
-    const int loc = s_mix[kk], a = loc % TX, b = loc / TX;
-    const int i = I0 + a, j = J0 + b, q = j * nx + i;
-    const int pos = s_mixbase + kk;
-    const bool ok = pos < P.mix_cap;
-    if (ok)
-      mixed_region_partials<R, NM>(P, Vs, i, j, tid % 8, sdx[b][a], sdy[b][a], sdx[b][a + 1],
-                                   sdy[b][a + 1], sdx[b + 1][a], sdy[b + 1][a], sdx[b + 1][a + 1],
-                                   sdy[b + 1][a + 1], P.mix_W + (size_t)pos * 8 * NM);
-    if (tid % 8 == 0) {
-      if (ok) {
-        stg(P.mix_cell + pos, q);
-        stg(P.mix_slot + q, pos);
-      } else {
-        stg(P.mix_slot + q, -1);
-        atomicOr(&P.ctl->err, ERR_MIXCAP);
-      }
-    }
-  }
 }
 
 // one block per tile of the map (LOOP false: grid = map), or a grid smaller
@@ -476,6 +466,38 @@ __global__ void __launch_bounds__(NTHREADS) k_lagrange(const Prob<R> *probs, con
     }
   } else {
     if (blockIdx.x < nmap) lagrange_tile<R, NM>(probs, map[blockIdx.x], gpar);
+  }
+}
+
+// =========================================================== k_mixed
+// VOF partial volumes of the mixed cells (§4.4), FP64, eight lanes per cell
+// (one per flux region of the cell).  Block (x, y) takes problem plist[y]'s
+// compact list of mixed cells (built by the Lagrange kernel) from entry
+// 32x on, strided by 32 gridDim.x: the interface work of a problem is spread
+// over the whole device instead of the tiles that hold its interfaces.  The
+// node displacements are re-formed from the stored u^{n+1/2}.  Separate from
+// the Lagrange kernel, whose occupancy the FP64 interface arithmetic would
+// halve.
+template <typename R, int NM>
+__global__ void __launch_bounds__(NTHREADS) k_mixed(const Prob<R> *probs, const int *plist, int gpar) {
+  const Prob<R> &P = probs[plist[blockIdx.y]];
+  const Grid &g = P.g;
+  const int par = gpar ^ P.flip;
+  Slot &S = P.ctl->slot[par];
+  if (ldg(&S.done) || ldg(&P.ctl->err)) return;
+  const int nmix = min(ldg(&S.nmix), P.mix_cap);
+  if ((int)blockIdx.x * (NTHREADS / 8) >= nmix) return;
+  const int nx = g.nx, tid = threadIdx.x;
+  const R *Vs = P.V[par];
+  bool last;
+  const R dt = R(slot_dt(g, S, last));
+  for (int w = blockIdx.x * (NTHREADS / 8) + tid / 8; w < nmix; w += gridDim.x * (NTHREADS / 8)) {
+    const int q = ldg(P.mix_cell + w), i = q % nx, j = q / nx;
+    const int bl = j * (nx + 1) + i, br = bl + 1, tl = bl + nx + 1, tr = tl + 1;
+    mixed_region_partials<R, NM>(P, Vs, i, j, tid % 8, dt * ldg(P.uhx + bl), dt * ldg(P.uhy + bl),
+                                 dt * ldg(P.uhx + br), dt * ldg(P.uhy + br), dt * ldg(P.uhx + tl),
+                                 dt * ldg(P.uhy + tl), dt * ldg(P.uhx + tr), dt * ldg(P.uhy + tr),
+                                 P.mix_W + (size_t)w * 8 * NM);
   }
 }
 
@@ -1488,8 +1510,8 @@ __global__ void k_start(Ctl *ctl, double t_end, long long max_steps) {
 }
 
 // ------------------------------------------------------------ kernel table
-constexpr int kKernels = 3;
-const char *const kKernelNames[kKernels] = {"k_lagrange", "k_remap", "k_dual"};
+constexpr int kKernels = 4;
+const char *const kKernelNames[kKernels] = {"k_lagrange", "k_mixed", "k_remap", "k_dual"};
 
 // one step's launches: the block maps of node and cell tiles of every
 // problem; `persistent` limits each grid to the blocks the device holds at
@@ -1498,18 +1520,22 @@ struct Launch {
   const void *probs;
   const BlockMap *node_map, *cell_map;
   int node_blocks, cell_blocks;
+  const int *plist;  // the problems of the launch (for the mixed-cell kernel)
+  int nprob;
+  int mix_chunks;    // blocks per problem of the mixed-cell kernel
   bool persistent;
 };
 
 template <typename R, int NM>
 struct Resident {  // blocks of each step kernel resident on the whole device
-  int n[kKernels] = {0, 0, 0};
+  int n[kKernels] = {0, 0, 0, 0};
   Resident() {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return;
     const void *fn[kKernels] = {reinterpret_cast<const void *>(&k_lagrange<R, NM, true>),
+                                reinterpret_cast<const void *>(&k_mixed<R, NM>),
                                 reinterpret_cast<const void *>(&k_remap<R, NM, true>),
                                 reinterpret_cast<const void *>(&k_dual<R, NM, true>)};
     for (int k = 0; k < kKernels; ++k) {
@@ -1519,6 +1545,14 @@ struct Resident {  // blocks of each step kernel resident on the whole device
     }
   }
 };
+
+// blocks per problem of the mixed-cell kernel: one 32-cell group per block
+// for up to C/1024 groups (mixed cells are a small fraction of the cells);
+// each block strides over the rest
+inline int mix_chunks_for(long long cells) {
+  const long long c = cells / 1024;
+  return (int)(c < 16 ? 16 : (c > 1024 ? 1024 : c));
+}
 
 template <typename R, int NM>
 const Resident<R, NM> &resident() {
@@ -1544,23 +1578,25 @@ void step_impl(const Launch &L, int gpar, hipStream_t s, hipEvent_t *ev) {
   auto mark = [&](int k) {
     if (ev) (void)hipEventRecord(ev[k], s);
   };
-  const bool loop = L.persistent && res.n[0] > 0 && res.n[1] > 0 && res.n[2] > 0;
+  const bool loop = L.persistent && res.n[0] > 0 && res.n[1] > 0 && res.n[2] > 0 && res.n[3] > 0;
   mark(0);
   if (loop)
     k_lagrange<R, NM, true><<<grid(0, L.node_blocks), NTHREADS, 0, s>>>(p, L.node_map, L.node_blocks, gpar);
   else
     k_lagrange<R, NM, false><<<L.node_blocks, NTHREADS, 0, s>>>(p, L.node_map, L.node_blocks, gpar);
   mark(1);
-  if (loop)
-    k_remap<R, NM, true><<<grid(1, L.cell_blocks), NTHREADS, 0, s>>>(p, L.cell_map, L.cell_blocks, gpar);
-  else
-    k_remap<R, NM, false><<<L.cell_blocks, NTHREADS, 0, s>>>(p, L.cell_map, L.cell_blocks, gpar);
+  k_mixed<R, NM><<<dim3(L.mix_chunks, L.nprob), NTHREADS, 0, s>>>(p, L.plist, gpar);
   mark(2);
   if (loop)
-    k_dual<R, NM, true><<<grid(2, L.node_blocks), NTHREADS, 0, s>>>(p, L.node_map, L.node_blocks, gpar);
+    k_remap<R, NM, true><<<grid(2, L.cell_blocks), NTHREADS, 0, s>>>(p, L.cell_map, L.cell_blocks, gpar);
+  else
+    k_remap<R, NM, false><<<L.cell_blocks, NTHREADS, 0, s>>>(p, L.cell_map, L.cell_blocks, gpar);
+  mark(3);
+  if (loop)
+    k_dual<R, NM, true><<<grid(3, L.node_blocks), NTHREADS, 0, s>>>(p, L.node_map, L.node_blocks, gpar);
   else
     k_dual<R, NM, false><<<L.node_blocks, NTHREADS, 0, s>>>(p, L.node_map, L.node_blocks, gpar);
-  mark(3);
+  mark(4);
 }
 using StepFn = void (*)(const Launch &, int, hipStream_t, hipEvent_t *);
 template <typename R>
