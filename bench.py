@@ -17,14 +17,18 @@ memory.  The same JSON line carries
       (grids 128^2..1024^2, FP32, t_end 0.25) served with continuous
       batching; p50/p99 latency from arrival to result fields on the host;
   "roofline": the dominant kernel of the plain step, its algorithmic bytes
-      per launch over its average duration measured with HIP event pairs on
-      the kernel's own stream;
+      per launch over its average duration, measured with start/stop HIP
+      events recorded by each launch's dispatch on the kernel's stream;
+      "traffic" is the HBM bytes per launch that rocprofv3 counted for the
+      same kernel sources (profiles/), else null;
   "cpu_baseline": the FP64 oracle timed on a bounded sample of the plain
       workload on the host (one thread).
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -33,6 +37,32 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 W64 = 8
+KERNEL_SOURCES = ("paper_2208_13409_amd/csrc/lr_kernels.hip", "paper_2208_13409_amd/csrc/lr_device.hpp")
+
+
+def kernel_sources_sha256():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counted_traffic(kernel, workload, precision):
+    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE and
+    WRITE_SIZE passes recorded in profiles/<kernel>_<workload>_<precision>.md
+    (each scaled by what the counter reads for a device copy of known size),
+    or None when there is no record or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def kernel_bytes(nx, ny, nmat, w=W64):
@@ -234,7 +264,8 @@ def main():
                    "t_start": 0.0, "cfl": 0.5},
         "gpu_event_ms_per_step": gpu_ms / n,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": counted_traffic(dom, p["name"], args.precision),
                      "algorithmic_bytes_per_launch": kb[dom], "avg_launch_us": avg_us[dom]},
         "roofline_step": {"bytes_per_cell_update": step_bytes(1, 1, nmat, w),
                           "achieved_GBs": step_bytes(nx, ny, nmat, w) / (wall / n) / 1e9,

@@ -137,8 +137,9 @@ int lr_totals(lr_ctx *c, double *out);
 int lr_debug_get(lr_ctx *c, const char *name, double *out);
 
 /* Kernel timing for benchmarks.  lr_profile(c, 1) makes every later step
- * record a HIP event pair around each of its kernel launches on the
- * context's stream; lr_profile_read adds up the elapsed milliseconds and the
+ * launch its kernels with a start/stop HIP event pair recorded by the
+ * dispatch itself on the context's stream (kernel execution time only);
+ * lr_profile_read adds up the elapsed milliseconds and the
  * launch counts per kernel into ms[n], counts[n] (n <= lr_kernel_count(), in
  * the order of lr_kernel_name(i)) and resets them.  Off by default. */
 int lr_profile(lr_ctx *c, int enable);

@@ -273,7 +273,8 @@ struct lr_ctx {
   bool have_state = false;
   std::string err;
   double *scratch = nullptr;  // staging for outputs
-  // kernel timing (lr_profile): event marks of the steps of one chunk
+  // kernel timing (lr_profile): a start/stop event pair per kernel of each
+  // step of one chunk
   bool prof = false;
   std::vector<hipEvent_t> ev;
   int prof_steps = 0;
@@ -353,8 +354,8 @@ int collect_profile(lr_ctx *c) {
   for (int st = 0; st < c->prof_steps; ++st)
     for (int k = 0; k < kKernels; ++k) {
       float ms = 0.0f;
-      hipEvent_t *e = &c->ev[(size_t)st * (kKernels + 1)];
-      HIP_CHECK(c, hipEventElapsedTime(&ms, e[k], e[k + 1]));
+      hipEvent_t *e = &c->ev[(size_t)st * 2 * kKernels];
+      HIP_CHECK(c, hipEventElapsedTime(&ms, e[2 * k], e[2 * k + 1]));
       c->prof_ms[k] += ms;
       c->prof_n[k] += 1;
     }
@@ -384,7 +385,7 @@ int run_steps(lr_ctx *c, double t_end, long long max_steps) {
     const long long n = left < kChunk ? left : kChunk;
     for (long long st = 0; st < n; ++st) {
       hipEvent_t *ev = nullptr;
-      if (c->prof && c->prof_steps < kChunk) ev = &c->ev[(size_t)c->prof_steps++ * (kKernels + 1)];
+      if (c->prof && c->prof_steps < kChunk) ev = &c->ev[(size_t)c->prof_steps++ * 2 * kKernels];
       c->step(L, gpar, c->stream, ev);
       gpar ^= 1;
     }
@@ -660,7 +661,7 @@ int lr_debug_get(lr_ctx *c, const char *name, double *out) {
 int lr_profile(lr_ctx *c, int enable) {
   if (!c) return LR_EINVAL;
   if (enable && c->ev.empty()) {
-    c->ev.resize((size_t)kChunk * (kKernels + 1));
+    c->ev.resize((size_t)kChunk * 2 * kKernels);
     for (auto &e : c->ev) HIP_CHECK(c, hipEventCreate(&e));
   }
   c->prof = enable != 0;

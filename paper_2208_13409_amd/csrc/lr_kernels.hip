@@ -26,6 +26,7 @@
 // The conserved state is double-buffered (the remap reads step n's buffer
 // while neighbouring tiles write step n+1's); everything is
 // structure-of-arrays, x fastest; walls are mirrored indices.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1570,33 +1571,31 @@ void warm_resident(int nmat) {
   }
 }
 
+// a kernel launch; with ev, a start/stop event pair recorded by the dispatch
+// itself (kernel time only, as a kernel trace reports it)
+template <typename K, typename... Args>
+void launch(K kernel, dim3 grid, hipStream_t s, hipEvent_t *ev, Args... args) {
+  if (ev) hipExtLaunchKernelGGL(kernel, grid, dim3(NTHREADS), 0, s, ev[0], ev[1], 0, args...);
+  else kernel<<<grid, NTHREADS, 0, s>>>(args...);
+}
+
+// one step: ev (optional) holds a start/stop pair per kernel
 template <typename R, int NM>
 void step_impl(const Launch &L, int gpar, hipStream_t s, hipEvent_t *ev) {
   const Resident<R, NM> &res = resident<R, NM>();
   const Prob<R> *p = static_cast<const Prob<R> *>(L.probs);
   auto grid = [&](int k, int n) { return (L.persistent && res.n[k] > 0 && res.n[k] < n) ? res.n[k] : n; };
-  auto mark = [&](int k) {
-    if (ev) (void)hipEventRecord(ev[k], s);
-  };
+  auto evk = [&](int k) { return ev ? ev + 2 * k : nullptr; };
   const bool loop = L.persistent && res.n[0] > 0 && res.n[1] > 0 && res.n[2] > 0 && res.n[3] > 0;
-  mark(0);
-  if (loop)
-    k_lagrange<R, NM, true><<<grid(0, L.node_blocks), NTHREADS, 0, s>>>(p, L.node_map, L.node_blocks, gpar);
-  else
-    k_lagrange<R, NM, false><<<L.node_blocks, NTHREADS, 0, s>>>(p, L.node_map, L.node_blocks, gpar);
-  mark(1);
-  k_mixed<R, NM><<<dim3(L.mix_chunks, L.nprob), NTHREADS, 0, s>>>(p, L.plist, gpar);
-  mark(2);
-  if (loop)
-    k_remap<R, NM, true><<<grid(2, L.cell_blocks), NTHREADS, 0, s>>>(p, L.cell_map, L.cell_blocks, gpar);
-  else
-    k_remap<R, NM, false><<<L.cell_blocks, NTHREADS, 0, s>>>(p, L.cell_map, L.cell_blocks, gpar);
-  mark(3);
-  if (loop)
-    k_dual<R, NM, true><<<grid(3, L.node_blocks), NTHREADS, 0, s>>>(p, L.node_map, L.node_blocks, gpar);
-  else
-    k_dual<R, NM, false><<<L.node_blocks, NTHREADS, 0, s>>>(p, L.node_map, L.node_blocks, gpar);
-  mark(4);
+  const BlockMap *nm = L.node_map, *cm = L.cell_map;
+  const int nb = L.node_blocks, cb = L.cell_blocks;
+  if (loop) launch(k_lagrange<R, NM, true>, dim3(grid(0, nb)), s, evk(0), p, nm, nb, gpar);
+  else launch(k_lagrange<R, NM, false>, dim3(nb), s, evk(0), p, nm, nb, gpar);
+  launch(k_mixed<R, NM>, dim3(L.mix_chunks, L.nprob), s, evk(1), p, L.plist, gpar);
+  if (loop) launch(k_remap<R, NM, true>, dim3(grid(2, cb)), s, evk(2), p, cm, cb, gpar);
+  else launch(k_remap<R, NM, false>, dim3(cb), s, evk(2), p, cm, cb, gpar);
+  if (loop) launch(k_dual<R, NM, true>, dim3(grid(3, nb)), s, evk(3), p, nm, nb, gpar);
+  else launch(k_dual<R, NM, false>, dim3(nb), s, evk(3), p, nm, nb, gpar);
 }
 using StepFn = void (*)(const Launch &, int, hipStream_t, hipEvent_t *);
 template <typename R>
