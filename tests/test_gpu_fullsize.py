@@ -1,0 +1,171 @@
+"""Parity at the benchmark sizes, in the launch configurations bench.py times.
+
+* Triple point 1792x768: the GPU runs the problem to a developed state (shock
+  past the material boundaries, mixed cells along them); from that state a
+  fresh GPU context (FP64, then FP32) and the FP64 oracle take two steps each
+  and are compared element by element (FP64: 1e-9 scaled, L1 1e-10; FP32:
+  relative L1 of density and pressure 1e-4).
+* The same problem in FP32 against FP64 on the GPU over a longer window:
+  relative L1 of density and pressure and the per-material mass drift of the
+  FP32 run are printed and bounded.
+* The 256-problem shock-bubble batch stepped exactly as the benchmark steps it
+  (one launch per kernel over all problems, graph replay, chunks of 8):
+  sampled problems against the oracle, and per-material mass conservation of
+  every problem.
+* The largest serving request (1024^2 four-quadrant, FP32) against the oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import RefSolver
+from paper_2208_13409_amd import inputs
+from paper_2208_13409_amd.lr import LR_FP32, LR_FP64, Batch, Solver
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l1(a, b):
+    return np.abs(a - b).sum() / max(np.abs(b).sum(), 1e-300)
+
+
+def developed_state(p, steps):
+    """run the problem on the GPU (FP64) and hand back its state as the
+    (k, rho, e, ux, uy) arrays of a fresh start; materials whose partial
+    density is not positive in a cell are dropped there and the fractions
+    renormalised (both sides get the same arrays)"""
+    g = Solver(p["nx"], p["ny"], p["gammas"], p["domain"])
+    g.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+    n, t = g.run(1e30, max_steps=steps)
+    f = g.fields("k", "rho_a", "e_a", "ux", "uy")
+    k, rho, e = f["k"], f["rho_a"], f["e_a"]
+    keep = (k > 1e-12) & (rho > 0) & (e >= 0)
+    k = np.where(keep, k, 0.0)
+    k = k / k.sum(0, keepdims=True)
+    rho, e = np.where(keep, rho, 0.0), np.where(keep, e, 0.0)
+    g.close()
+    return t, dict(p, k=k, rho=rho, e=e, ux=f["ux"], uy=f["uy"])
+
+
+@pytest.fixture(scope="module")
+def tp4():
+    p = inputs.triple_point(4)
+    say("triple point 1792x768: developing the state on the GPU (300 steps)")
+    return developed_state(p, 300)
+
+
+def test_triple_point_1792x768_fp64_two_steps_vs_oracle(tp4):
+    t0, q = tp4
+    g = Solver(q["nx"], q["ny"], q["gammas"], q["domain"])
+    r = RefSolver(q["nx"], q["ny"], q["gammas"], q["domain"])
+    for s in (g, r):
+        s.set_state(t0, q["k"], q["rho"], q["e"], q["ux"], q["uy"])
+    say("1792x768 FP64: two steps on the GPU and in the oracle")
+    ng, tg = g.run(1e30, max_steps=2)
+    nr, tr = r.run(1e30, max_steps=2)
+    assert ng == nr == 2 and tg == pytest.approx(tr, rel=1e-12)
+    fg = g.fields("vol", "mass", "ie", "ux", "uy", "rho", "p")
+    fr = r.fields("vol", "mass", "ie", "ux", "uy", "rho", "p")
+    for key in ("vol", "mass", "ie"):
+        for a in range(fr[key].shape[0]):
+            scale = max(np.abs(fr[key][a]).max(), 1e-300)
+            err = np.abs(fg[key][a] - fr[key][a]).max() / scale
+            assert err <= 1e-9, f"{key}[{a}] {err:.2e}"
+    us = max(np.abs(fr["ux"]).max(), np.abs(fr["uy"]).max())
+    assert np.abs(fg["ux"] - fr["ux"]).max() <= 1e-9 * us
+    assert np.abs(fg["uy"] - fr["uy"]).max() <= 1e-9 * us
+    assert rel_l1(fg["rho"], fr["rho"]) <= 1e-10 and rel_l1(fg["p"], fr["p"]) <= 1e-10
+    mixed = ((fr["vol"] > 1e-10 * (3.0 / 768) ** 2).sum(0) >= 2).sum()
+    say(f"  {mixed} mixed cells in the compared state")
+    assert mixed > 100
+
+
+def test_triple_point_1792x768_fp32_two_steps_vs_oracle(tp4):
+    t0, q = tp4
+    g = Solver(q["nx"], q["ny"], q["gammas"], q["domain"], precision=LR_FP32, k_eps=1e-6)
+    r = RefSolver(q["nx"], q["ny"], q["gammas"], q["domain"], k_eps=1e-6)
+    for s in (g, r):
+        s.set_state(t0, q["k"], q["rho"], q["e"], q["ux"], q["uy"])
+    say("1792x768 FP32: two steps on the GPU, FP64 oracle")
+    g.run(1e30, max_steps=2)
+    r.run(1e30, max_steps=2)
+    fg, fr = g.fields("rho", "p"), r.fields("rho", "p")
+    l1r, l1p = rel_l1(fg["rho"], fr["rho"]), rel_l1(fg["p"], fr["p"])
+    say(f"  L1 rho {l1r:.2e} p {l1p:.2e}")
+    assert l1r <= 1e-4 and l1p <= 1e-4
+
+
+def test_triple_point_1792x768_fp32_vs_fp64_window():
+    """FP32 against FP64 on the GPU over 400 steps from t = 0: the FP32
+    error report of the large triple point (relative L1 of density and
+    pressure, per-material mass drift of the FP32 run)."""
+    p = inputs.triple_point(4)
+    runs = {}
+    for prec in (LR_FP64, LR_FP32):
+        g = Solver(p["nx"], p["ny"], p["gammas"], p["domain"], precision=prec,
+                   k_eps=1e-6 if prec == LR_FP32 else 1e-10)
+        g.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+        m0 = g.totals()[3:6].copy()
+        n, t = g.run(1e30, max_steps=400)
+        runs[prec] = (g.fields("rho", "p"), g.totals()[3:6], m0, t)
+    f64, f32 = runs[LR_FP64][0], runs[LR_FP32][0]
+    l1r, l1p = rel_l1(f32["rho"], f64["rho"]), rel_l1(f32["p"], f64["p"])
+    m1, m0 = runs[LR_FP32][1], runs[LR_FP32][2]
+    drift = np.abs(m1 - m0) / m0
+    say(f"1792x768 FP32 vs FP64 after 400 steps (t {runs[LR_FP64][3]:.4f}): L1 rho {l1r:.2e} "
+        f"p {l1p:.2e}; FP32 per-material mass drift {drift}")
+    assert l1r <= 1e-3 and l1p <= 1e-3
+    assert np.all(drift <= 1e-6)
+
+
+def test_batch_in_bench_configuration():
+    probs = inputs.shock_bubble_batch(256)
+    probe = Batch(nmat=2, precision=LR_FP32, max_slots=1, pool_bytes=1 << 20)
+    pool = sum(probe.footprint(p["nx"], p["ny"]) for p in probs) + (64 << 20)
+    probe.close()
+    b = Batch(nmat=2, precision=LR_FP32, max_slots=256, pool_bytes=pool, chunk_steps=8,
+              use_graph=True, persistent=False)
+    say("shock-bubble batch of 256, FP32, 16 steps in 2 graph-replayed chunks")
+    ids = [b.submit(p, 1e30, max_steps=16, k_eps=1e-6) for p in probs]
+    m0 = [b.totals(i)[2:4].copy() for i in ids]
+    while b.step() > 0:
+        pass
+    for i, rid in enumerate(ids):
+        rc, st, _ = b.status(rid)
+        assert rc == 0 and st == 16
+        m1 = b.totals(rid)[2:4]
+        assert np.all(np.abs(m1 - m0[i]) <= 1e-6 * m0[i]), (i, m0[i], m1)
+    # sampled problems (one of each grid of the ladder present) against the oracle
+    seen = {}
+    for i, p in enumerate(probs):
+        seen.setdefault((p["nx"], p["ny"]), i)
+    for (nx, ny), i in sorted(seen.items())[:4]:
+        p = probs[i]
+        r = RefSolver(nx, ny, p["gammas"], p["domain"], k_eps=1e-6)
+        r.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+        r.run(1e30, max_steps=16)
+        fb, fr = b.fields(ids[i], "rho", "p"), r.fields("rho", "p")
+        l1r, l1p = rel_l1(fb["rho"], fr["rho"]), rel_l1(fb["p"], fr["p"])
+        say(f"  problem {i} ({nx}x{ny}): L1 rho {l1r:.2e} p {l1p:.2e}")
+        assert l1r <= 1e-4 and l1p <= 1e-4
+
+
+def test_largest_serving_request_vs_oracle():
+    p = inputs.four_quadrant(inputs.BASE_SEED, n=1024)
+    g = Solver(p["nx"], p["ny"], p["gammas"], p["domain"], precision=LR_FP32, k_eps=1e-6)
+    r = RefSolver(p["nx"], p["ny"], p["gammas"], p["domain"], k_eps=1e-6)
+    for s in (g, r):
+        s.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+    say("four-quadrant 1024^2 FP32: three steps on the GPU and in the oracle")
+    g.run(1e30, max_steps=3)
+    r.run(1e30, max_steps=3)
+    fg, fr = g.fields("rho", "p"), r.fields("rho", "p")
+    l1r, l1p = rel_l1(fg["rho"], fr["rho"]), rel_l1(fg["p"], fr["p"])
+    say(f"  L1 rho {l1r:.2e} p {l1p:.2e}")
+    assert l1r <= 1e-4 and l1p <= 1e-4
