@@ -78,6 +78,11 @@ struct Prob {
 struct BlockMap {
   int prob, i0, j0, n;  // n: blocks of this problem (list kernels)
 };
+// entry b of a block map, read through the constant address space
+__device__ __forceinline__ BlockMap map_entry(const BlockMap *map, int b) {
+  const auto &m = *(const __attribute__((address_space(4))) BlockMap *)(map + b);
+  return BlockMap{m.prob, m.i0, m.j0, m.n};
+}
 
 // ---------------------------------------------------------------- memory
 // Loads and stores through the arrays of a problem descriptor.  The pointers
@@ -91,6 +96,13 @@ __device__ __forceinline__ T ldg(const T *p) {
 template <typename T>
 __device__ __forceinline__ void stg(T *p, T v) {
   *(__attribute__((address_space(1))) T *)p = v;
+}
+// Problem descriptors and block maps do not change during a launch: read
+// through the constant address space they become scalar loads, kept in
+// scalar registers instead of being re-read by every lane after each barrier.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *cst(const T *p) {
+  return (const __attribute__((address_space(4))) T *)p;
 }
 
 // ---------------------------------------------------------------- arithmetic
@@ -302,7 +314,8 @@ __device__ __forceinline__ void block_min_to_slot(unsigned long long cand, Slot 
 
 // (called by all 64 lanes of every wave: lane k reads partial k % NDT and
 // the wave combines them with shuffles)
-__device__ __forceinline__ double slot_dt(const Grid &g, const Slot &s, bool &last) {
+template <typename GridT>
+__device__ __forceinline__ double slot_dt(const GridT &g, const Slot &s, bool &last) {
   unsigned long long b = ldg(&s.dtmin[__lane_id() % NDT]);
 #pragma unroll
   for (int o = NDT / 2; o > 0; o >>= 1) {

@@ -44,8 +44,8 @@ using namespace lr;
 
 namespace {
 
-template <typename R>
-__device__ __forceinline__ bool present(const Grid &g, R V) {
+template <typename GridT, typename R>
+__device__ __forceinline__ bool present(const GridT &g, R V) {
   return double(V) > g.k_eps * g.A;
 }
 
@@ -77,11 +77,11 @@ struct Acc<double> {
 // the Lagrangian faces, intersection with the region's rectangle, then the
 // donor-side clipping (group sums by shuffles).  d*: node displacements in the
 // bulk precision, exactly as the remap kernel forms them.
-template <typename R, int NM>
-__device__ void mixed_region_partials(const Prob<R> &P, const R *Vs, int i, int j, int s, R blx_r,
+template <typename R, int NM, typename ProbT>
+__device__ void mixed_region_partials(const ProbT &P, const R *Vs, int i, int j, int s, R blx_r,
                                       R bly_r, R brx_r, R bry_r, R tlx_r, R tly_r, R trx_r,
                                       R try_r, double *Wout) {
-  const Grid &g = P.g;
+  const auto &g = P.g;
   const int nx = g.nx, ny = g.ny, C = nx * ny, q = j * nx + i;
   CellRegions<R> rr;
   cell_regions<R>(R(g.dx), R(g.dy), blx_r, bly_r, brx_r, bry_r, tlx_r, tly_r, trx_r, try_r, rr);
@@ -261,8 +261,8 @@ __device__ void mixed_region_partials(const Prob<R> &P, const R *Vs, int i, int 
 // =========================================================== k_lagrange
 template <typename R, int NM>
 __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockMap bm, int gpar) {
-  const Prob<R> &P = probs[bm.prob];
-  const Grid &g = P.g;
+  const auto &P = *cst(probs + bm.prob);
+  const auto &g = P.g;
   const int par = gpar ^ P.flip;
   Slot &S = P.ctl->slot[par];
   if (ldg(&S.done) || ldg(&P.ctl->err)) return;
@@ -462,11 +462,11 @@ __global__ void __launch_bounds__(NTHREADS) k_lagrange(const Prob<R> *probs, con
                                                   int nmap, int gpar) {
   if constexpr (LOOP) {
     for (int b = blockIdx.x; b < nmap; b += gridDim.x) {
-      lagrange_tile<R, NM>(probs, map[b], gpar);
+      lagrange_tile<R, NM>(probs, map_entry(map, b), gpar);
       __syncthreads();  // the next tile reuses the LDS
     }
   } else {
-    if (blockIdx.x < nmap) lagrange_tile<R, NM>(probs, map[blockIdx.x], gpar);
+    if (blockIdx.x < nmap) lagrange_tile<R, NM>(probs, map_entry(map, blockIdx.x), gpar);
   }
 }
 
@@ -481,8 +481,8 @@ __global__ void __launch_bounds__(NTHREADS) k_lagrange(const Prob<R> *probs, con
 // halve.
 template <typename R, int NM>
 __global__ void __launch_bounds__(NTHREADS) k_mixed(const Prob<R> *probs, const int *plist, int gpar) {
-  const Prob<R> &P = probs[plist[blockIdx.y]];
-  const Grid &g = P.g;
+  const auto &P = *cst(probs + *cst(plist + blockIdx.y));
+  const auto &g = P.g;
   const int par = gpar ^ P.flip;
   Slot &S = P.ctl->slot[par];
   if (ldg(&S.done) || ldg(&P.ctl->err)) return;
@@ -554,8 +554,8 @@ template <typename R, int NM>
 __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap bm, int gpar) {
   using SH = RemapShared<R, NM>;
   __shared__ SH sh;
-  const Prob<R> &P = probs[bm.prob];
-  const Grid &g = P.g;
+  const auto &P = *cst(probs + bm.prob);
+  const auto &g = P.g;
   Ctl *ctl = P.ctl;
   const int par = gpar ^ P.flip;
   const Slot &S = ctl->slot[par];
@@ -565,13 +565,62 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
     if (i0 == 0 && j0 == 0 && tid == 0) stg(&ctl->slot[par ^ 1].done, 1);
     return;
   }
-  bool last;
-  const double dtd = slot_dt(g, S, last);
-  const R dt = R(dtd);
   const int nx = g.nx, ny = g.ny, C = nx * ny;
   const R Dx = R(g.dx), Dy = R(g.dy), A = R(g.A);
   const R *Vs = P.V[par], *Ms = P.M[par];
   R *Vd = P.V[par ^ 1], *Md = P.M[par ^ 1], *Ed = P.E[par ^ 1];
+
+  // Global loads issued before any is used (one memory latency for several
+  // phases): u^{n+1/2} of the staged nodes (P1), the owned cell's V, M (P6)
+  // and, in FP32 where the registers allow it, the records' V, M, e^{lag} (P3).
+  constexpr int NIT1 = (SH::NNX * SH::NNY + NTHREADS - 1) / NTHREADS;
+  constexpr int NIT3 = (SH::NCX * SH::NCY + NTHREADS - 1) / NTHREADS;
+  constexpr bool PRE3 = sizeof(R) == 4;
+  R pre1[NIT1][2];
+#pragma unroll
+  for (int it = 0; it < NIT1; ++it) {
+    pre1[it][0] = pre1[it][1] = R(0);
+    const int l = tid + it * NTHREADS;
+    if (l >= SH::NNX * SH::NNY) continue;
+    const int I = i0 - 2 + l % SH::NNX, J = j0 - 2 + l / SH::NNX;
+    if (I > nx + 2 || J > ny + 2) continue;
+    const int p = refl_node(J, ny) * (nx + 1) + refl_node(I, nx);
+    pre1[it][0] = ldg(P.uhx + p);
+    pre1[it][1] = ldg(P.uhy + p);
+  }
+  const int a6 = tid % TX, b6 = tid / TX, i6 = i0 + a6, j6 = j0 + b6;
+  const bool own6 = i6 < nx && j6 < ny;
+  const int q6 = own6 ? j6 * nx + i6 : 0;
+  R V6[NM], M6[NM];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) {
+    V6[m] = own6 ? ldg(Vs + (m * C + q6)) : R(0);
+    M6[m] = own6 ? ldg(Ms + (m * C + q6)) : R(0);
+  }
+  R pre3[PRE3 ? NIT3 : 1][3 * NM];
+  // V, M, e^{lag} of record l (the real cell it mirrors)
+  auto fetch3 = [&](int l, R *out) {
+    const int i = i0 - 2 + l % SH::NCX, j = j0 - 2 + l / SH::NCX;
+    if (l >= SH::NCX * SH::NCY || i > nx + 1 || j > ny + 1) {
+#pragma unroll
+      for (int k = 0; k < 3 * NM; ++k) out[k] = R(0);
+      return;
+    }
+    const int q = refl_cell(j, ny) * nx + refl_cell(i, nx);
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      out[m] = ldg(Vs + (m * C + q));
+      out[NM + m] = ldg(Ms + (m * C + q));
+      out[2 * NM + m] = ldg(P.eL + (m * C + q));
+    }
+  };
+  if constexpr (PRE3) {
+#pragma unroll
+    for (int it = 0; it < NIT3; ++it) fetch3(tid + it * NTHREADS, pre3[it]);
+  }
+  bool last;
+  const double dtd = slot_dt(g, S, last);
+  const R dt = R(dtd);
 
   // the first tile of the problem prepares the next step's slot
   if (i0 == 0 && j0 == 0 && tid == 0) {
@@ -593,14 +642,16 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   auto NB = [&](int J) { return J - (j0 - 2); };
 
   // ---- P1: node displacements d = dt u^{n+1/2}, mirrored at walls
-  for (int l = tid; l < SH::NNX * SH::NNY; l += NTHREADS) {
+#pragma unroll
+  for (int it = 0; it < NIT1; ++it) {
+    const int l = tid + it * NTHREADS;
+    if (l >= SH::NNX * SH::NNY) continue;
     const int a = l % SH::NNX, b = l / SH::NNX;
     const int I = i0 - 2 + a, J = j0 - 2 + b;
     if (I > nx + 2 || J > ny + 2) continue;
-    const int rI = refl_node(I, nx), rJ = refl_node(J, ny), p = rJ * (nx + 1) + rI;
-    R dx = dt * ldg(P.uhx + p), dy = dt * ldg(P.uhy + p);
-    if (rI != I) dx = -dx;
-    if (rJ != J) dy = -dy;
+    R dx = dt * pre1[it][0], dy = dt * pre1[it][1];
+    if (refl_node(I, nx) != I) dx = -dx;
+    if (refl_node(J, ny) != J) dy = -dy;
     sh.ndx[b][a] = dx;
     sh.ndy[b][a] = dy;
   }
@@ -629,10 +680,20 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   __syncthreads();
 
   // ---- P3: cell records; ghost cells mirror the real ones
-  for (int l = tid; l < SH::NCX * SH::NCY; l += NTHREADS) {
+#pragma unroll
+  for (int it = 0; it < NIT3; ++it) {
+    const int l = tid + it * NTHREADS;
+    if (l >= SH::NCX * SH::NCY) continue;
     const int a = l % SH::NCX, b = l / SH::NCX;
     const int i = i0 - 2 + a, j = j0 - 2 + b;
     if (i > nx + 1 || j > ny + 1) continue;
+    R vme[3 * NM];
+    if constexpr (PRE3) {
+#pragma unroll
+      for (int k = 0; k < 3 * NM; ++k) vme[k] = pre3[it][k];
+    } else {
+      fetch3(l, vme);
+    }
     const int ri = refl_cell(i, nx), rj = refl_cell(j, ny), q = rj * nx + ri;
     const int na = NA(ri), nb = NB(rj);  // local node of the real cell's BL node
     const R blx = sh.ndx[nb][na], bly = sh.ndy[nb][na], brx = sh.ndx[nb][na + 1],
@@ -675,14 +736,14 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
     int np = 0, pm = -1;
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
-      const R V = ldg(Vs + (m * C + q)), M = ldg(Ms + (m * C + q));
+      const R V = vme[m], M = vme[NM + m];
       const bool pr = present(g, V);
       if (pr) {
         ++np;
         pm = m;
       }
       sh.rcf[m][b][a] = pr ? qdiv(M, qdiv(V, A) * v) : R(0);
-      sh.el[m][b][a] = ldg(P.eL + (m * C + q));
+      sh.el[m][b][a] = vme[2 * NM + m];
     }
     sh.pure[b][a] = np == 1 ? pm : -1;
     if (ri == i && rj == j && a >= 2 && b >= 2 && a < TX + 2 && b < TY + 2) {
@@ -935,9 +996,9 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       bool bad_nan = false;
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
-        const R M0 = ldg(Ms + (m * C + q));
+        const R M0 = M6[m];
         Acc<R> V, M, E;
-        V.init(qdiv(ldg(Vs + (m * C + q)), A) * v);
+        V.init(qdiv(V6[m], A) * v);
         M.init(M0);
         E.init(M0 * sh.el[m][cb][ca]);
 #pragma unroll
@@ -1008,11 +1069,11 @@ __global__ void __launch_bounds__(NTHREADS) k_remap(const Prob<R> *probs, const 
                                                   int nmap, int gpar) {
   if constexpr (LOOP) {
     for (int b = blockIdx.x; b < nmap; b += gridDim.x) {
-      remap_tile<R, NM>(probs, map[b], gpar);
+      remap_tile<R, NM>(probs, map_entry(map, b), gpar);
       __syncthreads();  // the next tile reuses the LDS
     }
   } else {
-    if (blockIdx.x < nmap) remap_tile<R, NM>(probs, map[blockIdx.x], gpar);
+    if (blockIdx.x < nmap) remap_tile<R, NM>(probs, map_entry(map, blockIdx.x), gpar);
   }
 }
 
@@ -1032,75 +1093,104 @@ struct DualShared {
   R fx[3][NXF], fy[3][NYF], fd[3][NCN], fa[3][NCN];
 };
 
-template <typename R>
-__device__ __forceinline__ R mflux_x(const Prob<R> &P, int I, int j) {
-  const int nx = P.g.nx, ny = P.g.ny;
-  R sg = R(1);
-  j = refl_cell(j, ny);
-  if (I < 0) { I = -I; sg = R(-1); }
-  else if (I > nx) { I = 2 * nx - I; sg = R(-1); }
-  if (I == 0 || I == nx) return R(0);
-  return sg * ldg(P.MX + (j * (nx + 1) + I));
-}
-template <typename R>
-__device__ __forceinline__ R mflux_y(const Prob<R> &P, int i, int J) {
-  const int nx = P.g.nx, ny = P.g.ny;
-  R sg = R(1);
-  i = refl_cell(i, nx);
-  if (J < 0) { J = -J; sg = R(-1); }
-  else if (J > ny) { J = 2 * ny - J; sg = R(-1); }
-  if (J == 0 || J == ny) return R(0);
-  return sg * ldg(P.MY + (J * nx + i));
-}
-// (main, anti) corner mass flux at node (I,J), I in [-1, nx+1], J in
-// [-1, ny+1], mirrored at walls; the kind comes from the real node's
-// displacement d = dt u^{n+1/2}
-template <typename R>
-__device__ __forceinline__ void corner_mu(const Prob<R> &P, R dt, int I, int J, R &dg, R &an) {
-  const int nx = P.g.nx, ny = P.g.ny;
-  bool fx = false, fy = false;
-  int rI = I, rJ = J;
-  if (rI < 0) { rI = -rI; fx = true; }
-  else if (rI > nx) { rI = 2 * nx - rI; fx = true; }
-  if (rJ < 0) { rJ = -rJ; fy = true; }
-  else if (rJ > ny) { rJ = 2 * ny - rJ; fy = true; }
-  dg = an = R(0);
-  if (rI == 0 || rI == nx || rJ == 0 || rJ == ny) return;
-  const int p = rJ * (nx + 1) + rI;
-  const R F = ldg(P.MC + p);
-  if (corner_main(dt * ldg(P.uhx + p), dt * ldg(P.uhy + p))) dg = F;
-  else an = F;
-  if (fy) { const R t = dg; dg = an; an = t; }
-  if (fx) { const R t = dg; dg = -an; an = -t; }
-}
-
 template <typename R, int NM>
 __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap bm, int gpar) {
   using SH = DualShared<R>;
   __shared__ SH sh;
-  const Prob<R> &P = probs[bm.prob];
-  const Grid &g = P.g;
+  const auto &P = *cst(probs + bm.prob);
+  const auto &g = P.g;
   Ctl *ctl = P.ctl;
   const int par = gpar ^ P.flip;
   const Slot &S = ctl->slot[par];
   const int tid = threadIdx.x;
   if (ldg(&S.done) || ldg(&ctl->err)) return;
-  bool last;
-  const R dt = R(slot_dt(g, S, last));
   const int nx = g.nx, ny = g.ny;
   const int I0 = bm.i0, J0 = bm.j0;
   const R Dx = R(g.dx), Dy = R(g.dy);
 
+  // The global loads of the owned node (stage 3) and of every staged item
+  // (stage 1) are issued before any of them is used, so that the block waits
+  // for memory once instead of once per stage and item.
+  const int a3 = tid % TX, b3 = tid / TX, I3 = I0 + a3, J3 = J0 + b3;
+  const bool own3 = I3 <= nx && J3 <= ny;
+  const int p3 = own3 ? J3 * (nx + 1) + I3 : 0;
+  R ux3 = R(0), uy3 = R(0), mp3 = R(0), ulx3 = R(0), uly3 = R(0), cs3[4];
+  if (own3) {
+    ux3 = ldg(P.ux + p3);
+    uy3 = ldg(P.uy + p3);
+    if (!g.kinematic) {
+      mp3 = ldg(P.mp + p3);
+      ulx3 = ldg(P.uLx + p3);
+      uly3 = ldg(P.uLy + p3);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int ci = I3 - 1 + (c & 1), cj = J3 - 1 + (c >> 1);
+    cs3[c] = (own3 && ci >= 0 && cj >= 0 && ci < nx && cj < ny) ? ldg(P.cs + (cj * nx + ci)) : R(0);
+  }
+  constexpr int NIT = (SH::NSTAGE + NTHREADS - 1) / NTHREADS;
+  constexpr int NNODE = SH::NX_ * SH::NY_, NPX = SH::PXW * SH::PXH, NPY = SH::PYW * SH::PYH;
+  R pre[NIT][4];
+  if (!g.kinematic) {
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      pre[it][0] = pre[it][1] = pre[it][2] = pre[it][3] = R(0);
+      const int l = tid + it * NTHREADS;
+      if (l >= SH::NSTAGE) continue;
+      if (l < NNODE) {  // node: u^{lag}, u^{n+1/2}
+        const int I = I0 - 2 + l % SH::NX_, J = J0 - 2 + l / SH::NX_;
+        if (I > nx + 2 || J > ny + 2) continue;
+        const int p = refl_node(J, ny) * (nx + 1) + refl_node(I, nx);
+        pre[it][0] = ldg(P.uLx + p);
+        pre[it][1] = ldg(P.uLy + p);
+        pre[it][2] = ldg(P.uhx + p);
+        pre[it][3] = ldg(P.uhy + p);
+      } else if (l < NNODE + NPX) {  // primal x-face mass flux
+        const int k = l - NNODE;
+        int I = I0 - 1 + k % SH::PXW;
+        const int j = J0 - 1 + k / SH::PXW;
+        if (I > nx + 1 || j > ny) continue;
+        I = I < 0 ? -I : (I > nx ? 2 * nx - I : I);
+        if (I == 0 || I == nx) continue;
+        pre[it][0] = ldg(P.MX + (refl_cell(j, ny) * (nx + 1) + I));
+      } else if (l < NNODE + NPX + NPY) {  // primal y-face mass flux
+        const int k = l - NNODE - NPX;
+        const int i = I0 - 1 + k % SH::PYW;
+        int J = J0 - 1 + k / SH::PYW;
+        if (i > nx || J > ny + 1) continue;
+        J = J < 0 ? -J : (J > ny ? 2 * ny - J : J);
+        if (J == 0 || J == ny) continue;
+        pre[it][0] = ldg(P.MY + (J * nx + refl_cell(i, nx)));
+      } else {  // corner mass flux and the node's displacement direction
+        const int k = l - NNODE - NPX - NPY;
+        const int I = I0 - 1 + k % SH::PCW, J = J0 - 1 + k / SH::PCW;
+        if (I > nx + 1 || J > ny + 1) continue;
+        const int rI = refl_node(I, nx), rJ = refl_node(J, ny);
+        if (rI == 0 || rI == nx || rJ == 0 || rJ == ny) continue;
+        const int p = rJ * (nx + 1) + rI;
+        pre[it][0] = ldg(P.MC + p);
+        pre[it][1] = ldg(P.uhx + p);
+        pre[it][2] = ldg(P.uhy + p);
+      }
+    }
+  }
+  bool last;
+  const R dt = R(slot_dt(g, S, last));
+
   if (!g.kinematic) {
     // ---- stage 1: node data and the primal mass fluxes around the tile,
-    // mirrored at walls, in one pass over all staged items
-    for (int l = tid; l < SH::NSTAGE; l += NTHREADS) {
-      if (l < SH::NX_ * SH::NY_) {
+    // mirrored at walls, from the loads issued above
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int l = tid + it * NTHREADS;
+      if (l >= SH::NSTAGE) continue;
+      if (l < NNODE) {
         const int a = l % SH::NX_, b = l / SH::NX_;
         const int I = I0 - 2 + a, J = J0 - 2 + b;
         if (I > nx + 2 || J > ny + 2) continue;
-        const int rI = refl_node(I, nx), rJ = refl_node(J, ny), p = rJ * (nx + 1) + rI;
-        R ulx = ldg(P.uLx + p), uly = ldg(P.uLy + p), dx = dt * ldg(P.uhx + p), dy = dt * ldg(P.uhy + p);
+        const int rI = refl_node(I, nx), rJ = refl_node(J, ny);
+        R ulx = pre[it][0], uly = pre[it][1], dx = dt * pre[it][2], dy = dt * pre[it][3];
         R X = R(rI) * Dx + dx, Y = R(rJ) * Dy + dy;
         if (rI != I) {
           ulx = -ulx;
@@ -1118,28 +1208,31 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
         sh.dy[b][a] = dy;
         sh.X[b][a] = X;
         sh.Y[b][a] = Y;
-        continue;
-      }
-      int k = l - SH::NX_ * SH::NY_;
-      if (k < SH::PXW * SH::PXH) {
+      } else if (l < NNODE + NPX) {
+        const int k = l - NNODE;
         const int a = k % SH::PXW, b = k / SH::PXW;
-        const int I = I0 - 1 + a, j = J0 - 1 + b;
-        sh.mx[b][a] = (I <= nx + 1 && j <= ny) ? mflux_x(P, I, j) : R(0);
-        continue;
-      }
-      k -= SH::PXW * SH::PXH;
-      if (k < SH::PYW * SH::PYH) {
+        const int I = I0 - 1 + a;
+        const R sg = (I < 0 || I > nx) ? R(-1) : R(1);  // a mirrored x-face flux changes sign
+        sh.mx[b][a] = sg * pre[it][0];
+      } else if (l < NNODE + NPX + NPY) {
+        const int k = l - NNODE - NPX;
         const int a = k % SH::PYW, b = k / SH::PYW;
-        const int i = I0 - 1 + a, J = J0 - 1 + b;
-        sh.my[b][a] = (i <= nx && J <= ny + 1) ? mflux_y(P, i, J) : R(0);
-        continue;
-      }
-      k -= SH::PYW * SH::PYH;
-      {
+        const int J = J0 - 1 + b;
+        const R sg = (J < 0 || J > ny) ? R(-1) : R(1);
+        sh.my[b][a] = sg * pre[it][0];
+      } else {
+        const int k = l - NNODE - NPX - NPY;
         const int a = k % SH::PCW, b = k / SH::PCW;
         const int I = I0 - 1 + a, J = J0 - 1 + b;
+        const bool fx = I < 0 || I > nx, fy = J < 0 || J > ny;
+        // (main, anti) pair: the kind from the real node's displacement,
+        // then the mirrors (x: (d, a) -> (-a, -d); y: (d, a) -> (a, d))
+        const R F = pre[it][0];
         R dg = R(0), an = R(0);
-        if (I <= nx + 1 && J <= ny + 1) corner_mu(P, dt, I, J, dg, an);
+        if (corner_main(dt * pre[it][1], dt * pre[it][2])) dg = F;
+        else an = F;
+        if (fy) { const R t = dg; dg = an; an = t; }
+        if (fx) { const R t = dg; dg = -an; an = -t; }
         sh.cd[b][a] = dg;
         sh.ca[b][a] = an;
       }
@@ -1244,18 +1337,18 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
   // ---- stage 3: nodal momentum update, CFL bound of the new state
   unsigned long long cand = ~0ull;
   {
-    const int a = tid % TX, b = tid / TX;
-    const int I = I0 + a, J = J0 + b;
-    if (I <= nx && J <= ny) {
-      const int p = J * (nx + 1) + I;
-      R ux = ldg(P.ux + p), uy = ldg(P.uy + p);
+    const int a = a3, b = b3;
+    const int I = I3, J = J3;
+    if (own3) {
+      const int p = p3;
+      R ux = ux3, uy = uy3;
       if (!g.kinematic) {
         const int hW = b * (TX + 1) + a, hE = hW + 1;
         const int hS = b * TX + a, hN = hS + TX;
         const int hSW = b * (TX + 1) + a, hNE = (b + 1) * (TX + 1) + a + 1;  // cells (I-1,J-1), (I,J)
         const int hNW = (b + 1) * (TX + 1) + a, hSE = b * (TX + 1) + a + 1;  // cells (I-1,J), (I,J-1)
-        R m = ldg(P.mp + p);
-        R mu = m * ldg(P.uLx + p), mv = m * ldg(P.uLy + p);
+        R m = mp3;
+        R mu = m * ulx3, mv = m * uly3;
         m += sh.fx[0][hW]; mu += sh.fx[1][hW]; mv += sh.fx[2][hW];
         m -= sh.fx[0][hE]; mu -= sh.fx[1][hE]; mv -= sh.fx[2][hE];
         m += sh.fy[0][hS]; mu += sh.fy[1][hS]; mv += sh.fy[2][hS];
@@ -1276,13 +1369,7 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
       // node-wise CFL bound: the largest sound speed of the adjacent cells
       R cmax = R(0);
 #pragma unroll
-      for (int bb = -1; bb <= 0; ++bb)
-#pragma unroll
-        for (int aa = -1; aa <= 0; ++aa) {
-          const int ci = I + aa, cj = J + bb;
-          if (ci < 0 || cj < 0 || ci >= nx || cj >= ny) continue;
-          cmax = fmax(cmax, ldg(P.cs + (cj * nx + ci)));
-        }
+      for (int c = 0; c < 4; ++c) cmax = fmax(cmax, cs3[c]);
       const double bound = fmin(double(Dx / (cmax + fabs(ux))), double(Dy / (cmax + fabs(uy))));
       cand = (unsigned long long)__double_as_longlong(bound);
     }
@@ -1298,11 +1385,11 @@ __global__ void __launch_bounds__(NTHREADS) k_dual(const Prob<R> *probs, const B
                                                   int nmap, int gpar) {
   if constexpr (LOOP) {
     for (int b = blockIdx.x; b < nmap; b += gridDim.x) {
-      dual_tile<R, NM>(probs, map[b], gpar);
+      dual_tile<R, NM>(probs, map_entry(map, b), gpar);
       __syncthreads();  // the next tile reuses the LDS
     }
   } else {
-    if (blockIdx.x < nmap) dual_tile<R, NM>(probs, map[blockIdx.x], gpar);
+    if (blockIdx.x < nmap) dual_tile<R, NM>(probs, map_entry(map, blockIdx.x), gpar);
   }
 }
 
