@@ -266,8 +266,6 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
   const int par = gpar ^ P.flip;
   Slot &S = P.ctl->slot[par];
   if (ldg(&S.done) || ldg(&P.ctl->err)) return;
-  bool last;
-  const R dt = R(slot_dt(g, S, last));
   const int nx = g.nx, ny = g.ny, C = nx * ny;
   const int I0 = bm.i0, J0 = bm.j0, tid = threadIdx.x;
   const R Dx = R(g.dx), Dy = R(g.dy), A = R(g.A);
@@ -275,28 +273,99 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
 
   constexpr int CW = TX + 2, CH = TY + 2;  // cells [I0-1, I0+TX] x [J0-1, J0+TY]
   constexpr int NW = TX + 1, NH = TY + 1;  // nodes [I0, I0+TX] x [J0, J0+TY]
+  constexpr int UW = TX + 3, UH = TY + 3;  // node velocities [I0-1, I0+TX+1] x [J0-1, J0+TY+1]
   __shared__ R sS[CH][CW], sMc[CH][CW], sQ[CH][CW];
   __shared__ R sPh[NM][CH][CW];
   __shared__ R sdx[NH][NW], sdy[NH][NW];
+  __shared__ R sux[UH][UW], suy[UH][UW];
   __shared__ int s_mix[NTHREADS];  // the tile's mixed cells (cell index)
   __shared__ int s_nmix, s_mixbase;
+
+  // Global loads issued before any is used: the node velocities of the tile
+  // (each once, into LDS), the cells' V, M, E (FP32, where the registers allow
+  // it) and the owned cell's V, M, E (corrector).
+  constexpr int NITU = (UW * UH + NTHREADS - 1) / NTHREADS;
+  constexpr int NITC = (CW * CH + NTHREADS - 1) / NTHREADS;
+  constexpr bool PREC = sizeof(R) == 4;
+  R preu[NITU][2];
+#pragma unroll
+  for (int it = 0; it < NITU; ++it) {
+    const int l = tid + it * NTHREADS;
+    const int I = I0 - 1 + l % UW, J = J0 - 1 + l / UW;
+    const bool ok = l < UW * UH && I >= 0 && J >= 0 && I <= nx && J <= ny;
+    preu[it][0] = ok ? ldg(P.ux + (J * (nx + 1) + I)) : R(0);
+    preu[it][1] = ok ? ldg(P.uy + (J * (nx + 1) + I)) : R(0);
+  }
+  // V, M, E of stage-1 cell l (the real cell it mirrors)
+  auto fetchc = [&](int l, R *out) {
+    const int i = I0 - 1 + l % CW, j = J0 - 1 + l / CW;
+    if (l >= CW * CH || i > nx || j > ny) {
+#pragma unroll
+      for (int k = 0; k < 3 * NM; ++k) out[k] = R(0);
+      return;
+    }
+    const int q = refl_cell(j, ny) * nx + refl_cell(i, nx);
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      out[m] = ldg(Vs + (m * C + q));
+      out[NM + m] = ldg(Ms + (m * C + q));
+      out[2 * NM + m] = ldg(Es + (m * C + q));
+    }
+  };
+  R prec[PREC ? NITC : 1][3 * NM];
+  if constexpr (PREC) {
+#pragma unroll
+    for (int it = 0; it < NITC; ++it) fetchc(tid + it * NTHREADS, prec[it]);
+  }
+  const int a3 = tid % TX, b3 = tid / TX, i3 = I0 + a3, j3 = J0 + b3;
+  const bool own3 = i3 < nx && j3 < ny;
+  const int q3 = own3 ? j3 * nx + i3 : 0;
+  R pre3[3 * NM];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) {
+    pre3[m] = own3 ? ldg(Vs + (m * C + q3)) : R(0);
+    pre3[NM + m] = own3 ? ldg(Ms + (m * C + q3)) : R(0);
+    pre3[2 * NM + m] = own3 ? ldg(Es + (m * C + q3)) : R(0);
+  }
+  bool last;
+  const R dt = R(slot_dt(g, S, last));
+
+#pragma unroll
+  for (int it = 0; it < NITU; ++it) {
+    const int l = tid + it * NTHREADS;
+    if (l >= UW * UH) continue;
+    sux[l / UW][l % UW] = preu[it][0];
+    suy[l / UW][l % UW] = preu[it][1];
+  }
   if (tid == 0) s_nmix = 0;
   __syncthreads();
+  // velocity of node (I, J) of the staged window
+  auto ux_at = [&](int I, int J) { return sux[J - (J0 - 1)][I - (I0 - 1)]; };
+  auto uy_at = [&](int I, int J) { return suy[J - (J0 - 1)][I - (I0 - 1)]; };
 
   // ---- stage 1: predictor per cell (ghost cells mirror the real ones)
-  for (int l = tid; l < CW * CH; l += NTHREADS) {
+#pragma unroll
+  for (int it = 0; it < NITC; ++it) {
+    const int l = tid + it * NTHREADS;
+    if (l >= CW * CH) continue;
     const int a = l % CW, b = l / CW;
     const int i = I0 - 1 + a, j = J0 - 1 + b;
     const bool owned = i >= I0 && j >= J0 && i < nx && j < ny && a <= TX && b <= TY;
     int np = 0;
     if (i <= nx && j <= ny) {
       const int ri = refl_cell(i, nx), rj = refl_cell(j, ny), q = rj * nx + ri;
-      const int bl = rj * (nx + 1) + ri, br = bl + 1, tl = bl + nx + 1, tr = tl + 1;
+      R vme[3 * NM];
+      if constexpr (PREC) {
+#pragma unroll
+        for (int k = 0; k < 3 * NM; ++k) vme[k] = prec[it][k];
+      } else {
+        fetchc(l, vme);
+      }
       R Msum = R(0), rc2 = R(0), k[NM], e[NM], rho[NM], Pa[NM], Mm[NM];
       bool pr[NM];
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
-        const R V = ldg(Vs + (m * C + q)), M = ldg(Ms + (m * C + q)), E = ldg(Es + (m * C + q));
+        const R V = vme[m], M = vme[NM + m], E = vme[2 * NM + m];
         Mm[m] = M;
         k[m] = qdiv(V, A);
         pr[m] = present(g, V);
@@ -313,13 +382,16 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
         const R rhoc = qdiv(Msum, A);
         const R c2 = rhoc > R(0) ? qdiv(rc2, rhoc) : R(0);
         const R cc = c2 > R(0) ? sqrt(c2) : R(0);
-        const R div = qdiv(ldg(P.ux + br) + ldg(P.ux + tr) - ldg(P.ux + bl) - ldg(P.ux + tl), R(2) * Dx) +
-                      qdiv(ldg(P.uy + tl) + ldg(P.uy + tr) - ldg(P.uy + bl) - ldg(P.uy + br), R(2) * Dy);
+        const R uxbl = ux_at(ri, rj), uxbr = ux_at(ri + 1, rj), uxtl = ux_at(ri, rj + 1),
+                uxtr = ux_at(ri + 1, rj + 1);
+        const R uybl = uy_at(ri, rj), uybr = uy_at(ri + 1, rj), uytl = uy_at(ri, rj + 1),
+                uytr = uy_at(ri + 1, rj + 1);
+        const R div = qdiv(uxbr + uxtr - uxbl - uxtl, R(2) * Dx) + qdiv(uytl + uytr - uybl - uybr, R(2) * Dy);
         const R L = sqrt(A);
         if (div < R(0)) Qc = rhoc * (R(g.a1) * L * cc * fabs(div) + R(g.a2) * L * L * div * div);
         const R h = R(0.5) * dt;
-        const R hblx = h * ldg(P.ux + bl), hbly = h * ldg(P.uy + bl), hbrx = h * ldg(P.ux + br), hbry = h * ldg(P.uy + br);
-        const R htlx = h * ldg(P.ux + tl), htly = h * ldg(P.uy + tl), htrx = h * ldg(P.ux + tr), htry = h * ldg(P.uy + tr);
+        const R hblx = h * uxbl, hbly = h * uybl, hbrx = h * uxbr, hbry = h * uybr;
+        const R htlx = h * uxtl, htly = h * uytl, htrx = h * uxtr, htry = h * uytr;
         R Pch = R(0);
         if constexpr (sizeof(R) == 8) {
           const R Vh = quad_area(hblx, hbly, Dx + hbrx, hbry, htlx, Dy + htly, Dx + htrx, Dy + htry);
@@ -389,7 +461,7 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
     const int p = J * (nx + 1) + I;
     const R mp = R(0.25) * (sMc[b][a] + sMc[b][a + 1] + sMc[b + 1][a] + sMc[b + 1][a + 1]);
     R uhx, uhy, uLx, uLy;
-    const R ux = ldg(P.ux + p), uy = ldg(P.uy + p);
+    const R ux = ux_at(I, J), uy = uy_at(I, J);
     if (g.kinematic) {
       uhx = uLx = ux;
       uhy = uLy = uy;
@@ -435,7 +507,7 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
       if (P.dbg.VL) stg(P.dbg.VL + q, sizeof(R) == 8 ? VL : A + dVL);
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
-        const R V = ldg(Vs + (m * C + q)), M = ldg(Ms + (m * C + q)), E = ldg(Es + (m * C + q));
+        const R V = pre3[m], M = pre3[NM + m], E = pre3[2 * NM + m];
         const R e = M > R(0) ? E / M : R(0);  // M may be a denormal trace: IEEE quotient
         R eL = e;
         if (!g.kinematic && present(g, V)) {
