@@ -78,6 +78,16 @@ struct Prob {
 struct BlockMap {
   int prob, i0, j0, n;  // n: blocks of this problem (list kernels)
 };
+// Workgroups are dispatched to the eight XCDs in turn (block b to XCD b % 8),
+// each XCD with its own L2.  Block b takes map entry xcd_tile(b, n) instead of
+// b, so that each XCD works through a contiguous run of the map and
+// neighbouring tiles, which read each other's halos, share an L2.  A
+// bijection of [0, n): XCD x gets entries [x q + min(x, r), ...) with
+// q = n / 8, r = n % 8, the first r XCDs one more.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7, k = b >> 3;
+  return x * q + (x < r ? x : r) + k;
+}
 // entry b of a block map, read through the constant address space
 __device__ __forceinline__ BlockMap map_entry(const BlockMap *map, int b) {
   const auto &m = *(const __attribute__((address_space(4))) BlockMap *)(map + b);

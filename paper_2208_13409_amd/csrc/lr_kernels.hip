@@ -538,7 +538,7 @@ __global__ void __launch_bounds__(NTHREADS) k_lagrange(const Prob<R> *probs, con
       __syncthreads();  // the next tile reuses the LDS
     }
   } else {
-    if (blockIdx.x < nmap) lagrange_tile<R, NM>(probs, map_entry(map, blockIdx.x), gpar);
+    if (blockIdx.x < nmap) lagrange_tile<R, NM>(probs, map_entry(map, xcd_tile(blockIdx.x, nmap)), gpar);
   }
 }
 
@@ -1145,7 +1145,7 @@ __global__ void __launch_bounds__(NTHREADS) k_remap(const Prob<R> *probs, const 
       __syncthreads();  // the next tile reuses the LDS
     }
   } else {
-    if (blockIdx.x < nmap) remap_tile<R, NM>(probs, map_entry(map, blockIdx.x), gpar);
+    if (blockIdx.x < nmap) remap_tile<R, NM>(probs, map_entry(map, xcd_tile(blockIdx.x, nmap)), gpar);
   }
 }
 
@@ -1461,7 +1461,7 @@ __global__ void __launch_bounds__(NTHREADS) k_dual(const Prob<R> *probs, const B
       __syncthreads();  // the next tile reuses the LDS
     }
   } else {
-    if (blockIdx.x < nmap) dual_tile<R, NM>(probs, map_entry(map, blockIdx.x), gpar);
+    if (blockIdx.x < nmap) dual_tile<R, NM>(probs, map_entry(map, xcd_tile(blockIdx.x, nmap)), gpar);
   }
 }
 
