@@ -11,8 +11,9 @@ memory.  The same JSON line carries
 
   "fp32_batched": 256 seeded two-material shock-bubble problems (grids from
       64x64 to 512x256) stepped together in FP32, every launch covering the
-      tiles of all problems, each chunk of steps replayed from a HIP graph,
-      over a fixed window of steps;
+      tiles of all problems, under the launch schedule the batch's autotuner
+      picked on the first chunks (persistent grid or not, graph replay or
+      not), over a fixed window of steps;
   "serving": a seeded Poisson stream of four-quadrant Riemann problems
       (grids 128^2..1024^2, FP32, t_end 0.25) served with continuous
       batching; p50/p99 latency from arrival to result fields on the host;
@@ -114,10 +115,13 @@ def batch_leg(n_problems, steps, chunk=8):
     pool = sum(probe.footprint(p["nx"], p["ny"]) for p in probs) + (64 << 20)
     probe.close()
     b = Batch(nmat=2, precision=LR_FP32, max_slots=len(probs), pool_bytes=pool, chunk_steps=chunk,
-              use_graph=True, persistent=False)
-    ids = [b.submit(p, 1e30, max_steps=chunk + steps, k_eps=1e-6) for p in probs]
+              autotune=True)
+    untimed = 5 * chunk  # four chunks timing the candidate schedules, one capturing the chosen one
+    ids = [b.submit(p, 1e30, max_steps=untimed + steps, k_eps=1e-6) for p in probs]
     assert all(i is not None for i in ids)
-    b.step()  # warm-up chunk (graph capture)
+    for _ in range(5):
+        b.step()
+    persistent, graph, rates = b.schedule()
     t0 = time.perf_counter()
     chunks = 0
     while b.step() > 0:
@@ -126,7 +130,7 @@ def batch_leg(n_problems, steps, chunk=8):
     chunks += 1
     for rid in ids:
         rc, st, _ = b.status(rid)
-        assert rc == 0 and st == chunk + steps, (rid, rc, st)
+        assert rc == 0 and st == untimed + steps, (rid, rc, st)
     cells = sum(p["nx"] * p["ny"] for p in probs)
     value = cells * steps / wall
     bpc = step_bytes(1, 1, 2, 4)
@@ -134,8 +138,10 @@ def batch_leg(n_problems, steps, chunk=8):
     return {"value": value, "unit": "cell-updates/s", "dtype": "f32",
             "workload": f"shock_bubble_batch_{len(probs)}", "problems": len(probs), "cells": cells,
             "steps": steps, "ms_per_step": wall * 1e3 / steps, "chunks": chunks,
-            "launch": "one block per tile of every problem in each launch, one HIP graph "
-                      f"per chunk of {chunk} steps",
+            "launch": ("persistent grids" if persistent else "one block per tile of every problem")
+                      + (f", one HIP graph per chunk of {chunk} steps" if graph else
+                         f", chunks of {chunk} steps launched directly"),
+            "autotuner_cell_steps_per_ms": [round(float(r), 1) for r in rates] if rates is not None else None,
             "hbm_bytes_per_cell_update": bpc, "achieved_GBs": value * bpc / 1e9,
             "frac_hbm": value * bpc / 1e9 / HBM_PEAK_GBS}
 

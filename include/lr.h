@@ -167,6 +167,10 @@ typedef struct {
   int use_graph;        /* 1: replay each chunk from a captured HIP graph        */
   int persistent;       /* 1: grids limited to the blocks resident on the device, each
                            block walking the tile list; 0 (default): one block per tile */
+  int autotune;         /* 1: the first four chunks run under the four schedules
+                           (persistent x use_graph), each timed on the device; the
+                           fastest per cell-step is kept (persistent and use_graph
+                           above are then ignored).  Results do not depend on it. */
 } lr_batch_opts;
 typedef struct lr_batch lr_batch;
 
@@ -199,6 +203,10 @@ int lr_batch_totals(lr_batch *b, long id, double *out);
 /* free the problem's slot and pool range */
 int lr_batch_release(lr_batch *b, long id);
 int lr_batch_running(lr_batch *b);
+/* the schedule in use; rates[4] (may be NULL) receives the cell-steps per ms
+ * the autotuner measured for schedules c = persistent + 2*use_graph.
+ * LR_EAGAIN while the autotuner is still timing. */
+int lr_batch_schedule(lr_batch *b, int *persistent, int *use_graph, double *rates);
 const char *lr_batch_last_error(const lr_batch *b);
 void lr_batch_destroy(lr_batch *b);
 

@@ -97,6 +97,12 @@ struct lr_batch {
   size_t scratch_n = 0;
   hipGraphExec_t gexec = nullptr;
   bool graph_ok = false;
+  // schedule autotuning: the first chunks run under each candidate schedule
+  // (persistent grid x graph replay), timed with events around the launches
+  static constexpr int kCand = 4;
+  int tune_next = 0;      // next candidate to time (kCand: done)
+  double tune_rate[kCand] = {0, 0, 0, 0};  // cell-steps per ms
+  hipEvent_t tune_ev[2] = {nullptr, nullptr};
   std::string err;
 };
 
@@ -231,9 +237,12 @@ int batch_chunk(lr_batch *b) {
   const Launch L{b->dprobs, b->node_map, b->cell_map, b->node_blocks, b->cell_blocks,
                  b->plist,  b->nprob,    b->mix_chunks, b->o.persistent != 0};
   const int n = b->o.chunk_steps;
+  const bool timed = b->o.autotune && b->tune_next < lr_batch::kCand;
   if (!b->o.use_graph) {
+    if (timed) HIP_B(b, hipEventRecord(b->tune_ev[0], b->stream));
     for (int st = 0; st < n; ++st) b->step(L, st & 1, b->stream, nullptr);
     HIP_B(b, hipGetLastError());
+    if (timed) HIP_B(b, hipEventRecord(b->tune_ev[1], b->stream));
     return LR_OK;
   }
   if (!b->graph_ok) {
@@ -253,8 +262,18 @@ int batch_chunk(lr_batch *b) {
     if (ei != hipSuccess) return bset(b, LR_EDEVICE, "graph instantiation failed");
     b->graph_ok = true;
   }
+  if (timed) HIP_B(b, hipEventRecord(b->tune_ev[0], b->stream));
   HIP_B(b, hipGraphLaunch(b->gexec, b->stream));
+  if (timed) HIP_B(b, hipEventRecord(b->tune_ev[1], b->stream));
   return LR_OK;
+}
+
+// candidate schedule c: bit 0 persistent grid, bit 1 graph replay
+void set_schedule(lr_batch *b, int c) {
+  const int pers = c & 1, graph = (c >> 1) & 1;
+  if (pers != b->o.persistent || graph != b->o.use_graph) b->graph_ok = false;
+  b->o.persistent = pers;
+  b->o.use_graph = graph;
 }
 
 int find_req(lr_batch *b, long id, BatchReq **q) {
@@ -278,6 +297,7 @@ void lr_batch_default_opts(lr_batch_opts *o) {
   o->chunk_steps = kChunk;
   o->use_graph = 1;
   o->persistent = 0;
+  o->autotune = 0;
 }
 
 void lr_batch_destroy(lr_batch *b) {
@@ -285,6 +305,8 @@ void lr_batch_destroy(lr_batch *b) {
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->stage_ev) (void)hipEventDestroy(b->stage_ev);
+  for (hipEvent_t e : b->tune_ev)
+    if (e) (void)hipEventDestroy(e);
   for (void *p : {(void *)b->pool, b->dprobs, (void *)b->ctl, (void *)b->node_map,
                   (void *)b->cell_map, (void *)b->dstage, (void *)b->scratch, (void *)b->plist})
     if (p) (void)hipFree(p);
@@ -315,7 +337,8 @@ int lr_batch_create(const lr_batch_opts *opts, lr_batch **out) {
   b->slots.resize(o.max_slots);
   int rc = LR_OK;
   if (hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&b->stage_ev, hipEventDisableTiming) != hipSuccess)
+      hipEventCreateWithFlags(&b->stage_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreate(&b->tune_ev[0]) != hipSuccess || hipEventCreate(&b->tune_ev[1]) != hipSuccess)
     rc = LR_EDEVICE;
   b->stream = b->own;
   if (rc == LR_OK && (hipMalloc((void **)&b->pool, b->o.pool_bytes) != hipSuccess ||
@@ -420,11 +443,29 @@ int lr_batch_step(lr_batch *b, int *n_running) {
   if (rc) return rc;
   int running = 0;
   if (b->node_blocks > 0) {
+    const bool timed = b->o.autotune && b->tune_next < lr_batch::kCand;
+    long long cells = 0;
+    if (timed) {
+      set_schedule(b, b->tune_next);
+      for (const auto &q : b->slots)
+        if (q.running) cells += (long long)q.g.nx * q.g.ny;
+    }
     rc = batch_chunk(b);
     if (rc) return rc;
     HIP_B(b, hipMemcpyAsync(b->hctl, b->ctl, sizeof(Ctl) * b->slots.size(), hipMemcpyDeviceToHost,
                             b->stream));
     HIP_B(b, hipStreamSynchronize(b->stream));
+    if (timed) {
+      float ms = 0.0f;
+      HIP_B(b, hipEventElapsedTime(&ms, b->tune_ev[0], b->tune_ev[1]));
+      b->tune_rate[b->tune_next] = ms > 0.0f ? double(cells) * b->o.chunk_steps / ms : 0.0;
+      if (++b->tune_next == lr_batch::kCand) {
+        int best = 0;
+        for (int c = 1; c < lr_batch::kCand; ++c)
+          if (b->tune_rate[c] > b->tune_rate[best]) best = c;
+        set_schedule(b, best);
+      }
+    }
     for (size_t s = 0; s < b->slots.size(); ++s) {
       BatchReq &q = b->slots[s];
       if (!q.running) continue;
@@ -511,6 +552,15 @@ int lr_batch_release(lr_batch *b, long id) {
   b->where.erase(id);
   *q = BatchReq{};
   return LR_OK;
+}
+
+int lr_batch_schedule(lr_batch *b, int *persistent, int *use_graph, double *rates) {
+  if (!b) return LR_EINVAL;
+  if (persistent) *persistent = b->o.persistent;
+  if (use_graph) *use_graph = b->o.use_graph;
+  if (rates)
+    for (int c = 0; c < lr_batch::kCand; ++c) rates[c] = b->tune_rate[c];
+  return (b->o.autotune && b->tune_next < lr_batch::kCand) ? LR_EAGAIN : LR_OK;
 }
 
 const char *lr_batch_last_error(const lr_batch *b) { return b ? b->err.c_str() : "null batch"; }

@@ -30,7 +30,7 @@ EXPORTS = ("lr_default_opts", "lr_create", "lr_bind_stream", "lr_set_state", "lr
            "lr_batch_default_opts", "lr_batch_create", "lr_batch_bind_stream", "lr_batch_footprint",
            "lr_batch_submit", "lr_batch_step", "lr_batch_poll", "lr_batch_status",
            "lr_batch_get_fields", "lr_batch_totals", "lr_batch_release", "lr_batch_running",
-           "lr_batch_last_error", "lr_batch_destroy")
+           "lr_batch_schedule", "lr_batch_last_error", "lr_batch_destroy")
 LR_F64_IN, LR_F32_IN = 0, 1  # element types of lr_set_state_device
 
 
@@ -49,7 +49,7 @@ class lr_opts(C.Structure):
 class lr_batch_opts(C.Structure):
     _fields_ = [("max_slots", C.c_int), ("pool_bytes", C.c_size_t), ("nmat", C.c_int),
                 ("precision", C.c_int), ("chunk_steps", C.c_int), ("use_graph", C.c_int),
-                ("persistent", C.c_int)]
+                ("persistent", C.c_int), ("autotune", C.c_int)]
 
 
 class LRError(RuntimeError):
@@ -113,6 +113,8 @@ def load():
     lib.lr_batch_totals.argtypes = [vp, C.c_long, dp]
     lib.lr_batch_release.argtypes = [vp, C.c_long]
     lib.lr_batch_running.argtypes = [vp]
+    lib.lr_batch_schedule.argtypes = [vp, P(C.c_int), P(C.c_int), dp]
+    lib.lr_batch_schedule.restype = C.c_int
     lib.lr_batch_last_error.argtypes = [vp]
     lib.lr_batch_last_error.restype = C.c_char_p
     lib.lr_batch_destroy.argtypes = [vp]
@@ -276,11 +278,12 @@ class Batch:
     no room now (LR_EAGAIN)."""
 
     def __init__(self, nmat=2, precision=LR_FP32, max_slots=256, pool_bytes=4 << 30,
-                 chunk_steps=16, use_graph=True, persistent=False, stream=None):
+                 chunk_steps=16, use_graph=True, persistent=False, autotune=False, stream=None):
         self.lib = load()
         o = lr_batch_default_opts()
         o.max_slots, o.pool_bytes, o.nmat, o.precision = int(max_slots), int(pool_bytes), int(nmat), int(precision)
         o.chunk_steps, o.use_graph, o.persistent = int(chunk_steps), int(bool(use_graph)), int(bool(persistent))
+        o.autotune = int(bool(autotune))
         self.nmat, self.precision = int(nmat), int(precision)
         h = C.c_void_p()
         rc = self.lib.lr_batch_create(C.byref(o), C.byref(h))
@@ -363,3 +366,10 @@ class Batch:
 
     def running(self):
         return int(self.lib.lr_batch_running(self.h))
+
+    def schedule(self):
+        """(persistent, use_graph, measured rates or None while tuning)"""
+        pe, ug = C.c_int(), C.c_int()
+        rates = np.zeros(4)
+        rc = self.lib.lr_batch_schedule(self.h, C.byref(pe), C.byref(ug), _dptr(rates))
+        return bool(pe.value), bool(ug.value), (rates if rc == LR_OK else None)

@@ -203,3 +203,19 @@ def test_set_state_device_float32_inputs():
     for s in (a, d):
         s.run(1e30, max_steps=5)
     same_fields(d.fields(*FIELDS), a.fields(*FIELDS), "float32 device input")
+
+
+def test_autotuned_schedule_keeps_results():
+    """The autotuner times the four launch schedules on the first chunks and
+    keeps the fastest; every schedule runs the same arithmetic."""
+    ps = problems()
+    b = Batch(nmat=2, precision=LR_FP32, max_slots=8, pool_bytes=64 << 20, chunk_steps=2, autotune=True)
+    ids = [b.submit(p, 1e30, max_steps=14, k_eps=1e-6) for p in ps]
+    assert b.schedule()[2] is None  # still timing
+    drain(b)
+    persistent, graph, rates = b.schedule()
+    assert rates is not None and np.all(rates > 0)
+    assert int(persistent) + 2 * int(graph) == int(np.argmax(rates))
+    for p, rid in zip(ps, ids):
+        g, n, _ = alone(p, LR_FP32, steps=14)
+        same_fields(b.fields(rid, *FIELDS), g.fields(*FIELDS), p["name"])
