@@ -604,6 +604,7 @@ struct RemapShared {
   R xv[XH][XW], yv[YH][YW];
   R vcf[NCY][NCX], xc[NCY][NCX], yc[NCY][NCX], wx[NCY][NCX], wy[NCY][NCX];
   int pure[NCY][NCX];  // material of a pure cell, -1 mixed; +16 once P5 keeps order 2
+  R mpure[NCY][NCX];   // the pure material's mass (positivity guard)
   R rcf[NM][NCY][NCX], el[NM][NCY][NCX];
   R vr[NV], ve[NV];  // x-faces, then y-faces, then corners
 };
@@ -818,6 +819,11 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       sh.el[m][b][a] = vme[2 * NM + m];
     }
     sh.pure[b][a] = np == 1 ? pm : -1;
+    R mp = R(0);
+#pragma unroll
+    for (int m = 0; m < NM; ++m)
+      if (m == pm) mp = vme[NM + m];
+    sh.mpure[b][a] = mp;
     if (ri == i && rj == j && a >= 2 && b >= 2 && a < TX + 2 && b < TY + 2) {
       if (!(v > R(0))) atomicOr(&ctl->err, ERR_VOLCF);
       if (P.dbg.volcf) stg(P.dbg.volcf + q, v);
@@ -952,13 +958,11 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       const int ca = di - (i0 - 2), cb = dj - (j0 - 2);
       const int pm = sh.pure[cb][ca];
       if (pm < 0) continue;
-      R eD = R(0), Mpm = R(0);
+      const R Mpm = sh.mpure[cb][ca];
+      R eD = R(0);
 #pragma unroll
       for (int m = 0; m < NM; ++m)
-        if (m == pm) {
-          eD = sh.el[m][cb][ca];
-          Mpm = ldg(Ms + (m * C + dj * nx + di));
-        }
+        if (m == pm) eD = sh.el[m][cb][ca];
       R Mout = R(0), Eout = R(0);
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
@@ -1160,7 +1164,7 @@ struct DualShared {
   static constexpr int PXW = TX + 2, PXH = TY + 1, PYW = TX + 1, PYH = TY + 2;
   static constexpr int PCW = TX + 2, PCH = TY + 2;
   static constexpr int NSTAGE = NX_ * NY_ + PXW * PXH + PYW * PYH + PCW * PCH;
-  R ulx[NY_][NX_], uly[NY_][NX_], dx[NY_][NX_], dy[NY_][NX_], X[NY_][NX_], Y[NY_][NX_];
+  R ulx[NY_][NX_], uly[NY_][NX_], dx[NY_][NX_], dy[NY_][NX_];
   R mx[PXH][PXW], my[PYH][PYW], cd[PCH][PCW], ca[PCH][PCW];
   R fx[3][NXF], fy[3][NYF], fd[3][NCN], fa[3][NCN];
 };
@@ -1261,25 +1265,19 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
         const int a = l % SH::NX_, b = l / SH::NX_;
         const int I = I0 - 2 + a, J = J0 - 2 + b;
         if (I > nx + 2 || J > ny + 2) continue;
-        const int rI = refl_node(I, nx), rJ = refl_node(J, ny);
         R ulx = pre[it][0], uly = pre[it][1], dx = dt * pre[it][2], dy = dt * pre[it][3];
-        R X = R(rI) * Dx + dx, Y = R(rJ) * Dy + dy;
-        if (rI != I) {
+        if (refl_node(I, nx) != I) {
           ulx = -ulx;
           dx = -dx;
-          X = (I < 0 ? R(0) : R(2.0 * g.Lx)) - X;
         }
-        if (rJ != J) {
+        if (refl_node(J, ny) != J) {
           uly = -uly;
           dy = -dy;
-          Y = (J < 0 ? R(0) : R(2.0 * g.Ly)) - Y;
         }
         sh.ulx[b][a] = ulx;
         sh.uly[b][a] = uly;
         sh.dx[b][a] = dx;
         sh.dy[b][a] = dy;
-        sh.X[b][a] = X;
-        sh.Y[b][a] = Y;
       } else if (l < NNODE + NPX) {
         const int k = l - NNODE;
         const int a = k % SH::PXW, b = k / SH::PXW;
@@ -1315,13 +1313,17 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
     const bool o2 = g.recon_order == 2;
     // both velocity components at donor node (la, lb), limited slopes along
     // (sa, sb) projected on (vx, vy), offset `off`
+    // Lagrangian position of a staged node: its index times the cell size
+    // plus its (mirrored) displacement, for ghost nodes too
+    auto Xp = [&](int la, int lb) { return R(I0 - 2 + la) * Dx + sh.dx[lb][la]; };
+    auto Yp = [&](int la, int lb) { return R(J0 - 2 + lb) * Dy + sh.dy[lb][la]; };
     auto recon = [&](int la, int lb, int sa, int sb, R vx, R vy, R off, R &u, R &v) {
       u = sh.ulx[lb][la];
       v = sh.uly[lb][la];
       if (!o2) return;
       const int ma = la - sa, mb = lb - sb, pa = la + sa, pb = lb + sb;
-      const R lm = (sh.X[lb][la] - sh.X[mb][ma]) * vx + (sh.Y[lb][la] - sh.Y[mb][ma]) * vy;
-      const R lp = (sh.X[pb][pa] - sh.X[lb][la]) * vx + (sh.Y[pb][pa] - sh.Y[lb][la]) * vy;
+      const R lm = (Xp(la, lb) - Xp(ma, mb)) * vx + (Yp(la, lb) - Yp(ma, mb)) * vy;
+      const R lp = (Xp(pa, pb) - Xp(la, lb)) * vx + (Yp(pa, pb) - Yp(la, lb)) * vy;
       const R ilm = qdiv(R(1), lm), ilp = qdiv(R(1), lp);
       const R su = van_leer((u - sh.ulx[mb][ma]) * ilm, (sh.ulx[pb][pa] - u) * ilp);
       const R sv = van_leer((v - sh.uly[mb][ma]) * ilm, (sh.uly[pb][pa] - v) * ilp);
