@@ -603,10 +603,14 @@ struct RemapShared {
   R ndx[NNY][NNX], ndy[NNY][NNX];
   R xv[XH][XW], yv[YH][YW];
   R vcf[NCY][NCX], xc[NCY][NCX], yc[NCY][NCX], wx[NCY][NCX], wy[NCY][NCX];
-  int pure[NCY][NCX];  // material of a pure cell, -1 mixed; +16 once P5 keeps order 2
+  signed char pure[NCY][NCX];  // material of a pure cell, -1 mixed; +16 once P5 keeps order 2
   R mpure[NCY][NCX];   // the pure material's mass (positivity guard)
   R rcf[NM][NCY][NCX], el[NM][NCY][NCX];
-  R vr[NV], ve[NV];  // x-faces, then y-faces, then corners
+  // per region (x-faces, then y-faces, then corners): the order-2 mass and
+  // energy fluxes of a pure donor, and the region's slot in its donor's frame
+  // (-1: no pure donor in the window)
+  R vm[NV], vq[NV];
+  signed char rslot[NV];
 };
 
 // the donor-frame region s (W, E, S, N, BL, BR, TL, TR) of region `kind`
@@ -846,19 +850,6 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
     if (kind == 1) return SH::VXW * SH::VXH + (J - (j0 - 1)) * SH::VYW + (I - (i0 - 1));
     return SH::VXW * SH::VXH + SH::VYW * SH::VYH + (J - (j0 - 1)) * SH::VCW + (I - (i0 - 1));
   };
-  // donor-frame region s of donor (di, dj) -> (kind, I, J) of the region
-  auto region_of = [&](int di, int dj, int s, int &kind, int &I, int &J) {
-    switch (s) {
-      case 0: kind = 0; I = di; J = dj; break;
-      case 1: kind = 0; I = di + 1; J = dj; break;
-      case 2: kind = 1; I = di; J = dj; break;
-      case 3: kind = 1; I = di; J = dj + 1; break;
-      case 4: kind = 2; I = di; J = dj; break;
-      case 5: kind = 2; I = di + 1; J = dj; break;
-      case 6: kind = 2; I = di; J = dj + 1; break;
-      default: kind = 2; I = di + 1; J = dj + 1; break;
-    }
-  };
   // signed volume of region (kind, I, J) (real position); for corners the
   // sign is that of the node's x-displacement and *mainc its kind
   auto region_vol = [&](int kind, int I, int J, bool &mainc) {
@@ -875,6 +866,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   if (o2) {
     for (int l = tid; l < SH::NV; l += NTHREADS) {
       int kind, I, J;
+      sh.rslot[l] = -1;
       if (l < SH::VXW * SH::VXH) {
         kind = 0; I = i0 - 1 + l % SH::VXW; J = j0 - 1 + l / SH::VXW;
         if (I < 0 || I > nx || J < 0 || J >= ny) continue;
@@ -890,6 +882,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       bool mainc;
       const R sv = region_vol(kind, I, J, mainc);
       const RegionRef rf = region_donor(kind, I, J, signbit(sv), mainc);
+      sh.rslot[l] = -1;
       if (!donor_in(rf.di, rf.dj)) continue;
       const int ca = rf.di - (i0 - 2), cb = rf.dj - (j0 - 2);
       const int pm = sh.pure[cb][ca];
@@ -945,8 +938,10 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
         vr = rD + R(0.5) * van_leer((rD - rm) * ilm, (rp - rD) * ilp) * off;
         ve = eD + R(0.5) * van_leer((eD - em) * ilm, (ep - eD) * ilp) * off;
       }
-      sh.vr[l] = vr;
-      sh.ve[l] = ve;
+      const R mu = vr * fabs(sv);
+      sh.vm[l] = mu;
+      sh.vq[l] = mu * ve;
+      sh.rslot[l] = rf.s;
     }
     __syncthreads();
 
@@ -963,19 +958,18 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
 #pragma unroll
       for (int m = 0; m < NM; ++m)
         if (m == pm) eD = sh.el[m][cb][ca];
+      // the donor's eight regions in the region arrays: W, E faces, S, N
+      // faces, corners at its BL, BR, TL, TR nodes; a region is an outflow
+      // of this donor iff P4 recorded this donor-frame slot for it
+      const int vx0 = vidx(0, di, dj), vy0 = vidx(1, di, dj), vc0 = vidx(2, di, dj);
+      const int vi8[8] = {vx0, vx0 + 1, vy0, vy0 + SH::VYW, vc0, vc0 + 1, vc0 + SH::VCW, vc0 + SH::VCW + 1};
       R Mout = R(0), Eout = R(0);
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
-        int kind, I, J;
-        region_of(di, dj, s, kind, I, J);
-        bool mainc;
-        const R sv = region_vol(kind, I, J, mainc);
-        const RegionRef rf = region_donor(kind, I, J, signbit(sv), mainc);
-        if (rf.di != di || rf.dj != dj || rf.s != s) continue;  // not an outflow of this donor
-        const int vi = vidx(kind, I, J);
-        const R mu = sh.vr[vi] * fabs(sv);
-        Mout += mu;
-        Eout += mu * sh.ve[vi];
+        const int vi = vi8[s];
+        if (sh.rslot[vi] != s) continue;  // not an outflow of this donor
+        Mout += sh.vm[vi];
+        Eout += sh.vq[vi];
       }
       if (!(Mout > Mpm || Eout > Mpm * eD)) sh.pure[cb][ca] = pm + 16;
     }
@@ -1036,13 +1030,13 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
               rho = sh.rcf[m][db][da];
               e = sh.el[m][db][da];
             }
-          if (o2 && pq >= 16) {
+          R mu = w > R(0) ? rho * w : R(0);
+          R ep = w > R(0) ? mu * e : R(0);
+          if (o2 && pq >= 16) {  // order 2 kept by the guard: the region's own fluxes
             const int vi = vidx(rk[s], rI[s], rJ[s]);
-            rho = sh.vr[vi];
-            e = sh.ve[vi];
+            mu = w > R(0) ? sh.vm[vi] : R(0);
+            ep = w > R(0) ? sh.vq[vi] : R(0);
           }
-          const R mu = w > R(0) ? rho * w : R(0);
-          const R ep = w > R(0) ? mu * e : R(0);
 #pragma unroll
           for (int m = 0; m < NM; ++m)
             if (m == pm) {
