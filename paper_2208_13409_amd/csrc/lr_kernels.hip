@@ -153,38 +153,85 @@ __device__ void mixed_region_partials(const ProbT &P, const R *Vs, int i, int j,
   const double Rx0 = 0.5 * (blx + tlx) - hx, Rx1 = 0.5 * (brx + trx) + hx;
   const double Ry0 = 0.5 * (bly + bry) - hy, Ry1 = 0.5 * (tly + try_) + hy;
   const double gmin = 1e-10 / fmin(g.dx, g.dy);
-  auto youngs = [&](int m, double &gx, double &gy) {
+  // The per-material work of the cell is spread over its eight lanes: lane s
+  // (s < NM) forms the Youngs gradient of material s, then the interface of
+  // material s (for two materials, the interface of the first one present,
+  // on its lane only); the other lanes read both with shuffles.  Every value
+  // is formed with the same operations as on a single lane.
+  static_assert(NM <= 8, "one lane of the group per material");
+  const int grp = __lane_id() & ~7;
+  double gxs = 0.0, gys = 0.0;  // this lane's material's gradient
+  if (s < NM && np >= 2) {
     double k[3][3];
 #pragma unroll
     for (int bb = -1; bb <= 1; ++bb)
 #pragma unroll
       for (int aa = -1; aa <= 1; ++aa)
         k[bb + 1][aa + 1] =
-            double(ldg(Vs + (m * C + refl_cell(j + bb, ny) * nx + refl_cell(i + aa, nx)))) / g.A;
-    gx = ((k[0][2] + 2.0 * k[1][2] + k[2][2]) - (k[0][0] + 2.0 * k[1][0] + k[2][0])) / (8.0 * g.dx);
-    gy = ((k[2][0] + 2.0 * k[2][1] + k[2][2]) - (k[0][0] + 2.0 * k[0][1] + k[0][2])) / (8.0 * g.dy);
-  };
-  if (np == 2) {
-    int a0 = -1, b0 = -1;
+            double(ldg(Vs + (s * C + refl_cell(j + bb, ny) * nx + refl_cell(i + aa, nx)))) / g.A;
+    gxs = ((k[0][2] + 2.0 * k[1][2] + k[2][2]) - (k[0][0] + 2.0 * k[1][0] + k[2][0])) / (8.0 * g.dx);
+    gys = ((k[2][0] + 2.0 * k[2][1] + k[2][2]) - (k[0][0] + 2.0 * k[0][1] + k[0][2])) / (8.0 * g.dy);
+  }
+  int a0 = -1, b0 = -1;
 #pragma unroll
-    for (int m = 0; m < NM; ++m)
-      if (pr[m]) {
-        if (a0 < 0) a0 = m;
-        else b0 = m;
+  for (int m = 0; m < NM; ++m)
+    if (pr[m]) {
+      if (a0 < 0) a0 = m;
+      else if (b0 < 0) b0 = m;
+    }
+  double GX[NM], GY[NM];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) {
+    GX[m] = __shfl(gxs, grp + m, 64);
+    GY[m] = __shfl(gys, grp + m, 64);
+  }
+  // interface of this lane's material: unit normal and offset, or degenerate
+  double inx = 0.0, iny = 0.0, ioff = 0.0;
+  int ideg = 1;
+  if (s < NM && np >= 2 && pr[s] && (np > 2 || s == a0)) {
+    double gx = gxs, gy = gys, Vm = 0.0;
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      if (m == s) Vm = V[m];
+      if (np == 2 && m == b0) {  // two materials: the difference of their gradients
+        gx = gxs - GX[m];
+        gy = gys - GY[m];
       }
-    double gax, gay, gbx, gby;
-    youngs(a0, gax, gay);
-    youngs(b0, gbx, gby);
-    const double gx = gax - gbx, gy = gay - gby;
+    }
     const double nrm = sqrt(gx * gx + gy * gy);
+    if (!(nrm <= gmin)) {
+      inx = gx / nrm;
+      iny = gy / nrm;
+      ioff = interface_offset(Rx0, Rx1, Ry0, Ry1, inx, iny, Vm / Vp);
+      ideg = 0;
+    }
+  }
+  double NX[NM], NY[NM], OF[NM];
+  int DG[NM];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) {
+    NX[m] = __shfl(inx, grp + m, 64);
+    NY[m] = __shfl(iny, grp + m, 64);
+    OF[m] = __shfl(ioff, grp + m, 64);
+    DG[m] = __shfl(ideg, grp + m, 64);
+  }
+  if (np == 2) {
     if (out && vol != 0.0) {
-      if (nrm <= gmin) {
+      bool deg = false;
+      double nxa = 0.0, nya = 0.0, sa = 0.0;
+#pragma unroll
+      for (int m = 0; m < NM; ++m)
+        if (m == a0) {
+          deg = DG[m] != 0;
+          nxa = NX[m];
+          nya = NY[m];
+          sa = OF[m];
+        }
+      if (deg) {
 #pragma unroll
         for (int m = 0; m < NM; ++m)
           if (pr[m]) W[m] = vol * (V[m] / Vp);
       } else {
-        const double nxa = gx / nrm, nya = gy / nrm;
-        const double sa = interface_offset(Rx0, Rx1, Ry0, Ry1, nxa, nya, V[a0] / Vp);
         double wa = rect_halfplane_area(x0, x1, y0, y1, nxa, nya, sa);
         wa = fmin(fmax(wa, 0.0), vol);
 #pragma unroll
@@ -201,16 +248,11 @@ __device__ void mixed_region_partials(const ProbT &P, const R *Vs, int i, int j,
     for (int m = 0; m < NM; ++m) {
       raw[m] = 0.0;
       if (!pr[m]) continue;
-      double gx, gy;
-      youngs(m, gx, gy);
-      const double nrm = sqrt(gx * gx + gy * gy);
-      if (nrm <= gmin) {
+      if (DG[m]) {
         degenerate = true;
         continue;
       }
-      const double nxm = gx / nrm, nym = gy / nrm;
-      const double sm = interface_offset(Rx0, Rx1, Ry0, Ry1, nxm, nym, V[m] / Vp);
-      raw[m] = rect_halfplane_area(x0, x1, y0, y1, nxm, nym, sm);
+      raw[m] = rect_halfplane_area(x0, x1, y0, y1, NX[m], NY[m], OF[m]);
     }
     if (out && vol != 0.0) {
 #pragma unroll
@@ -882,18 +924,12 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       bool mainc;
       const R sv = region_vol(kind, I, J, mainc);
       const RegionRef rf = region_donor(kind, I, J, signbit(sv), mainc);
-      sh.rslot[l] = -1;
       if (!donor_in(rf.di, rf.dj)) continue;
       const int ca = rf.di - (i0 - 2), cb = rf.dj - (j0 - 2);
       const int pm = sh.pure[cb][ca];
       if (pm < 0) continue;
-      R rD = R(0), eD = R(0);
-#pragma unroll
-      for (int m = 0; m < NM; ++m)
-        if (m == pm) {
-          rD = sh.rcf[m][cb][ca];
-          eD = sh.el[m][cb][ca];
-        }
+      // LDS indexed by the material directly (no private array is indexed)
+      const R rD = sh.rcf[pm][cb][ca], eD = sh.el[pm][cb][ca];
       R vr = rD, ve = eD;
       const int na = NA(rf.di), nb = NB(rf.dj);  // donor's BL node
       const R dxL = sh.wx[cb][ca], dyL = sh.wy[cb][ca];
@@ -927,16 +963,10 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
         const R xD = sh.xc[cb][ca], yD = sh.yc[cb][ca];
         const R lm = (xD - sh.xc[bmn][am]) * vx + (yD - sh.yc[bmn][am]) * vy;
         const R lp = (sh.xc[bp][ap] - xD) * vx + (sh.yc[bp][ap] - yD) * vy;
-        R rm = R(0), rp = R(0), em = R(0), ep = R(0);
-#pragma unroll
-        for (int m = 0; m < NM; ++m)
-          if (m == pm) {
-            rm = sh.rcf[m][bmn][am]; rp = sh.rcf[m][bp][ap];
-            em = sh.el[m][bmn][am]; ep = sh.el[m][bp][ap];
-          }
-        const R ilm = qdiv(R(1), lm), ilp = qdiv(R(1), lp);
-        vr = rD + R(0.5) * van_leer((rD - rm) * ilm, (rp - rD) * ilp) * off;
-        ve = eD + R(0.5) * van_leer((eD - em) * ilm, (ep - eD) * ilp) * off;
+        const R rm = sh.rcf[pm][bmn][am], rp = sh.rcf[pm][bp][ap];
+        const R em = sh.el[pm][bmn][am], ep = sh.el[pm][bp][ap];
+        vr = rD + R(0.5) * van_leer_d(rD - rm, rp - rD, lm, lp) * off;
+        ve = eD + R(0.5) * van_leer_d(eD - em, ep - eD, lm, lp) * off;
       }
       const R mu = vr * fabs(sv);
       sh.vm[l] = mu;
@@ -954,10 +984,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       const int pm = sh.pure[cb][ca];
       if (pm < 0) continue;
       const R Mpm = sh.mpure[cb][ca];
-      R eD = R(0);
-#pragma unroll
-      for (int m = 0; m < NM; ++m)
-        if (m == pm) eD = sh.el[m][cb][ca];
+      const R eD = sh.el[pm][cb][ca];
       // the donor's eight regions in the region arrays: W, E faces, S, N
       // faces, corners at its BL, BR, TL, TR nodes; a region is an outflow
       // of this donor iff P4 recorded this donor-frame slot for it
@@ -1023,13 +1050,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
         const int pq = sh.pure[db][da];
         if (pq >= 0) {
           const int pm = pq & 15;
-          R rho = R(0), e = R(0);
-#pragma unroll
-          for (int m = 0; m < NM; ++m)
-            if (m == pm) {
-              rho = sh.rcf[m][db][da];
-              e = sh.el[m][db][da];
-            }
+          const R rho = sh.rcf[pm][db][da], e = sh.el[pm][db][da];
           R mu = w > R(0) ? rho * w : R(0);
           R ep = w > R(0) ? mu * e : R(0);
           if (o2 && pq >= 16) {  // order 2 kept by the guard: the region's own fluxes
@@ -1318,9 +1339,8 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
       const int ma = la - sa, mb = lb - sb, pa = la + sa, pb = lb + sb;
       const R lm = (Xp(la, lb) - Xp(ma, mb)) * vx + (Yp(la, lb) - Yp(ma, mb)) * vy;
       const R lp = (Xp(pa, pb) - Xp(la, lb)) * vx + (Yp(pa, pb) - Yp(la, lb)) * vy;
-      const R ilm = qdiv(R(1), lm), ilp = qdiv(R(1), lp);
-      const R su = van_leer((u - sh.ulx[mb][ma]) * ilm, (sh.ulx[pb][pa] - u) * ilp);
-      const R sv = van_leer((v - sh.uly[mb][ma]) * ilm, (sh.uly[pb][pa] - v) * ilp);
+      const R su = van_leer_d(u - sh.ulx[mb][ma], sh.ulx[pb][pa] - u, lm, lp);
+      const R sv = van_leer_d(v - sh.uly[mb][ma], sh.uly[pb][pa] - v, lm, lp);
       u += su * off;
       v += sv * off;
     };
