@@ -83,6 +83,20 @@ __device__ void mixed_region_partials(const ProbT &P, const R *Vs, int i, int j,
                                       R try_r, double *Wout) {
   const auto &g = P.g;
   const int nx = g.nx, ny = g.ny, C = nx * ny, q = j * nx + i;
+  // all of the cell's loads first (one memory latency): its partial volumes
+  // and the 3x3 neighbourhood of material min(s, NM-1) for the Youngs gradient
+  // formed on lane s < NM (the other lanes repeat the last material's loads)
+  R Vr[NM], kr[3][3];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) Vr[m] = ldg(Vs + (m * C + q));
+  {
+    const int ms = s < NM ? s : NM - 1;
+#pragma unroll
+    for (int bb = -1; bb <= 1; ++bb)
+#pragma unroll
+      for (int aa = -1; aa <= 1; ++aa)
+        kr[bb + 1][aa + 1] = ldg(Vs + (ms * C + refl_cell(j + bb, ny) * nx + refl_cell(i + aa, nx)));
+  }
   CellRegions<R> rr;
   cell_regions<R>(R(g.dx), R(g.dy), blx_r, bly_r, brx_r, bry_r, tlx_r, tly_r, trx_r, try_r, rr);
   R vcf_r = R(g.A);
@@ -140,7 +154,7 @@ __device__ void mixed_region_partials(const ProbT &P, const R *Vs, int i, int j,
   int np = 0;
 #pragma unroll
   for (int m = 0; m < NM; ++m) {
-    V[m] = double(ldg(Vs + (m * C + q)));
+    V[m] = double(Vr[m]);
     pr[m] = V[m] > g.k_eps * g.A;
     if (pr[m]) {
       ++np;
@@ -160,15 +174,15 @@ __device__ void mixed_region_partials(const ProbT &P, const R *Vs, int i, int j,
   // is formed with the same operations as on a single lane.
   static_assert(NM <= 8, "one lane of the group per material");
   const int grp = __lane_id() & ~7;
-  double gxs = 0.0, gys = 0.0;  // this lane's material's gradient
-  if (s < NM && np >= 2) {
+  // this lane's material's gradient (formed on every lane, used from lanes
+  // s < NM: the group runs the same instructions either way)
+  double gxs, gys;
+  {
     double k[3][3];
 #pragma unroll
-    for (int bb = -1; bb <= 1; ++bb)
+    for (int bb = 0; bb < 3; ++bb)
 #pragma unroll
-      for (int aa = -1; aa <= 1; ++aa)
-        k[bb + 1][aa + 1] =
-            double(ldg(Vs + (s * C + refl_cell(j + bb, ny) * nx + refl_cell(i + aa, nx)))) / g.A;
+      for (int aa = 0; aa < 3; ++aa) k[bb][aa] = double(kr[bb][aa]) / g.A;
     gxs = ((k[0][2] + 2.0 * k[1][2] + k[2][2]) - (k[0][0] + 2.0 * k[1][0] + k[2][0])) / (8.0 * g.dx);
     gys = ((k[2][0] + 2.0 * k[2][1] + k[2][2]) - (k[0][0] + 2.0 * k[0][1] + k[0][2])) / (8.0 * g.dy);
   }
@@ -307,7 +321,8 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
   const auto &g = P.g;
   const int par = gpar ^ P.flip;
   Slot &S = P.ctl->slot[par];
-  if (ldg(&S.done) || ldg(&P.ctl->err)) return;
+  // read with the tile's first global loads; tested once they are issued
+  const bool stop = (ldg(&S.done) | ldg(&P.ctl->err)) != 0;
   const int nx = g.nx, ny = g.ny, C = nx * ny;
   const int I0 = bm.i0, J0 = bm.j0, tid = threadIdx.x;
   const R Dx = R(g.dx), Dy = R(g.dy), A = R(g.A);
@@ -371,6 +386,7 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
   }
   bool last;
   const R dt = R(slot_dt(g, S, last));
+  if (stop) return;
 
 #pragma unroll
   for (int it = 0; it < NITU; ++it) {
@@ -599,15 +615,23 @@ __global__ void __launch_bounds__(NTHREADS) k_mixed(const Prob<R> *probs, const 
   const auto &g = P.g;
   const int par = gpar ^ P.flip;
   Slot &S = P.ctl->slot[par];
-  if (ldg(&S.done) || ldg(&P.ctl->err)) return;
+  // the stop flags, the list length, the step and the block's first list
+  // entry are read together (the entry speculatively, within the list's
+  // capacity)
+  const bool stop = (ldg(&S.done) | ldg(&P.ctl->err)) != 0;
   const int nmix = min(ldg(&S.nmix), P.mix_cap);
-  if ((int)blockIdx.x * (NTHREADS / 8) >= nmix) return;
   const int nx = g.nx, tid = threadIdx.x;
-  const R *Vs = P.V[par];
+  const int w0 = blockIdx.x * (NTHREADS / 8) + tid / 8;
+  const int q0 = ldg(P.mix_cell + min(w0, P.mix_cap - 1));
   bool last;
   const R dt = R(slot_dt(g, S, last));
-  for (int w = blockIdx.x * (NTHREADS / 8) + tid / 8; w < nmix; w += gridDim.x * (NTHREADS / 8)) {
-    const int q = ldg(P.mix_cell + w), i = q % nx, j = q / nx;
+  // keeps the entry's load ahead of the test (it would otherwise be sunk
+  // below it, one more memory latency)
+  asm volatile("" ::"v"(q0));
+  if (stop || (int)blockIdx.x * (NTHREADS / 8) >= nmix) return;
+  const R *Vs = P.V[par];
+  for (int w = w0; w < nmix; w += gridDim.x * (NTHREADS / 8)) {
+    const int q = w == w0 ? q0 : ldg(P.mix_cell + w), i = q % nx, j = q / nx;
     const int bl = j * (nx + 1) + i, br = bl + 1, tl = bl + nx + 1, tr = tl + 1;
     mixed_region_partials<R, NM>(P, Vs, i, j, tid % 8, dt * ldg(P.uhx + bl), dt * ldg(P.uhy + bl),
                                  dt * ldg(P.uhx + br), dt * ldg(P.uhy + br), dt * ldg(P.uhx + tl),
@@ -679,11 +703,8 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   const int par = gpar ^ P.flip;
   const Slot &S = ctl->slot[par];
   const int i0 = bm.i0, j0 = bm.j0, tid = threadIdx.x;
-  if (ldg(&S.done) || ldg(&ctl->err)) {
-    // keep the other slot stopped too, so that later launches also return
-    if (i0 == 0 && j0 == 0 && tid == 0) stg(&ctl->slot[par ^ 1].done, 1);
-    return;
-  }
+  // read with the tile's first global loads; tested once they are issued
+  const bool stop = (ldg(&S.done) | ldg(&ctl->err)) != 0;
   const int nx = g.nx, ny = g.ny, C = nx * ny;
   const R Dx = R(g.dx), Dy = R(g.dy), A = R(g.A);
   const R *Vs = P.V[par], *Ms = P.M[par];
@@ -740,6 +761,11 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   bool last;
   const double dtd = slot_dt(g, S, last);
   const R dt = R(dtd);
+  if (stop) {
+    // keep the other slot stopped too, so that later launches also return
+    if (i0 == 0 && j0 == 0 && tid == 0) stg(&ctl->slot[par ^ 1].done, 1);
+    return;
+  }
 
   // the first tile of the problem prepares the next step's slot
   if (i0 == 0 && j0 == 0 && tid == 0) {
@@ -1178,7 +1204,6 @@ struct DualShared {
   // [J0-1, J0+TY]; (main, anti) corner fluxes at nodes [I0-1, I0+TX] x [J0-1, J0+TY]
   static constexpr int PXW = TX + 2, PXH = TY + 1, PYW = TX + 1, PYH = TY + 2;
   static constexpr int PCW = TX + 2, PCH = TY + 2;
-  static constexpr int NSTAGE = NX_ * NY_ + PXW * PXH + PYW * PYH + PCW * PCH;
   R ulx[NY_][NX_], uly[NY_][NX_], dx[NY_][NX_], dy[NY_][NX_];
   R mx[PXH][PXW], my[PYH][PYW], cd[PCH][PCW], ca[PCH][PCW];
   R fx[3][NXF], fy[3][NYF], fd[3][NCN], fa[3][NCN];
@@ -1194,7 +1219,8 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
   const int par = gpar ^ P.flip;
   const Slot &S = ctl->slot[par];
   const int tid = threadIdx.x;
-  if (ldg(&S.done) || ldg(&ctl->err)) return;
+  // read with the tile's first global loads; tested once they are issued
+  const bool stop = (ldg(&S.done) | ldg(&ctl->err)) != 0;
   const int nx = g.nx, ny = g.ny;
   const int I0 = bm.i0, J0 = bm.j0;
   const R Dx = R(g.dx), Dy = R(g.dy);
@@ -1205,122 +1231,145 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
   const int a3 = tid % TX, b3 = tid / TX, I3 = I0 + a3, J3 = J0 + b3;
   const bool own3 = I3 <= nx && J3 <= ny;
   const int p3 = own3 ? J3 * (nx + 1) + I3 : 0;
-  R ux3 = R(0), uy3 = R(0), mp3 = R(0), ulx3 = R(0), uly3 = R(0), cs3[4];
-  if (own3) {
-    ux3 = ldg(P.ux + p3);
-    uy3 = ldg(P.uy + p3);
-    if (!g.kinematic) {
-      mp3 = ldg(P.mp + p3);
-      ulx3 = ldg(P.uLx + p3);
-      uly3 = ldg(P.uLy + p3);
-    }
+  // (every load is issued unconditionally from a clamped index and its value
+  // zeroed where it is not wanted: loads under branches would be serialised)
+  R ux3 = ldg(P.ux + p3), uy3 = ldg(P.uy + p3), mp3 = R(0), ulx3 = R(0), uly3 = R(0), cs3[4];
+  if (!g.kinematic) {
+    mp3 = ldg(P.mp + p3);
+    ulx3 = ldg(P.uLx + p3);
+    uly3 = ldg(P.uLy + p3);
   }
+  // (the owned node's values are used by its own thread only; the corner
+  // sound speeds are masked where they are used)
+  int cs_ok = 0;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int ci = I3 - 1 + (c & 1), cj = J3 - 1 + (c >> 1);
-    cs3[c] = (own3 && ci >= 0 && cj >= 0 && ci < nx && cj < ny) ? ldg(P.cs + (cj * nx + ci)) : R(0);
+    const bool ok = own3 && ci >= 0 && cj >= 0 && ci < nx && cj < ny;
+    cs3[c] = ldg(P.cs + (ok ? cj * nx + ci : 0));
+    cs_ok |= ok ? 1 << c : 0;
   }
-  constexpr int NIT = (SH::NSTAGE + NTHREADS - 1) / NTHREADS;
-  constexpr int NNODE = SH::NX_ * SH::NY_, NPX = SH::PXW * SH::PXH, NPY = SH::PYW * SH::PYH;
-  R pre[NIT][4];
+  // One loop per kind of staged item, so that a lane without an item of a
+  // kind (the tail of each loop, walls) loads nothing for it: the loads sit
+  // under branches with no other side, and no other branch writes their
+  // registers while they are in flight (with one loop over all kinds the
+  // compiler waits for each kind's loads before the next kind's branch).
+  // Values of items that have none stay unset; stage 1 writes zero there.
+  constexpr int NNODE = SH::NX_ * SH::NY_, NPX = SH::PXW * SH::PXH, NPY = SH::PYW * SH::PYH,
+                NPC = SH::PCW * SH::PCH;
+  constexpr int ITN = (NNODE + NTHREADS - 1) / NTHREADS, ITX = (NPX + NTHREADS - 1) / NTHREADS,
+                ITY = (NPY + NTHREADS - 1) / NTHREADS, ITC = (NPC + NTHREADS - 1) / NTHREADS;
+  R pn[ITN][4], px[ITX], py[ITY], pc[ITC][3];
   if (!g.kinematic) {
 #pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-      pre[it][0] = pre[it][1] = pre[it][2] = pre[it][3] = R(0);
+    for (int it = 0; it < ITN; ++it) {  // node: u^{lag}, u^{n+1/2}
       const int l = tid + it * NTHREADS;
-      if (l >= SH::NSTAGE) continue;
-      if (l < NNODE) {  // node: u^{lag}, u^{n+1/2}
-        const int I = I0 - 2 + l % SH::NX_, J = J0 - 2 + l / SH::NX_;
-        if (I > nx + 2 || J > ny + 2) continue;
+      const int I = I0 - 2 + l % SH::NX_, J = J0 - 2 + l / SH::NX_;
+      if (l < NNODE && I <= nx + 2 && J <= ny + 2) {
         const int p = refl_node(J, ny) * (nx + 1) + refl_node(I, nx);
-        pre[it][0] = ldg(P.uLx + p);
-        pre[it][1] = ldg(P.uLy + p);
-        pre[it][2] = ldg(P.uhx + p);
-        pre[it][3] = ldg(P.uhy + p);
-      } else if (l < NNODE + NPX) {  // primal x-face mass flux
-        const int k = l - NNODE;
-        int I = I0 - 1 + k % SH::PXW;
-        const int j = J0 - 1 + k / SH::PXW;
-        if (I > nx + 1 || j > ny) continue;
-        I = I < 0 ? -I : (I > nx ? 2 * nx - I : I);
-        if (I == 0 || I == nx) continue;
-        pre[it][0] = ldg(P.MX + (refl_cell(j, ny) * (nx + 1) + I));
-      } else if (l < NNODE + NPX + NPY) {  // primal y-face mass flux
-        const int k = l - NNODE - NPX;
-        const int i = I0 - 1 + k % SH::PYW;
-        int J = J0 - 1 + k / SH::PYW;
-        if (i > nx || J > ny + 1) continue;
-        J = J < 0 ? -J : (J > ny ? 2 * ny - J : J);
-        if (J == 0 || J == ny) continue;
-        pre[it][0] = ldg(P.MY + (J * nx + refl_cell(i, nx)));
-      } else {  // corner mass flux and the node's displacement direction
-        const int k = l - NNODE - NPX - NPY;
-        const int I = I0 - 1 + k % SH::PCW, J = J0 - 1 + k / SH::PCW;
-        if (I > nx + 1 || J > ny + 1) continue;
-        const int rI = refl_node(I, nx), rJ = refl_node(J, ny);
-        if (rI == 0 || rI == nx || rJ == 0 || rJ == ny) continue;
+        pn[it][0] = ldg(P.uLx + p);
+        pn[it][1] = ldg(P.uLy + p);
+        pn[it][2] = ldg(P.uhx + p);
+        pn[it][3] = ldg(P.uhy + p);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < ITX; ++it) {  // primal x-face mass flux
+      const int k = tid + it * NTHREADS;
+      const int I = I0 - 1 + k % SH::PXW, j = J0 - 1 + k / SH::PXW;
+      const int rI = I < 0 ? -I : (I > nx ? 2 * nx - I : I);
+      if (k < NPX && I <= nx + 1 && j <= ny && rI != 0 && rI != nx)
+        px[it] = ldg(P.MX + (refl_cell(j, ny) * (nx + 1) + rI));
+    }
+#pragma unroll
+    for (int it = 0; it < ITY; ++it) {  // primal y-face mass flux
+      const int k = tid + it * NTHREADS;
+      const int i = I0 - 1 + k % SH::PYW, J = J0 - 1 + k / SH::PYW;
+      const int rJ = J < 0 ? -J : (J > ny ? 2 * ny - J : J);
+      if (k < NPY && i <= nx && J <= ny + 1 && rJ != 0 && rJ != ny)
+        py[it] = ldg(P.MY + (rJ * nx + refl_cell(i, nx)));
+    }
+#pragma unroll
+    for (int it = 0; it < ITC; ++it) {  // corner mass flux and the node's displacement direction
+      const int k = tid + it * NTHREADS;
+      const int I = I0 - 1 + k % SH::PCW, J = J0 - 1 + k / SH::PCW;
+      const int rI = refl_node(I, nx), rJ = refl_node(J, ny);
+      if (k < NPC && I <= nx + 1 && J <= ny + 1 && rI != 0 && rI != nx && rJ != 0 && rJ != ny) {
         const int p = rJ * (nx + 1) + rI;
-        pre[it][0] = ldg(P.MC + p);
-        pre[it][1] = ldg(P.uhx + p);
-        pre[it][2] = ldg(P.uhy + p);
+        pc[it][0] = ldg(P.MC + p);
+        pc[it][1] = ldg(P.uhx + p);
+        pc[it][2] = ldg(P.uhy + p);
       }
     }
   }
   bool last;
   const R dt = R(slot_dt(g, S, last));
+  if (stop) return;
 
   if (!g.kinematic) {
     // ---- stage 1: node data and the primal mass fluxes around the tile,
     // mirrored at walls, from the loads issued above
 #pragma unroll
-    for (int it = 0; it < NIT; ++it) {
+    for (int it = 0; it < ITN; ++it) {
       const int l = tid + it * NTHREADS;
-      if (l >= SH::NSTAGE) continue;
-      if (l < NNODE) {
-        const int a = l % SH::NX_, b = l / SH::NX_;
-        const int I = I0 - 2 + a, J = J0 - 2 + b;
-        if (I > nx + 2 || J > ny + 2) continue;
-        R ulx = pre[it][0], uly = pre[it][1], dx = dt * pre[it][2], dy = dt * pre[it][3];
-        if (refl_node(I, nx) != I) {
-          ulx = -ulx;
-          dx = -dx;
-        }
-        if (refl_node(J, ny) != J) {
-          uly = -uly;
-          dy = -dy;
-        }
-        sh.ulx[b][a] = ulx;
-        sh.uly[b][a] = uly;
-        sh.dx[b][a] = dx;
-        sh.dy[b][a] = dy;
-      } else if (l < NNODE + NPX) {
-        const int k = l - NNODE;
-        const int a = k % SH::PXW, b = k / SH::PXW;
-        const int I = I0 - 1 + a;
-        const R sg = (I < 0 || I > nx) ? R(-1) : R(1);  // a mirrored x-face flux changes sign
-        sh.mx[b][a] = sg * pre[it][0];
-      } else if (l < NNODE + NPX + NPY) {
-        const int k = l - NNODE - NPX;
-        const int a = k % SH::PYW, b = k / SH::PYW;
-        const int J = J0 - 1 + b;
-        const R sg = (J < 0 || J > ny) ? R(-1) : R(1);
-        sh.my[b][a] = sg * pre[it][0];
-      } else {
-        const int k = l - NNODE - NPX - NPY;
-        const int a = k % SH::PCW, b = k / SH::PCW;
-        const int I = I0 - 1 + a, J = J0 - 1 + b;
-        const bool fx = I < 0 || I > nx, fy = J < 0 || J > ny;
-        // (main, anti) pair: the kind from the real node's displacement,
-        // then the mirrors (x: (d, a) -> (-a, -d); y: (d, a) -> (a, d))
-        const R F = pre[it][0];
-        R dg = R(0), an = R(0);
-        if (corner_main(dt * pre[it][1], dt * pre[it][2])) dg = F;
-        else an = F;
-        if (fy) { const R t = dg; dg = an; an = t; }
-        if (fx) { const R t = dg; dg = -an; an = -t; }
-        sh.cd[b][a] = dg;
-        sh.ca[b][a] = an;
+      const int a = l % SH::NX_, b = l / SH::NX_;
+      const int I = I0 - 2 + a, J = J0 - 2 + b;
+      if (l >= NNODE || I > nx + 2 || J > ny + 2) continue;
+      R ulx = pn[it][0], uly = pn[it][1], dx = dt * pn[it][2], dy = dt * pn[it][3];
+      if (refl_node(I, nx) != I) {
+        ulx = -ulx;
+        dx = -dx;
       }
+      if (refl_node(J, ny) != J) {
+        uly = -uly;
+        dy = -dy;
+      }
+      sh.ulx[b][a] = ulx;
+      sh.uly[b][a] = uly;
+      sh.dx[b][a] = dx;
+      sh.dy[b][a] = dy;
+    }
+#pragma unroll
+    for (int it = 0; it < ITX; ++it) {
+      const int k = tid + it * NTHREADS;
+      const int a = k % SH::PXW, b = k / SH::PXW;
+      const int I = I0 - 1 + a, j = J0 - 1 + b;
+      const int rI = I < 0 ? -I : (I > nx ? 2 * nx - I : I);
+      if (k >= NPX) continue;
+      const bool none = I > nx + 1 || j > ny || rI == 0 || rI == nx;  // wall or outside
+      const R sg = (I < 0 || I > nx) ? R(-1) : R(1);  // a mirrored x-face flux changes sign
+      sh.mx[b][a] = none ? R(0) : sg * px[it];
+    }
+#pragma unroll
+    for (int it = 0; it < ITY; ++it) {
+      const int k = tid + it * NTHREADS;
+      const int a = k % SH::PYW, b = k / SH::PYW;
+      const int i = I0 - 1 + a, J = J0 - 1 + b;
+      const int rJ = J < 0 ? -J : (J > ny ? 2 * ny - J : J);
+      if (k >= NPY) continue;
+      const bool none = i > nx || J > ny + 1 || rJ == 0 || rJ == ny;
+      const R sg = (J < 0 || J > ny) ? R(-1) : R(1);
+      sh.my[b][a] = none ? R(0) : sg * py[it];
+    }
+#pragma unroll
+    for (int it = 0; it < ITC; ++it) {
+      const int k = tid + it * NTHREADS;
+      const int a = k % SH::PCW, b = k / SH::PCW;
+      const int I = I0 - 1 + a, J = J0 - 1 + b;
+      if (k >= NPC) continue;
+      const bool fx = I < 0 || I > nx, fy = J < 0 || J > ny;
+      const int rI = refl_node(I, nx), rJ = refl_node(J, ny);
+      const bool none = I > nx + 1 || J > ny + 1 || rI == 0 || rI == nx || rJ == 0 || rJ == ny;
+      // (main, anti) pair: the kind from the real node's displacement,
+      // then the mirrors (x: (d, a) -> (-a, -d); y: (d, a) -> (a, d))
+      const R F = none ? R(0) : pc[it][0];
+      R dg = R(0), an = R(0);
+      if (corner_main(dt * pc[it][1], dt * pc[it][2])) dg = F;
+      else an = F;
+      if (fy) { const R t = dg; dg = an; an = t; }
+      if (fx) { const R t = dg; dg = -an; an = -t; }
+      sh.cd[b][a] = dg;
+      sh.ca[b][a] = an;
     }
     __syncthreads();
     auto L = [&](int I) { return I - (I0 - 2); };
@@ -1457,7 +1506,7 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
       // node-wise CFL bound: the largest sound speed of the adjacent cells
       R cmax = R(0);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) cmax = fmax(cmax, cs3[c]);
+      for (int c = 0; c < 4; ++c) cmax = fmax(cmax, ((cs_ok >> c) & 1) ? cs3[c] : R(0));
       const double bound = fmin(double(Dx / (cmax + fabs(ux))), double(Dy / (cmax + fabs(uy))));
       cand = (unsigned long long)__double_as_longlong(bound);
     }
