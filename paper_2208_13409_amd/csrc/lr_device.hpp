@@ -69,7 +69,8 @@ struct Prob {
   R *MX, *MY, *MC;                // signed total mass flux of x-faces, y-faces, corners
   int *mix_cell, *mix_slot;       // compacted mixed cells; cell -> list position or -1
   int mix_cap;
-  double *mix_W;                  // [mix_cap][8][nmat] outflow partial volumes (FP64)
+  R *mix_W;                       // [mix_cap][8][nmat] outflow partial volumes (formed in
+                                  // FP64, stored in the bulk precision)
   Ctl *ctl;
   Dbg<R> dbg;
 };

@@ -53,7 +53,7 @@ size_t carve_prob(Prob<R> &P, char *base, const Grid &g, bool stages, Ctl *ctl) 
   P.MX = cv.take<R>(nX); P.MY = cv.take<R>(nY); P.MC = cv.take<R>(N);
   P.mix_cell = cv.take<int>(C); P.mix_slot = cv.take<int>(C);
   P.mix_cap = (int)C;
-  P.mix_W = cv.take<double>(C * 8 * m);
+  P.mix_W = cv.take<R>(C * 8 * m);
   if (stages) {
     P.dbg.Q = cv.take<R>(C); P.dbg.S = cv.take<R>(C); P.dbg.VL = cv.take<R>(C);
     P.dbg.Ph = cv.take<R>(m * C); P.dbg.volcf = cv.take<R>(C);

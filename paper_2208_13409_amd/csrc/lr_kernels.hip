@@ -80,7 +80,7 @@ struct Acc<double> {
 template <typename R, int NM, typename ProbT>
 __device__ void mixed_region_partials(const ProbT &P, const R *Vs, int i, int j, int s, R blx_r,
                                       R bly_r, R brx_r, R bry_r, R tlx_r, R tly_r, R trx_r,
-                                      R try_r, double *Wout) {
+                                      R try_r, R *Wout) {
   const auto &g = P.g;
   const int nx = g.nx, ny = g.ny, C = nx * ny, q = j * nx + i;
   // all of the cell's loads first (one memory latency): its partial volumes
@@ -311,7 +311,7 @@ __device__ void mixed_region_partials(const ProbT &P, const R *Vs, int i, int j,
     }
   }
 #pragma unroll
-  for (int m = 0; m < NM; ++m) stg(Wout + (s * NM + m), out ? W[m] : 0.0);
+  for (int m = 0; m < NM; ++m) stg(Wout + (s * NM + m), R(out ? W[m] : 0.0));
 }
 
 // =========================================================== k_lagrange
@@ -671,6 +671,7 @@ struct RemapShared {
   R vcf[NCY][NCX], xc[NCY][NCX], yc[NCY][NCX], wx[NCY][NCX], wy[NCY][NCX];
   signed char pure[NCY][NCX];  // material of a pure cell, -1 mixed; +16 once P5 keeps order 2
   R mpure[NCY][NCX];   // the pure material's mass (positivity guard)
+  int mslot[NCY][NCX];  // a mixed cell's position in the list of partial volumes
   R rcf[NM][NCY][NCX], el[NM][NCY][NCX];
   // per region (x-faces, then y-faces, then corners): the order-2 mass and
   // energy fluxes of a pure donor, and the region's slot in its donor's frame
@@ -712,10 +713,9 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
 
   // Global loads issued before any is used (one memory latency for several
   // phases): u^{n+1/2} of the staged nodes (P1), the owned cell's V, M (P6)
-  // and, in FP32 where the registers allow it, the records' V, M, e^{lag} (P3).
+  // and the records' V, M, e^{lag} and list positions (P3).
   constexpr int NIT1 = (SH::NNX * SH::NNY + NTHREADS - 1) / NTHREADS;
   constexpr int NIT3 = (SH::NCX * SH::NCY + NTHREADS - 1) / NTHREADS;
-  constexpr bool PRE3 = sizeof(R) == 4;
   R pre1[NIT1][2];
 #pragma unroll
   for (int it = 0; it < NIT1; ++it) {
@@ -737,15 +737,13 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
     V6[m] = own6 ? ldg(Vs + (m * C + q6)) : R(0);
     M6[m] = own6 ? ldg(Ms + (m * C + q6)) : R(0);
   }
-  R pre3[PRE3 ? NIT3 : 1][3 * NM];
-  // V, M, e^{lag} of record l (the real cell it mirrors)
+  // V, M, e^{lag} of record l (the real cell it mirrors); loaded here in
+  // FP32, in P3 in FP64 (issued early it does not pay there: the FP64 block
+  // is held to two per CU by its LDS and hides the latency with the other)
+  constexpr bool PRE3 = sizeof(R) == 4;
   auto fetch3 = [&](int l, R *out) {
     const int i = i0 - 2 + l % SH::NCX, j = j0 - 2 + l / SH::NCX;
-    if (l >= SH::NCX * SH::NCY || i > nx + 1 || j > ny + 1) {
-#pragma unroll
-      for (int k = 0; k < 3 * NM; ++k) out[k] = R(0);
-      return;
-    }
+    if (l >= SH::NCX * SH::NCY || i > nx + 1 || j > ny + 1) return;
     const int q = refl_cell(j, ny) * nx + refl_cell(i, nx);
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
@@ -754,6 +752,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       out[2 * NM + m] = ldg(P.eL + (m * C + q));
     }
   };
+  R pre3[PRE3 ? NIT3 : 1][3 * NM];
   if constexpr (PRE3) {
 #pragma unroll
     for (int it = 0; it < NIT3; ++it) fetch3(tid + it * NTHREADS, pre3[it]);
@@ -825,8 +824,10 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   __syncthreads();
 
   // ---- P3: cell records; ghost cells mirror the real ones
+  int ms3[NIT3];
 #pragma unroll
   for (int it = 0; it < NIT3; ++it) {
+    ms3[it] = -1;
     const int l = tid + it * NTHREADS;
     if (l >= SH::NCX * SH::NCY) continue;
     const int a = l % SH::NCX, b = l / SH::NCX;
@@ -891,6 +892,9 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       sh.el[m][b][a] = vme[2 * NM + m];
     }
     sh.pure[b][a] = np == 1 ? pm : -1;
+    // a mixed record's list position: loaded here, stored in LDS after P5,
+    // so that the load's latency is spent on P4 and P5
+    ms3[it] = np >= 2 ? ldg(P.mix_slot + q) : -1;
     R mp = R(0);
 #pragma unroll
     for (int m = 0; m < NM; ++m)
@@ -1026,8 +1030,13 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       }
       if (!(Mout > Mpm || Eout > Mpm * eD)) sh.pure[cb][ca] = pm + 16;
     }
-    __syncthreads();
   }
+#pragma unroll
+  for (int it = 0; it < NIT3; ++it) {
+    const int l = tid + it * NTHREADS;
+    if (l < SH::NCX * SH::NCY) sh.mslot[l / SH::NCX][l % SH::NCX] = ms3[it];
+  }
+  __syncthreads();
 
   // ---- P6: nine-point update of the tile's cells
   {
@@ -1042,8 +1051,11 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       const int rk[8] = {0, 0, 1, 1, 2, 2, 2, 2};
       const int rI[8] = {i, i + 1, i, i, i, i + 1, i, i + 1};
       const int rJ[8] = {j, j, j, j + 1, j, j, j + 1, j + 1};
-      R F[8][3 * NM];
-      R sgn[8];
+      // first every region's donor, and the loads of the partial volumes of
+      // the mixed donors (all issued before any is used), then the fluxes
+      R sgn[8], wr[8], dirs[8];
+      int dd[8], pqs[8], mss[8];
+      R wmx[8][NM];  // unset unless the region's donor is mixed
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
         bool mainc;
@@ -1065,18 +1077,34 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
           sgn[s] = (!wall && mine) ? ((s == 4 || s == 6) ? R(1) : R(-1)) : R(0);
           need = s == 4 ? !wall : sgn[s] != R(0);
         }
-#pragma unroll
-        for (int k = 0; k < 3 * NM; ++k) F[s][k] = R(0);
-        if (!need) continue;
         const bool neg = signbit(sv);
         const RegionRef rf = region_donor(rk[s], rI[s], rJ[s], neg, mainc);
-        const R dir = neg ? R(-1) : R(1);
-        const R w = fabs(sv);
+        dirs[s] = neg ? R(-1) : R(1);
+        wr[s] = fabs(sv);
         const int da = rf.di - (i0 - 2), db = rf.dj - (j0 - 2);
-        const int pq = sh.pure[db][da];
+        dd[s] = db * SH::NCX + da;
+        pqs[s] = need ? int(sh.pure[db][da]) : -2;  // -2: no flux
+        mss[s] = -1;
+        if (pqs[s] == -1) {
+          const int ms = sh.mslot[db][da];
+          if (ms >= 0 && ms < P.mix_cap) {
+            mss[s] = ms;
+            const R *src = P.mix_W + (size_t)ms * 8 * NM + rf.s * NM;
+#pragma unroll
+            for (int m = 0; m < NM; ++m) wmx[s][m] = ldg(src + m);
+          }
+        }
+      }
+      R F[8][3 * NM];
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+#pragma unroll
+        for (int k = 0; k < 3 * NM; ++k) F[s][k] = R(0);
+        const int pq = pqs[s], d = dd[s];  // donor record, flattened
+        const R dir = dirs[s], w = wr[s];
         if (pq >= 0) {
           const int pm = pq & 15;
-          const R rho = sh.rcf[pm][db][da], e = sh.el[pm][db][da];
+          const R rho = (&sh.rcf[pm][0][0])[d], e = (&sh.el[pm][0][0])[d];
           R mu = w > R(0) ? rho * w : R(0);
           R ep = w > R(0) ? mu * e : R(0);
           if (o2 && pq >= 16) {  // order 2 kept by the guard: the region's own fluxes
@@ -1091,20 +1119,15 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
               F[s][NM + m] = dir * mu;
               F[s][2 * NM + m] = dir * ep;
             }
-        } else {
-          const int dq = rf.dj * nx + rf.di;
-          const int ms = ldg(P.mix_slot + dq);
-          if (ms >= 0 && ms < P.mix_cap) {
-            const double *src = P.mix_W + (size_t)ms * 8 * NM + rf.s * NM;
+        } else if (pq == -1 && mss[s] >= 0) {
 #pragma unroll
-            for (int m = 0; m < NM; ++m) {
-              const R wm = R(ldg(src + m));
-              const R mu = wm > R(0) ? sh.rcf[m][db][da] * wm : R(0);
-              const R ep = wm > R(0) ? mu * sh.el[m][db][da] : R(0);
-              F[s][m] = dir * wm;
-              F[s][NM + m] = dir * mu;
-              F[s][2 * NM + m] = dir * ep;
-            }
+          for (int m = 0; m < NM; ++m) {
+            const R wm = wmx[s][m];
+            const R mu = wm > R(0) ? (&sh.rcf[m][0][0])[d] * wm : R(0);
+            const R ep = wm > R(0) ? mu * (&sh.el[m][0][0])[d] : R(0);
+            F[s][m] = dir * wm;
+            F[s][NM + m] = dir * mu;
+            F[s][2 * NM + m] = dir * ep;
           }
         }
       }
