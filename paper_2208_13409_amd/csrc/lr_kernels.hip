@@ -668,10 +668,14 @@ struct RemapShared {
   static constexpr int NV = VXW * VXH + VYW * VYH + VCW * VCH;
   R ndx[NNY][NNX], ndy[NNY][NNX];
   R xv[XH][XW], yv[YH][YW];
-  R vcf[NCY][NCX], xc[NCY][NCX], yc[NCY][NCX], wx[NCY][NCX], wy[NCY][NCX];
+  R vcf[NCY][NCX], xc[NCY][NCX], yc[NCY][NCX];
   signed char pure[NCY][NCX];  // material of a pure cell, -1 mixed; +16 once P5 keeps order 2
-  R mpure[NCY][NCX];   // the pure material's mass (positivity guard)
-  int mslot[NCY][NCX];  // a mixed cell's position in the list of partial volumes
+  // a pure cell's mass of its material (positivity guard, P5); once P5 is
+  // done, a mixed cell's position in the list of partial volumes (P6)
+  union MassOrSlot {
+    R mass;
+    int slot;
+  } mps[NCY][NCX];
   R rcf[NM][NCY][NCX], el[NM][NCY][NCX];
   // per region (x-faces, then y-faces, then corners): the order-2 mass and
   // energy fluxes of a pure donor, and the region's slot in its donor's frame
@@ -824,10 +828,10 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   __syncthreads();
 
   // ---- P3: cell records; ghost cells mirror the real ones
-  int ms3[NIT3];
+  int ms3[NIT3];  // list position of a mixed record (-1: not listed); -2 not mixed
 #pragma unroll
   for (int it = 0; it < NIT3; ++it) {
-    ms3[it] = -1;
+    ms3[it] = -2;
     const int l = tid + it * NTHREADS;
     if (l >= SH::NCX * SH::NCY) continue;
     const int a = l % SH::NCX, b = l / SH::NCX;
@@ -877,8 +881,6 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
     sh.vcf[b][a] = v;
     sh.xc[b][a] = xc;
     sh.yc[b][a] = yc;
-    sh.wx[b][a] = Dx + R(0.5) * ((brx + trx) - (blx + tlx));
-    sh.wy[b][a] = Dy + R(0.5) * ((tly + try_) - (bly + bry));
     int np = 0, pm = -1;
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
@@ -894,12 +896,12 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
     sh.pure[b][a] = np == 1 ? pm : -1;
     // a mixed record's list position: loaded here, stored in LDS after P5,
     // so that the load's latency is spent on P4 and P5
-    ms3[it] = np >= 2 ? ldg(P.mix_slot + q) : -1;
+    ms3[it] = np >= 2 ? ldg(P.mix_slot + q) : -2;
     R mp = R(0);
 #pragma unroll
     for (int m = 0; m < NM; ++m)
       if (m == pm) mp = vme[NM + m];
-    sh.mpure[b][a] = mp;
+    sh.mps[b][a].mass = mp;
     if (ri == i && rj == j && a >= 2 && b >= 2 && a < TX + 2 && b < TY + 2) {
       if (!(v > R(0))) atomicOr(&ctl->err, ERR_VOLCF);
       if (P.dbg.volcf) stg(P.dbg.volcf + q, v);
@@ -962,7 +964,15 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       const R rD = sh.rcf[pm][cb][ca], eD = sh.el[pm][cb][ca];
       R vr = rD, ve = eD;
       const int na = NA(rf.di), nb = NB(rf.dj);  // donor's BL node
-      const R dxL = sh.wx[cb][ca], dyL = sh.wy[cb][ca];
+      // the donor's Lagrangian widths, from the nodes of the real cell it
+      // mirrors (as its record's centre is formed)
+      const int ra = NA(refl_cell(rf.di, nx)), rb = NB(refl_cell(rf.dj, ny));
+      auto width_x = [&]() {
+        return Dx + R(0.5) * ((sh.ndx[rb][ra + 1] + sh.ndx[rb + 1][ra + 1]) - (sh.ndx[rb][ra] + sh.ndx[rb + 1][ra]));
+      };
+      auto width_y = [&]() {
+        return Dy + R(0.5) * ((sh.ndy[rb + 1][ra] + sh.ndy[rb + 1][ra + 1]) - (sh.ndy[rb][ra] + sh.ndy[rb][ra + 1]));
+      };
       const int s = rf.s;
       int si, sj;
       R vx, vy, off;
@@ -970,13 +980,14 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
         const R sg = s == 0 ? R(-1) : R(1);
         const R lo = sh.ndx[nb][na + (s == 1)], hi = sh.ndx[nb + 1][na + (s == 1)];
         si = 1; sj = 0; vx = R(1); vy = R(0);
-        off = sg * dxL - R(0.5) * (lo + hi);
+        off = sg * width_x() - R(0.5) * (lo + hi);
       } else if (s < 4) {
         const R sg = s == 2 ? R(-1) : R(1);
         const R lo = sh.ndy[nb + (s == 3)][na], hi = sh.ndy[nb + (s == 3)][na + 1];
         si = 0; sj = 1; vx = R(0); vy = R(1);
-        off = sg * dyL - R(0.5) * (lo + hi);
+        off = sg * width_y() - R(0.5) * (lo + hi);
       } else {
+        const R dxL = width_x(), dyL = width_y();
         const int cn = s - 4;  // BL, BR, TL, TR node of the donor
         const R cdx = sh.ndx[nb + (cn >> 1)][na + (cn & 1)], cdy = sh.ndy[nb + (cn >> 1)][na + (cn & 1)];
         const R sx = cdx >= R(0) ? R(1) : R(-1);
@@ -1013,7 +1024,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       const int ca = di - (i0 - 2), cb = dj - (j0 - 2);
       const int pm = sh.pure[cb][ca];
       if (pm < 0) continue;
-      const R Mpm = sh.mpure[cb][ca];
+      const R Mpm = sh.mps[cb][ca].mass;
       const R eD = sh.el[pm][cb][ca];
       // the donor's eight regions in the region arrays: W, E faces, S, N
       // faces, corners at its BL, BR, TL, TR nodes; a region is an outflow
@@ -1034,7 +1045,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
 #pragma unroll
   for (int it = 0; it < NIT3; ++it) {
     const int l = tid + it * NTHREADS;
-    if (l < SH::NCX * SH::NCY) sh.mslot[l / SH::NCX][l % SH::NCX] = ms3[it];
+    if (l < SH::NCX * SH::NCY && ms3[it] != -2) sh.mps[l / SH::NCX][l % SH::NCX].slot = ms3[it];
   }
   __syncthreads();
 
@@ -1086,7 +1097,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
         pqs[s] = need ? int(sh.pure[db][da]) : -2;  // -2: no flux
         mss[s] = -1;
         if (pqs[s] == -1) {
-          const int ms = sh.mslot[db][da];
+          const int ms = sh.mps[db][da].slot;
           if (ms >= 0 && ms < P.mix_cap) {
             mss[s] = ms;
             const R *src = P.mix_W + (size_t)ms * 8 * NM + rf.s * NM;
