@@ -1240,7 +1240,9 @@ struct DualShared {
   static constexpr int PCW = TX + 2, PCH = TY + 2;
   R ulx[NY_][NX_], uly[NY_][NX_], dx[NY_][NX_], dy[NY_][NX_];
   R mx[PXH][PXW], my[PYH][PYW], cd[PCH][PCW], ca[PCH][PCW];
-  R fx[3][NXF], fy[3][NYF], fd[3][NCN], fa[3][NCN];
+  // momentum fluxes (x, y components) of the dual regions; their mass fluxes
+  // are re-formed from the staged primal fluxes where the nodes sum them
+  R fx[2][NXF], fy[2][NYF], fd[2][NCN], fa[2][NCN];
 };
 
 template <typename R, int NM>
@@ -1445,9 +1447,8 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
         const R off = R(0.5) * (sg * wxd(L(D), M_(J)) - df);
         R u, v;
         recon(L(D), M_(J), 1, 0, R(1), R(0), off, u, v);
-        sh.fx[0][l] = phi;
-        sh.fx[1][l] = phi * u;
-        sh.fx[2][l] = phi * v;
+        sh.fx[0][l] = phi * u;
+        sh.fx[1][l] = phi * v;
       } else if (l < SH::NXF + SH::NYF) {  // dual y-face (I,J): nodes (I,J-1)-(I,J)
         const int k = l - SH::NXF;
         const int a = k % TX, b = k / TX;
@@ -1460,9 +1461,8 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
         const R off = R(0.5) * (sg * wyd(L(I), M_(D)) - df);
         R u, v;
         recon(L(I), M_(D), 0, 1, R(0), R(1), off, u, v);
-        sh.fy[0][k] = phi;
-        sh.fy[1][k] = phi * u;
-        sh.fy[2][k] = phi * v;
+        sh.fy[0][k] = phi * u;
+        sh.fy[1][k] = phi * v;
       } else {  // dual corners at cell (i,j)
         const int k = l - SH::NXF - SH::NYF;
         const int a = k % (TX + 1), b = k / (TX + 1);
@@ -1484,9 +1484,8 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
           R u, v, off = R(0);
           if (o2) off = R(0.5) * ((sg * wxd(L(DI), M_(DJ)) - dcx) * vx + (sg * wyd(L(DI), M_(DJ)) - dcy) * vy);
           recon(L(DI), M_(DJ), 1, 1, vx, vy, off, u, v);
-          sh.fd[0][k] = phi;
-          sh.fd[1][k] = phi * u;
-          sh.fd[2][k] = phi * v;
+          sh.fd[0][k] = phi * u;
+          sh.fd[1][k] = phi * v;
         }
         {  // anti-diagonal: (i,j+1) -> (i+1,j)
           const R phi = R(0.25) * (a00 + a10 + a01 + a11);
@@ -1496,9 +1495,8 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
           R u, v, off = R(0);
           if (o2) off = R(0.5) * ((sg * wxd(L(DI), M_(DJ)) - dcx) * vx + (-sg * wyd(L(DI), M_(DJ)) - dcy) * vy);
           recon(L(DI), M_(DJ), 1, -1, vx, vy, off, u, v);
-          sh.fa[0][k] = phi;
-          sh.fa[1][k] = phi * u;
-          sh.fa[2][k] = phi * v;
+          sh.fa[0][k] = phi * u;
+          sh.fa[1][k] = phi * v;
         }
       }
     }
@@ -1520,14 +1518,27 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
         const int hNW = (b + 1) * (TX + 1) + a, hSE = b * (TX + 1) + a + 1;  // cells (I-1,J), (I,J-1)
         R m = mp3;
         R mu = m * ulx3, mv = m * uly3;
-        m += sh.fx[0][hW]; mu += sh.fx[1][hW]; mv += sh.fx[2][hW];
-        m -= sh.fx[0][hE]; mu -= sh.fx[1][hE]; mv -= sh.fx[2][hE];
-        m += sh.fy[0][hS]; mu += sh.fy[1][hS]; mv += sh.fy[2][hS];
-        m -= sh.fy[0][hN]; mu -= sh.fy[1][hN]; mv -= sh.fy[2][hN];
-        m += sh.fd[0][hSW]; mu += sh.fd[1][hSW]; mv += sh.fd[2][hSW];
-        m -= sh.fd[0][hNE]; mu -= sh.fd[1][hNE]; mv -= sh.fd[2][hNE];
-        m += sh.fa[0][hNW]; mu += sh.fa[1][hNW]; mv += sh.fa[2][hNW];
-        m -= sh.fa[0][hSE]; mu -= sh.fa[1][hSE]; mv -= sh.fa[2][hSE];
+        // mass fluxes of the eight dual regions, as stage 2 forms them
+        auto px = [&](int a_, int b_) {  // dual x-face at staged (a_, b_)
+          return R(0.25) * (sh.mx[b_][a_] + sh.mx[b_][a_ + 1] + sh.mx[b_ + 1][a_] + sh.mx[b_ + 1][a_ + 1]);
+        };
+        auto py = [&](int a_, int b_) {
+          return R(0.25) * (sh.my[b_][a_] + sh.my[b_][a_ + 1] + sh.my[b_ + 1][a_] + sh.my[b_ + 1][a_ + 1]);
+        };
+        auto pd = [&](int a_, int b_) {
+          return R(0.25) * (sh.cd[b_][a_] + sh.cd[b_][a_ + 1] + sh.cd[b_ + 1][a_] + sh.cd[b_ + 1][a_ + 1]);
+        };
+        auto pa = [&](int a_, int b_) {
+          return R(0.25) * (sh.ca[b_][a_] + sh.ca[b_][a_ + 1] + sh.ca[b_ + 1][a_] + sh.ca[b_ + 1][a_ + 1]);
+        };
+        m += px(a, b); mu += sh.fx[0][hW]; mv += sh.fx[1][hW];
+        m -= px(a + 1, b); mu -= sh.fx[0][hE]; mv -= sh.fx[1][hE];
+        m += py(a, b); mu += sh.fy[0][hS]; mv += sh.fy[1][hS];
+        m -= py(a, b + 1); mu -= sh.fy[0][hN]; mv -= sh.fy[1][hN];
+        m += pd(a, b); mu += sh.fd[0][hSW]; mv += sh.fd[1][hSW];
+        m -= pd(a + 1, b + 1); mu -= sh.fd[0][hNE]; mv -= sh.fd[1][hNE];
+        m += pa(a, b + 1); mu += sh.fa[0][hNW]; mv += sh.fa[1][hNW];
+        m -= pa(a + 1, b); mu -= sh.fa[0][hSE]; mv -= sh.fa[1][hSE];
         if (!(m > R(0))) atomicOr(&ctl->err, ERR_NODEMASS);
         ux = qdiv(mu, m);
         uy = qdiv(mv, m);
