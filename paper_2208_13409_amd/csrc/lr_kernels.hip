@@ -668,7 +668,7 @@ struct RemapShared {
   static constexpr int NV = VXW * VXH + VYW * VYH + VCW * VCH;
   R ndx[NNY][NNX], ndy[NNY][NNX];
   R xv[XH][XW], yv[YH][YW];
-  R vcf[NCY][NCX], xc[NCY][NCX], yc[NCY][NCX];
+  R xc[NCY][NCX], yc[NCY][NCX];
   signed char pure[NCY][NCX];  // material of a pure cell, -1 mixed; +16 once P5 keeps order 2
   // a pure cell's mass of its material (positivity guard, P5); once P5 is
   // done, a mixed cell's position in the list of partial volumes (P6)
@@ -678,10 +678,8 @@ struct RemapShared {
   } mps[NCY][NCX];
   R rcf[NM][NCY][NCX], el[NM][NCY][NCX];
   // per region (x-faces, then y-faces, then corners): the order-2 mass and
-  // energy fluxes of a pure donor, and the region's slot in its donor's frame
-  // (-1: no pure donor in the window)
+  // energy fluxes of a pure donor in the window (set for those regions only)
   R vm[NV], vq[NV];
-  signed char rslot[NV];
 };
 
 // the donor-frame region s (W, E, S, N, BL, BR, TL, TR) of region `kind`
@@ -827,6 +825,32 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   }
   __syncthreads();
 
+  // Vol^{lagCF} of the real cell whose BL node is staged at (na, nb):
+  // A + outflow - inflow over W, E, S, N, BL, BR, TL, TR (formed where it is
+  // used, P3 and P6, by the same operations)
+  auto cell_volcf = [&](int na, int nb) {
+    R v = A;
+    const R xw = sh.xv[nb][na], xe = sh.xv[nb][na + 1], ys = sh.yv[nb][na], yn = sh.yv[nb + 1][na];
+    if (signbit(xw)) v += fabs(xw); else v -= fabs(xw);
+    if (!signbit(xe)) v += fabs(xe); else v -= fabs(xe);
+    if (signbit(ys)) v += fabs(ys); else v -= fabs(ys);
+    if (!signbit(yn)) v += fabs(yn); else v -= fabs(yn);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const R cx = sh.ndx[nb + (c >> 1)][na + (c & 1)], cy = sh.ndy[nb + (c >> 1)][na + (c & 1)];
+      const bool sx = cx >= R(0), sy = cy >= R(0);
+      const R vol = fabs(cx * cy);
+      int role;
+      if (c == 0) role = (sx == sy) ? (sx ? -1 : 1) : 0;       // cell is NE of its BL node
+      else if (c == 1) role = (sx != sy) ? (sx ? 1 : -1) : 0;  // NW of its BR node
+      else if (c == 2) role = (sx != sy) ? (sx ? -1 : 1) : 0;  // SE of its TL node
+      else role = (sx == sy) ? (sx ? 1 : -1) : 0;              // SW of its TR node
+      if (role > 0) v += vol;
+      else if (role < 0) v -= vol;
+    }
+    return v;
+  };
+
   // ---- P3: cell records; ghost cells mirror the real ones
   int ms3[NIT3];  // list position of a mixed record (-1: not listed); -2 not mixed
 #pragma unroll
@@ -850,35 +874,13 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
             bry = sh.ndy[nb][na + 1];
     const R tlx = sh.ndx[nb + 1][na], tly = sh.ndy[nb + 1][na], trx = sh.ndx[nb + 1][na + 1],
             try_ = sh.ndy[nb + 1][na + 1];
-    // Vol^{lagCF} = A + outflow - inflow over W, E, S, N, BL, BR, TL, TR
-    R v = A;
-    {
-      const R xw = sh.xv[nb][na], xe = sh.xv[nb][na + 1], ys = sh.yv[nb][na], yn = sh.yv[nb + 1][na];
-      if (signbit(xw)) v += fabs(xw); else v -= fabs(xw);
-      if (!signbit(xe)) v += fabs(xe); else v -= fabs(xe);
-      if (signbit(ys)) v += fabs(ys); else v -= fabs(ys);
-      if (!signbit(yn)) v += fabs(yn); else v -= fabs(yn);
-      const R cx[4] = {blx, brx, tlx, trx}, cy[4] = {bly, bry, tly, try_};
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const bool sx = cx[c] >= R(0), sy = cy[c] >= R(0);
-        const R vol = fabs(cx[c] * cy[c]);
-        int role;
-        if (c == 0) role = (sx == sy) ? (sx ? -1 : 1) : 0;       // cell is NE of its BL node
-        else if (c == 1) role = (sx != sy) ? (sx ? 1 : -1) : 0;  // NW of its BR node
-        else if (c == 2) role = (sx != sy) ? (sx ? -1 : 1) : 0;  // SE of its TL node
-        else role = (sx == sy) ? (sx ? 1 : -1) : 0;              // SW of its TR node
-        if (role > 0) v += vol;
-        else if (role < 0) v -= vol;
-      }
-    }
+    const R v = cell_volcf(na, nb);
     R xc = R(0.25) * ((R(ri) * Dx + blx) + (R(ri + 1) * Dx + brx) + (R(ri) * Dx + tlx) +
                       (R(ri + 1) * Dx + trx));
     R yc = R(0.25) * ((R(rj) * Dy + bly) + (R(rj) * Dy + bry) + (R(rj + 1) * Dy + tly) +
                       (R(rj + 1) * Dy + try_));
     if (ri != i) xc = (i < 0 ? R(0) : R(2.0 * g.Lx)) - xc;
     if (rj != j) yc = (j < 0 ? R(0) : R(2.0 * g.Ly)) - yc;
-    sh.vcf[b][a] = v;
     sh.xc[b][a] = xc;
     sh.yc[b][a] = yc;
     int np = 0, pm = -1;
@@ -940,7 +942,6 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   if (o2) {
     for (int l = tid; l < SH::NV; l += NTHREADS) {
       int kind, I, J;
-      sh.rslot[l] = -1;
       if (l < SH::VXW * SH::VXH) {
         kind = 0; I = i0 - 1 + l % SH::VXW; J = j0 - 1 + l / SH::VXW;
         if (I < 0 || I > nx || J < 0 || J >= ny) continue;
@@ -1012,7 +1013,6 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       const R mu = vr * fabs(sv);
       sh.vm[l] = mu;
       sh.vq[l] = mu * ve;
-      sh.rslot[l] = rf.s;
     }
     __syncthreads();
 
@@ -1027,15 +1027,29 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       const R Mpm = sh.mps[cb][ca].mass;
       const R eD = sh.el[pm][cb][ca];
       // the donor's eight regions in the region arrays: W, E faces, S, N
-      // faces, corners at its BL, BR, TL, TR nodes; a region is an outflow
-      // of this donor iff P4 recorded this donor-frame slot for it
+      // faces, corners at its BL, BR, TL, TR nodes.  A region is an outflow
+      // of this donor iff the donor choice of P4 (sign of the region's volume,
+      // the corner's diagonal) names it
       const int vx0 = vidx(0, di, dj), vy0 = vidx(1, di, dj), vc0 = vidx(2, di, dj);
       const int vi8[8] = {vx0, vx0 + 1, vy0, vy0 + SH::VYW, vc0, vc0 + 1, vc0 + SH::VCW, vc0 + SH::VCW + 1};
+      const int na = NA(di), nb = NB(dj);
+      bool out[8];
+      out[0] = signbit(sh.xv[nb][na]);
+      out[1] = !signbit(sh.xv[nb][na + 1]);
+      out[2] = signbit(sh.yv[nb][na]);
+      out[3] = !signbit(sh.yv[nb + 1][na]);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const R cdx = sh.ndx[nb + (c >> 1)][na + (c & 1)], cdy = sh.ndy[nb + (c >> 1)][na + (c & 1)];
+        const bool mainc = corner_main(cdx, cdy), neg = !(cdx >= R(0));
+        // BL: main diagonal, flow to -x; BR: anti, +x; TL: anti, -x; TR: main, +x
+        out[4 + c] = (c == 0 || c == 3) ? (mainc && neg == (c == 0)) : (!mainc && neg == (c == 2));
+      }
       R Mout = R(0), Eout = R(0);
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
+        if (!out[s]) continue;
         const int vi = vi8[s];
-        if (sh.rslot[vi] != s) continue;  // not an outflow of this donor
         Mout += sh.vm[vi];
         Eout += sh.vq[vi];
       }
@@ -1056,6 +1070,13 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
     if (i < nx && j < ny) {
       const int q = j * nx + i;
       const int ca = a + 2, cb = b + 2;
+      // V^{lagCF}_a = k_a Vol^{lagCF}, formed first (few values are live here)
+      R Vcf[NM];
+      {
+        const R v = cell_volcf(NA(i), NB(j));
+#pragma unroll
+        for (int m = 0; m < NM; ++m) Vcf[m] = qdiv(V6[m], A) * v;
+      }
       // regions W, E, S, N (faces) and the corners at BL, BR, TL, TR;
       // sign +: into this cell along the region's orientation; walls and
       // corners of the other diagonal carry nothing
@@ -1142,14 +1163,13 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
           }
         }
       }
-      const R v = sh.vcf[cb][ca];
       R Vn[NM], Mn[NM], En[NM], Msa = R(0), Esa = R(0);
       bool bad_nan = false;
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
         const R M0 = M6[m];
         Acc<R> V, M, E;
-        V.init(qdiv(V6[m], A) * v);
+        V.init(Vcf[m]);
         M.init(M0);
         E.init(M0 * sh.el[m][cb][ca]);
 #pragma unroll
