@@ -78,7 +78,8 @@ typedef struct lr_ctx lr_ctx;
 void lr_default_opts(lr_opts *o);
 
 /* Create a problem context and allocate its device memory on the current HIP
- * device.  nx, ny >= 2; 1 <= nmat <= LR_MAXMAT; eos[nmat]; bc[4] = {xlo, xhi,
+ * device.  nx, ny >= 2, nx*ny <= 2^28 (32-bit cell indices with up to
+ * LR_MAXMAT materials); 1 <= nmat <= LR_MAXMAT; eos[nmat]; bc[4] = {xlo, xhi,
  * ylo, yhi}, all LR_BC_REFLECT (NULL means all reflective); opts NULL means
  * defaults.  *out receives the context (NULL on failure). */
 int lr_create(int nx, int ny, int nmat, const lr_eos *eos, const int bc[4],

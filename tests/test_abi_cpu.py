@@ -62,6 +62,9 @@ def test_argument_validation_without_device():
     h = ctypes.c_void_p()
     assert lib.lr_create(1, 4, 1, eos, None, ctypes.byref(o), ctypes.byref(h)) == lr.LR_EINVAL
     assert lib.lr_create(4, 4, 0, eos, None, ctypes.byref(o), ctypes.byref(h)) == lr.LR_EINVAL
+    # more than 2^28 cells: beyond the 32-bit cell indexing
+    assert lib.lr_create(1 << 15, (1 << 13) + 1, 1, eos, None, ctypes.byref(o),
+                         ctypes.byref(h)) == lr.LR_EINVAL
     o.precision = 7
     assert lib.lr_create(4, 4, 1, eos, None, ctypes.byref(o), ctypes.byref(h)) == lr.LR_EINVAL
     bad = (lr.lr_eos * 1)(lr.lr_eos(1.4, 3.0))
