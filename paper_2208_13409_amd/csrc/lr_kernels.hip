@@ -1128,12 +1128,17 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
         }
       }
       R F[8][3 * NM];
+      // FP32: materials that some added region carries (bit m); the sums of
+      // the others only add zeros and are skipped (a wave inside one material
+      // skips them all).  Not worth its instructions in the FP64 sums.
+      unsigned used = sizeof(R) == 4 ? 0u : ~0u;
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
 #pragma unroll
         for (int k = 0; k < 3 * NM; ++k) F[s][k] = R(0);
         const int pq = pqs[s], d = dd[s];  // donor record, flattened
         const R dir = dirs[s], w = wr[s];
+        if (sizeof(R) == 4 && sgn[s] != R(0)) used |= pq >= 0 ? 1u << (pq & 15) : (pq == -1 ? ~0u : 0u);
         if (pq >= 0) {
           const int pm = pq & 15;
           const R rho = (&sh.rcf[pm][0][0])[d], e = (&sh.el[pm][0][0])[d];
@@ -1172,12 +1177,14 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
         V.init(Vcf[m]);
         M.init(M0);
         E.init(M0 * sh.el[m][cb][ca]);
+        if ((used >> m) & 1u) {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          if (sgn[s] == R(0)) continue;
-          const R w = F[s][m], mu = F[s][NM + m], ep = F[s][2 * NM + m];
-          if (sgn[s] > R(0)) { V.add(w); M.add(mu); E.add(ep); }
-          else { V.add(-w); M.add(-mu); E.add(-ep); }
+          for (int s = 0; s < 8; ++s) {
+            if (sgn[s] == R(0)) continue;
+            const R w = F[s][m], mu = F[s][NM + m], ep = F[s][2 * NM + m];
+            if (sgn[s] > R(0)) { V.add(w); M.add(mu); E.add(ep); }
+            else { V.add(-w); M.add(-mu); E.add(-ep); }
+          }
         }
         Vn[m] = V.get();
         Mn[m] = M.get();
