@@ -1296,14 +1296,12 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
   const int p3 = own3 ? J3 * (nx + 1) + I3 : 0;
   // (every load is issued unconditionally from a clamped index and its value
   // zeroed where it is not wanted: loads under branches would be serialised)
-  R ux3 = ldg(P.ux + p3), uy3 = ldg(P.uy + p3), mp3 = R(0), ulx3 = R(0), uly3 = R(0), cs3[4];
-  if (!g.kinematic) {
-    mp3 = ldg(P.mp + p3);
-    ulx3 = ldg(P.uLx + p3);
-    uly3 = ldg(P.uLy + p3);
-  }
-  // (the owned node's values are used by its own thread only; the corner
-  // sound speeds are masked where they are used)
+  // (the owned node's values are used by its own thread only; its u^{lag} is
+  // read from the staged node data)
+  R ux3 = ldg(P.ux + p3), uy3 = ldg(P.uy + p3), mp3 = R(0);
+  if (!g.kinematic) mp3 = ldg(P.mp + p3);
+  // (the corner sound speeds are masked where they are used)
+  R cs3[4];
   int cs_ok = 0;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -1544,7 +1542,7 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
         const int hSW = b * (TX + 1) + a, hNE = (b + 1) * (TX + 1) + a + 1;  // cells (I-1,J-1), (I,J)
         const int hNW = (b + 1) * (TX + 1) + a, hSE = b * (TX + 1) + a + 1;  // cells (I-1,J), (I,J-1)
         R m = mp3;
-        R mu = m * ulx3, mv = m * uly3;
+        R mu = m * sh.ulx[b + 2][a + 2], mv = m * sh.uly[b + 2][a + 2];  // u^{lag} of the node
         // mass fluxes of the eight dual regions, as stage 2 forms them
         auto px = [&](int a_, int b_) {  // dual x-face at staged (a_, b_)
           return R(0.25) * (sh.mx[b_][a_] + sh.mx[b_][a_ + 1] + sh.mx[b_ + 1][a_] + sh.mx[b_ + 1][a_ + 1]);
