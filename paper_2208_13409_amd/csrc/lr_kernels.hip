@@ -539,7 +539,9 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
     }
     sdx[b][a] = dt * uhx;
     sdy[b][a] = dt * uhy;
-    if (a < TX && b < TY) {
+    // the tile owns nodes [I0, I0+TX) x [J0, J0+TY) (it runs over the cell
+    // tiles), the last tile of a row or column also the boundary nodes
+    if ((a < TX || I == nx) && (b < TY || J == ny)) {
       stg(P.uhx + p, uhx);
       stg(P.uhy + p, uhy);
       stg(P.uLx + p, uLx);
@@ -1883,8 +1885,10 @@ void step_impl(const Launch &L, int gpar, hipStream_t s, hipEvent_t *ev) {
   const bool loop = L.persistent && res.n[0] > 0 && res.n[1] > 0 && res.n[2] > 0 && res.n[3] > 0;
   const BlockMap *nm = L.node_map, *cm = L.cell_map;
   const int nb = L.node_blocks, cb = L.cell_blocks;
-  if (loop) launch(k_lagrange<R, NM, true>, dim3(grid(0, nb)), s, evk(0), p, nm, nb, gpar);
-  else launch(k_lagrange<R, NM, false>, dim3(nb), s, evk(0), p, nm, nb, gpar);
+  // the Lagrange kernel runs over the cell tiles: node tiles of a boundary
+  // node column or row alone would be one thirty-second or one eighth full
+  if (loop) launch(k_lagrange<R, NM, true>, dim3(grid(0, cb)), s, evk(0), p, cm, cb, gpar);
+  else launch(k_lagrange<R, NM, false>, dim3(cb), s, evk(0), p, cm, cb, gpar);
   launch(k_mixed<R, NM>, dim3(L.mix_chunks, L.nprob), s, evk(1), p, L.plist, gpar);
   if (loop) launch(k_remap<R, NM, true>, dim3(grid(2, cb)), s, evk(2), p, cm, cb, gpar);
   else launch(k_remap<R, NM, false>, dim3(cb), s, evk(2), p, cm, cb, gpar);
