@@ -190,7 +190,7 @@ int rebuild_maps(lr_batch *b) {
   b->node_blocks = (int)nm.size();
   b->cell_blocks = (int)cm.size();
   b->nprob = (int)pl.size();
-  b->mix_chunks = mix_chunks_for(cmax);
+  b->mix_chunks = mix_chunks_for(cmax, (int)pl.size());
   b->maps_dirty = false;
   b->graph_ok = false;
   return LR_OK;
