@@ -192,6 +192,15 @@ int lr_batch_submit(lr_batch *b, int nx, int ny, const lr_eos *eos, const lr_opt
  * check which finished.  *n_running (may be NULL) receives the number still
  * running.  Synchronizes. */
 int lr_batch_step(lr_batch *b, int *n_running);
+/* lr_batch_step in two halves, so that host work (admissions of new
+ * requests) runs while the chunk does: begin launches the chunk and returns
+ * at once; end waits for it and then behaves as lr_batch_step's check.
+ * Between the two, submit and release may be called, and poll, status,
+ * get_fields and totals on requests that are not running (a request
+ * submitted meanwhile joins at the next begin).  Begin while a chunk is in
+ * flight is LR_EINVAL; end with none in flight only counts. */
+int lr_batch_step_begin(lr_batch *b);
+int lr_batch_step_end(lr_batch *b, int *n_running);
 /* Ids of problems that finished (t_end or max_steps reached, or failed)
  * since the last poll, at most cap of them; *n receives the count. */
 int lr_batch_poll(lr_batch *b, long *ids, int cap, int *n);

@@ -58,6 +58,10 @@ class PoolRanges {
 struct BatchReq {
   long id = -1;
   bool used = false, running = false;
+  // admitted while a chunk was in flight: the chunk's copy of the control
+  // records overwrites this slot's mirror with stale data, restored from ctl0
+  bool fresh = false;
+  Ctl ctl0{};
   int rc = LR_OK;
   size_t off = 0, bytes = 0;
   Grid g{};
@@ -82,6 +86,9 @@ struct lr_batch {
   int *plist = nullptr;  // device [max_slots]: slots of the running problems
   int nprob = 0, mix_chunks = 16;
   bool maps_dirty = true;
+  bool inflight = false;    // a chunk launched by lr_batch_step_begin, not yet ended
+  bool chunk_timed = false;  // ... and timed for the autotuner
+  long long chunk_cells = 0;
   StepFn step = nullptr;
   std::vector<BatchReq> slots;
   std::unordered_map<long, int> where;  // request id -> slot
@@ -222,6 +229,8 @@ int batch_admit(lr_batch *b, int s, BatchReq &q, Prob<R> &P, const double *const
   Prob<R> *hp = reinterpret_cast<Prob<R> *>(tail + ((sizeof(Ctl) + 255) & ~size_t(255)));
   *hp = P;
   b->hctl[s] = *hc;
+  q.ctl0 = *hc;
+  q.fresh = b->inflight;
   HIP_B(b, hipMemcpyAsync(b->dstage, hk, nd * sizeof(double), hipMemcpyHostToDevice, b->stream));
   HIP_B(b, hipMemcpyAsync(b->ctl + s, hc, sizeof(Ctl), hipMemcpyHostToDevice, b->stream));
   HIP_B(b, hipMemcpyAsync(static_cast<char *>(b->dprobs) + s * b->prob_size, hp, sizeof(Prob<R>),
@@ -425,7 +434,7 @@ int lr_batch_submit(lr_batch *b, int nx, int ny, const lr_eos *eos, const lr_opt
   q.used = true;
   q.id = b->next_id++;
   b->where[q.id] = s;
-  const Slot &s0 = b->hctl[s].slot[0];
+  const Slot &s0 = q.ctl0.slot[0];
   if (s0.done) {
     b->finished.push_back(q.id);
   } else {
@@ -436,53 +445,78 @@ int lr_batch_submit(lr_batch *b, int nx, int ny, const lr_eos *eos, const lr_opt
   return LR_OK;
 }
 
-int lr_batch_step(lr_batch *b, int *n_running) {
+int lr_batch_step_begin(lr_batch *b) {
   if (!b) return LR_EINVAL;
+  if (b->inflight) return bset(b, LR_EINVAL, "a chunk is already in flight");
   int rc = LR_OK;
   if (b->maps_dirty) rc = rebuild_maps(b);
   if (rc) return rc;
+  if (b->node_blocks == 0) return LR_OK;  // nothing runs; the end call only counts
+  b->chunk_timed = b->o.autotune && b->tune_next < lr_batch::kCand;
+  b->chunk_cells = 0;
+  if (b->chunk_timed) {
+    set_schedule(b, b->tune_next);
+    for (const auto &q : b->slots)
+      if (q.running) b->chunk_cells += (long long)q.g.nx * q.g.ny;
+  }
+  rc = batch_chunk(b);
+  if (rc) return rc;
+  HIP_B(b, hipMemcpyAsync(b->hctl, b->ctl, sizeof(Ctl) * b->slots.size(), hipMemcpyDeviceToHost,
+                          b->stream));
+  b->inflight = true;
+  return LR_OK;
+}
+
+int lr_batch_step_end(lr_batch *b, int *n_running) {
+  if (!b) return LR_EINVAL;
   int running = 0;
-  if (b->node_blocks > 0) {
-    const bool timed = b->o.autotune && b->tune_next < lr_batch::kCand;
-    long long cells = 0;
-    if (timed) {
-      set_schedule(b, b->tune_next);
-      for (const auto &q : b->slots)
-        if (q.running) cells += (long long)q.g.nx * q.g.ny;
+  if (!b->inflight) {
+    for (const auto &q : b->slots) running += q.running;
+    if (n_running) *n_running = running;
+    return LR_OK;
+  }
+  b->inflight = false;
+  HIP_B(b, hipStreamSynchronize(b->stream));
+  for (size_t s = 0; s < b->slots.size(); ++s) {
+    BatchReq &q = b->slots[s];
+    if (q.used && q.fresh) {
+      b->hctl[s] = q.ctl0;
+      q.fresh = false;
     }
-    rc = batch_chunk(b);
-    if (rc) return rc;
-    HIP_B(b, hipMemcpyAsync(b->hctl, b->ctl, sizeof(Ctl) * b->slots.size(), hipMemcpyDeviceToHost,
-                            b->stream));
-    HIP_B(b, hipStreamSynchronize(b->stream));
-    if (timed) {
-      float ms = 0.0f;
-      HIP_B(b, hipEventElapsedTime(&ms, b->tune_ev[0], b->tune_ev[1]));
-      b->tune_rate[b->tune_next] = ms > 0.0f ? double(cells) * b->o.chunk_steps / ms : 0.0;
-      if (++b->tune_next == lr_batch::kCand) {
-        int best = 0;
-        for (int c = 1; c < lr_batch::kCand; ++c)
-          if (b->tune_rate[c] > b->tune_rate[best]) best = c;
-        set_schedule(b, best);
-      }
+  }
+  if (b->chunk_timed) {
+    float ms = 0.0f;
+    HIP_B(b, hipEventElapsedTime(&ms, b->tune_ev[0], b->tune_ev[1]));
+    b->tune_rate[b->tune_next] = ms > 0.0f ? double(b->chunk_cells) * b->o.chunk_steps / ms : 0.0;
+    if (++b->tune_next == lr_batch::kCand) {
+      int best = 0;
+      for (int c = 1; c < lr_batch::kCand; ++c)
+        if (b->tune_rate[c] > b->tune_rate[best]) best = c;
+      set_schedule(b, best);
     }
-    for (size_t s = 0; s < b->slots.size(); ++s) {
-      BatchReq &q = b->slots[s];
-      if (!q.running) continue;
-      const Ctl &k = b->hctl[s];
-      if (k.slot[cur_slot(k)].done || k.err) {
-        const char *msg = "";
-        q.rc = err_code(k.err, &msg);
-        q.running = false;
-        b->finished.push_back(q.id);
-        b->maps_dirty = true;
-      } else {
-        ++running;
-      }
+  }
+  for (size_t s = 0; s < b->slots.size(); ++s) {
+    BatchReq &q = b->slots[s];
+    if (!q.running) continue;
+    const Ctl &k = b->hctl[s];
+    if (k.slot[cur_slot(k)].done || k.err) {
+      const char *msg = "";
+      q.rc = err_code(k.err, &msg);
+      q.running = false;
+      b->finished.push_back(q.id);
+      b->maps_dirty = true;
+    } else {
+      ++running;
     }
   }
   if (n_running) *n_running = running;
   return LR_OK;
+}
+
+int lr_batch_step(lr_batch *b, int *n_running) {
+  const int rc = lr_batch_step_begin(b);
+  if (rc) return rc;
+  return lr_batch_step_end(b, n_running);
 }
 
 int lr_batch_running(lr_batch *b) {

@@ -28,7 +28,8 @@ EXPORTS = ("lr_default_opts", "lr_create", "lr_bind_stream", "lr_set_state", "lr
            "lr_step", "lr_run", "lr_get_fields", "lr_totals", "lr_debug_get", "lr_last_error",
            "lr_destroy", "lr_profile", "lr_profile_read", "lr_kernel_count", "lr_kernel_name",
            "lr_batch_default_opts", "lr_batch_create", "lr_batch_bind_stream", "lr_batch_footprint",
-           "lr_batch_submit", "lr_batch_step", "lr_batch_poll", "lr_batch_status",
+           "lr_batch_submit", "lr_batch_step", "lr_batch_step_begin", "lr_batch_step_end",
+           "lr_batch_poll", "lr_batch_status",
            "lr_batch_get_fields", "lr_batch_totals", "lr_batch_release", "lr_batch_running",
            "lr_batch_schedule", "lr_batch_last_error", "lr_batch_destroy")
 LR_F64_IN, LR_F32_IN = 0, 1  # element types of lr_set_state_device
@@ -107,6 +108,8 @@ def load():
     lib.lr_batch_submit.argtypes = [vp, C.c_int, C.c_int, P(lr_eos), P(lr_opts), C.c_double, C.c_long,
                                     dp, dp, dp, dp, dp, P(C.c_long)]
     lib.lr_batch_step.argtypes = [vp, P(C.c_int)]
+    lib.lr_batch_step_begin.argtypes = [vp]
+    lib.lr_batch_step_end.argtypes = [vp, P(C.c_int)]
     lib.lr_batch_poll.argtypes = [vp, P(C.c_long), C.c_int, P(C.c_int)]
     lib.lr_batch_status.argtypes = [vp, C.c_long, P(C.c_int), P(C.c_long), dp]
     lib.lr_batch_get_fields.argtypes = [vp, C.c_long, C.c_uint, P(dp)]
@@ -122,8 +125,9 @@ def load():
     for n in ("lr_create", "lr_bind_stream", "lr_set_state", "lr_set_state_device", "lr_step",
               "lr_run", "lr_get_fields", "lr_totals", "lr_debug_get", "lr_profile",
               "lr_profile_read", "lr_kernel_count", "lr_batch_create", "lr_batch_bind_stream",
-              "lr_batch_submit", "lr_batch_step", "lr_batch_poll", "lr_batch_status",
-              "lr_batch_get_fields", "lr_batch_totals", "lr_batch_release", "lr_batch_running"):
+              "lr_batch_submit", "lr_batch_step", "lr_batch_step_begin", "lr_batch_step_end",
+              "lr_batch_poll", "lr_batch_status", "lr_batch_get_fields", "lr_batch_totals",
+              "lr_batch_release", "lr_batch_running"):
         getattr(lib, n).restype = C.c_int
     _LIB = lib
     return lib
@@ -337,6 +341,16 @@ class Batch:
         """one chunk of steps; returns the number of problems still running"""
         n = C.c_int()
         self._check(self.lib.lr_batch_step(self.h, C.byref(n)))
+        return n.value
+
+    def step_begin(self):
+        """launch one chunk and return at once (host work may overlap it)"""
+        self._check(self.lib.lr_batch_step_begin(self.h))
+
+    def step_end(self):
+        """wait for the chunk in flight; returns the number still running"""
+        n = C.c_int()
+        self._check(self.lib.lr_batch_step_end(self.h, C.byref(n)))
         return n.value
 
     def poll(self, cap=4096):

@@ -5,8 +5,10 @@ slot and a range of its device pool are free (admission by device-memory
 footprint: ``submit`` declines while the request does not fit).  It then
 runs in the shared launches with whatever else is running, and its result
 fields are copied to the host when it finishes, after which its slot and
-memory are released for the next one.  Latency is measured from a
-request's arrival to its fields being on the host.
+memory are released for the next one.  Admissions (host-side checks and
+staging of the inputs) run while a chunk of steps is in flight on the
+device.  Latency is measured from a request's arrival to its fields being
+on the host.
 """
 import collections
 import time
@@ -24,7 +26,7 @@ def serve(batch, requests, arrivals, fields=("rho", "p"), keep=False):
 
     Returns a dict: per-request latency, steps and cells, the fields when
     ``keep``, the wall time, the cell-updates served per second, the share of
-    the wall time spent stepping, and p50/p99 latency."""
+    the wall time with a chunk of steps in flight, and p50/p99 latency."""
     n = len(requests)
     order = sorted(range(n), key=lambda i: arrivals[i])
     lat, steps, rcs = [None] * n, [0] * n, [None] * n
@@ -39,30 +41,9 @@ def serve(batch, requests, arrivals, fields=("rho", "p"), keep=False):
     def clock():
         return time.perf_counter() - t0
 
-    while done < n:
-        now = clock()
-        while nxt < n and arrivals[order[nxt]] <= now:
-            queue.append(order[nxt])
-            nxt += 1
-        while queue:
-            i = queue[0]
-            rid = batch.submit(requests[i], requests[i]["t_end"])
-            if rid is None:
-                if batch.running() == 0 and not ids:
-                    raise RuntimeError(f"request {i} does not fit in an empty batch")
-                break
-            ids[rid] = i
-            queue.popleft()
-        running = batch.running()
-        max_running = max(max_running, running)
-        if running == 0 and not ids:
-            if nxt < n:  # idle until the next arrival
-                time.sleep(max(0.0, arrivals[order[nxt]] - clock()))
-            continue
-        tb = clock()
-        if running:
-            batch.step()
-        busy += clock() - tb
+    def collect():
+        """fields of the finished requests to the host, then their release"""
+        nonlocal done
         for rid in batch.poll():
             i = ids.pop(rid)
             rc, st, _ = batch.status(rid)
@@ -73,6 +54,40 @@ def serve(batch, requests, arrivals, fields=("rho", "p"), keep=False):
                 results[i] = out
             batch.release(rid)
             done += 1
+
+    inflight = False  # a chunk launched and not yet waited for
+    t_launch = 0.0
+    while done < n:
+        now = clock()
+        while nxt < n and arrivals[order[nxt]] <= now:
+            queue.append(order[nxt])
+            nxt += 1
+        # admissions: their host work overlaps the chunk in flight
+        while queue:
+            i = queue[0]
+            rid = batch.submit(requests[i], requests[i]["t_end"])
+            if rid is None:
+                if batch.running() == 0 and not ids and not inflight:
+                    raise RuntimeError(f"request {i} does not fit in an empty batch")
+                break
+            ids[rid] = i
+            queue.popleft()
+        if inflight:
+            batch.step_end()
+            busy += clock() - t_launch
+            inflight = False
+            collect()
+            continue  # admit what arrived meanwhile and what now fits
+        running = batch.running()
+        max_running = max(max_running, running)
+        if running:
+            t_launch = clock()
+            batch.step_begin()
+            inflight = True
+        else:
+            collect()  # requests that finished at admission (nothing to step)
+            if not ids and nxt < n:  # idle until the next arrival
+                time.sleep(max(0.0, arrivals[order[nxt]] - clock()))
     wall = clock()
     cells = [r["nx"] * r["ny"] for r in requests]
     served = float(sum(c * s for c, s in zip(cells, steps)))

@@ -134,6 +134,45 @@ def test_continuous_admission_and_release():
     assert sorted(finished) == list(range(len(ps)))
 
 
+def test_admission_while_a_chunk_is_in_flight():
+    """lr_batch_step_begin / _end: requests submitted and released while a
+    chunk runs join at the next chunk; each result equals the problem alone,
+    and a second begin while one is in flight is refused."""
+    ps = problems(seeds=(41, 42, 43, 44, 45), sizes=((48, 32), (64, 40), (40, 40), (72, 24), (32, 56)))
+    b = Batch(nmat=2, precision=LR_FP64, max_slots=3, pool_bytes=64 << 20, chunk_steps=4)
+    steps = [12, 8, 16, 4, 8]
+    pending = list(range(len(ps)))
+    ids = {}
+    finished = []
+    rid = b.submit(ps[0], 1e30, max_steps=steps[0])
+    ids[rid] = 0
+    pending.pop(0)
+    for _ in range(1000):
+        b.step_begin()
+        with pytest.raises(LRError):
+            b.step_begin()
+        while pending:  # admitted while the chunk runs
+            k = pending[0]
+            rid = b.submit(ps[k], 1e30, max_steps=steps[k])
+            if rid is None:
+                break
+            ids[rid] = k
+            pending.pop(0)
+        b.step_end()
+        for rid in b.poll():
+            k = ids[rid]
+            g, n, _ = alone(ps[k], LR_FP64, steps=steps[k])
+            rc, st, _ = b.status(rid)
+            assert rc == LR_OK and st == steps[k], (k, rc, st)
+            same_fields(b.fields(rid, *FIELDS), g.fields(*FIELDS), f"request {k}")
+            b.release(rid)
+            finished.append(k)
+        if not pending and b.running() == 0:
+            break
+    assert sorted(finished) == list(range(len(ps)))
+    assert b.step_end() == 0  # none in flight: only counts
+
+
 def test_pool_full_is_eagain_then_fits_after_release():
     p = inputs.random_mixed(41, 64, 64)
     probe = Batch(nmat=2, precision=LR_FP32, max_slots=4, pool_bytes=1 << 20)
