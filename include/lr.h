@@ -37,7 +37,7 @@ enum { LR_BC_REFLECT = 0 };     /* the only boundary: reflective wall          *
 enum { LR_FP64 = 0, LR_FP32 = 1 };
 
 /* material equation of state: perfect gas p = (gamma-1) rho e (paper §5.1);
- * pinf must be 0 (stiffened gas is not part of this build) */
+ * pinf must be 0 (the stiffened-gas form is not implemented) */
 typedef struct { double gamma, pinf; } lr_eos;
 
 typedef struct {

@@ -435,7 +435,7 @@ def test_limited_advection_makes_no_new_extrema():
             s.step()
         res[order] = s.fields("mass")["mass"][0]
     # the walls hold u_x = 0, so the flow empties the cells behind it from the
-    # left wall on (about U per step) and piles up at the right wall: judge
+    # left wall on (about U per step) and piles up at the right wall: check
     # only the cells neither wall effect has reached
     r2 = res[2][:, 16:-4]
     assert r2.max() <= 3.0 * (1 + 1e-13) and r2.min() >= 1.0 * (1 - 1e-13)
