@@ -198,7 +198,8 @@ int lr_batch_step(lr_batch *b, int *n_running);
  * Between the two, submit and release may be called, and poll, status,
  * get_fields and totals on requests that are not running (a request
  * submitted meanwhile joins at the next begin).  Begin while a chunk is in
- * flight is LR_EINVAL; end with none in flight only counts. */
+ * flight is LR_EINVAL, and so is lr_batch_bind_stream; end with none in
+ * flight only counts. */
 int lr_batch_step_begin(lr_batch *b);
 int lr_batch_step_end(lr_batch *b, int *n_running);
 /* Ids of problems that finished (t_end or max_steps reached, or failed)

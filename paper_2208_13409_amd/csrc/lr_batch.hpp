@@ -375,6 +375,7 @@ int lr_batch_create(const lr_batch_opts *opts, lr_batch **out) {
 
 int lr_batch_bind_stream(lr_batch *b, void *hip_stream) {
   if (!b) return LR_EINVAL;
+  if (b->inflight) return bset(b, LR_EINVAL, "a chunk is in flight: end it first");
   HIP_B(b, hipStreamSynchronize(b->stream));
   b->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : b->own;
   HIP_B(b, hipEventRecord(b->stage_ev, b->stream));
