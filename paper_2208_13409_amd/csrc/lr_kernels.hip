@@ -1274,7 +1274,7 @@ struct DualShared {
   R fx[2][NXF], fy[2][NYF], fd[2][NCN], fa[2][NCN];
 };
 
-template <typename R, int NM>
+template <typename R, int NM, int BT>
 __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap bm, int gpar) {
   using SH = DualShared<R>;
   __shared__ SH sh;
@@ -1294,7 +1294,7 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
   // (stage 1) are issued before any of them is used, so that the block waits
   // for memory once instead of once per stage and item.
   const int a3 = tid % TX, b3 = tid / TX, I3 = I0 + a3, J3 = J0 + b3;
-  const bool own3 = I3 <= nx && J3 <= ny;
+  const bool own3 = tid < TX * TY && I3 <= nx && J3 <= ny;  // (BT may exceed the tile)
   const int p3 = own3 ? J3 * (nx + 1) + I3 : 0;
   // (every load is issued unconditionally from a clamped index and its value
   // zeroed where it is not wanted: loads under branches would be serialised)
@@ -1320,13 +1320,13 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
   // Values of items that have none stay unset; stage 1 writes zero there.
   constexpr int NNODE = SH::NX_ * SH::NY_, NPX = SH::PXW * SH::PXH, NPY = SH::PYW * SH::PYH,
                 NPC = SH::PCW * SH::PCH;
-  constexpr int ITN = (NNODE + NTHREADS - 1) / NTHREADS, ITX = (NPX + NTHREADS - 1) / NTHREADS,
-                ITY = (NPY + NTHREADS - 1) / NTHREADS, ITC = (NPC + NTHREADS - 1) / NTHREADS;
+  constexpr int ITN = (NNODE + BT - 1) / BT, ITX = (NPX + BT - 1) / BT,
+                ITY = (NPY + BT - 1) / BT, ITC = (NPC + BT - 1) / BT;
   R pn[ITN][4], px[ITX], py[ITY], pc[ITC][3];
   if (!g.kinematic) {
 #pragma unroll
     for (int it = 0; it < ITN; ++it) {  // node: u^{lag}, u^{n+1/2}
-      const int l = tid + it * NTHREADS;
+      const int l = tid + it * BT;
       const int I = I0 - 2 + l % SH::NX_, J = J0 - 2 + l / SH::NX_;
       if (l < NNODE && I <= nx + 2 && J <= ny + 2) {
         const int p = refl_node(J, ny) * (nx + 1) + refl_node(I, nx);
@@ -1338,7 +1338,7 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
     }
 #pragma unroll
     for (int it = 0; it < ITX; ++it) {  // primal x-face mass flux
-      const int k = tid + it * NTHREADS;
+      const int k = tid + it * BT;
       const int I = I0 - 1 + k % SH::PXW, j = J0 - 1 + k / SH::PXW;
       const int rI = I < 0 ? -I : (I > nx ? 2 * nx - I : I);
       if (k < NPX && I <= nx + 1 && j <= ny && rI != 0 && rI != nx)
@@ -1346,7 +1346,7 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
     }
 #pragma unroll
     for (int it = 0; it < ITY; ++it) {  // primal y-face mass flux
-      const int k = tid + it * NTHREADS;
+      const int k = tid + it * BT;
       const int i = I0 - 1 + k % SH::PYW, J = J0 - 1 + k / SH::PYW;
       const int rJ = J < 0 ? -J : (J > ny ? 2 * ny - J : J);
       if (k < NPY && i <= nx && J <= ny + 1 && rJ != 0 && rJ != ny)
@@ -1354,7 +1354,7 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
     }
 #pragma unroll
     for (int it = 0; it < ITC; ++it) {  // corner mass flux and the node's displacement direction
-      const int k = tid + it * NTHREADS;
+      const int k = tid + it * BT;
       const int I = I0 - 1 + k % SH::PCW, J = J0 - 1 + k / SH::PCW;
       const int rI = refl_node(I, nx), rJ = refl_node(J, ny);
       if (k < NPC && I <= nx + 1 && J <= ny + 1 && rI != 0 && rI != nx && rJ != 0 && rJ != ny) {
@@ -1374,7 +1374,7 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
     // mirrored at walls, from the loads issued above
 #pragma unroll
     for (int it = 0; it < ITN; ++it) {
-      const int l = tid + it * NTHREADS;
+      const int l = tid + it * BT;
       const int a = l % SH::NX_, b = l / SH::NX_;
       const int I = I0 - 2 + a, J = J0 - 2 + b;
       if (l >= NNODE || I > nx + 2 || J > ny + 2) continue;
@@ -1394,7 +1394,7 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
     }
 #pragma unroll
     for (int it = 0; it < ITX; ++it) {
-      const int k = tid + it * NTHREADS;
+      const int k = tid + it * BT;
       const int a = k % SH::PXW, b = k / SH::PXW;
       const int I = I0 - 1 + a, j = J0 - 1 + b;
       const int rI = I < 0 ? -I : (I > nx ? 2 * nx - I : I);
@@ -1405,7 +1405,7 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
     }
 #pragma unroll
     for (int it = 0; it < ITY; ++it) {
-      const int k = tid + it * NTHREADS;
+      const int k = tid + it * BT;
       const int a = k % SH::PYW, b = k / SH::PYW;
       const int i = I0 - 1 + a, J = J0 - 1 + b;
       const int rJ = J < 0 ? -J : (J > ny ? 2 * ny - J : J);
@@ -1416,7 +1416,7 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
     }
 #pragma unroll
     for (int it = 0; it < ITC; ++it) {
-      const int k = tid + it * NTHREADS;
+      const int k = tid + it * BT;
       const int a = k % SH::PCW, b = k / SH::PCW;
       const int I = I0 - 1 + a, J = J0 - 1 + b;
       if (k >= NPC) continue;
@@ -1462,7 +1462,7 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
 
     // ---- stage 2: every dual region of the tile once: x-faces, y-faces,
     // then the corners, in one pass
-    for (int l = tid; l < SH::NXF + SH::NYF + SH::NCN; l += NTHREADS) {
+    for (int l = tid; l < SH::NXF + SH::NYF + SH::NCN; l += BT) {
       if (l < SH::NXF) {  // dual x-face (I,J): nodes (I-1,J)-(I,J)
         const int a = l % (TX + 1), b = l / (TX + 1);
         const int I = I0 + a, J = J0 + b;
@@ -1589,18 +1589,25 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
 // one block per tile of the map (LOOP false: grid = map), or a grid smaller
 // than the map whose blocks walk it (LOOP true; a separate instantiation,
 // since the loop keeps values live across tiles and costs registers)
-template <typename R, int NM, bool LOOP>
-__global__ void __launch_bounds__(NTHREADS) k_dual(const Prob<R> *probs, const BlockMap *map,
-                                                  int nmap, int gpar) {
+// WIDE: 512 threads per tile (two per node), so that each thread stages and
+// forms half as many items.  For small FP64 launches, where the grid is one
+// round of blocks and its time one tile's latency; with many tiles the 256-
+// thread form keeps more tiles per CU.
+template <typename R, int NM, bool LOOP, bool WIDE>
+__global__ void __launch_bounds__(WIDE ? 2 * NTHREADS : NTHREADS)
+    k_dual(const Prob<R> *probs, const BlockMap *map, int nmap, int gpar) {
+  constexpr int BT = WIDE ? 2 * NTHREADS : NTHREADS;
   if constexpr (LOOP) {
     for (int b = blockIdx.x; b < nmap; b += gridDim.x) {
-      dual_tile<R, NM>(probs, map_entry(map, b), gpar);
+      dual_tile<R, NM, BT>(probs, map_entry(map, b), gpar);
       __syncthreads();  // the next tile reuses the LDS
     }
   } else {
-    if (blockIdx.x < nmap) dual_tile<R, NM>(probs, map_entry(map, xcd_tile(blockIdx.x, nmap)), gpar);
+    if (blockIdx.x < nmap) dual_tile<R, NM, BT>(probs, map_entry(map, xcd_tile(blockIdx.x, nmap)), gpar);
   }
 }
+// launches of at most this many node tiles take the wide FP64 dual kernel
+constexpr int kWideDualMaxTiles = 1024;
 
 // =========================================================== set-up kernels
 template <typename R>
@@ -1834,7 +1841,7 @@ struct Resident {  // blocks of each step kernel resident on the whole device
     const void *fn[kKernels] = {reinterpret_cast<const void *>(&k_lagrange<R, NM, true>),
                                 reinterpret_cast<const void *>(&k_mixed<R, NM>),
                                 reinterpret_cast<const void *>(&k_remap<R, NM, true>),
-                                reinterpret_cast<const void *>(&k_dual<R, NM, true>)};
+                                reinterpret_cast<const void *>(&k_dual<R, NM, true, false>)};
     for (int k = 0; k < kKernels; ++k) {
       int per = 0;
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn[k], NTHREADS, 0) == hipSuccess)
@@ -1876,9 +1883,13 @@ void warm_resident(int nmat) {
 // a kernel launch; with ev, a start/stop event pair recorded by the dispatch
 // itself (kernel time only, as a kernel trace reports it)
 template <typename K, typename... Args>
+void launch_b(K kernel, dim3 grid, int block, hipStream_t s, hipEvent_t *ev, Args... args) {
+  if (ev) hipExtLaunchKernelGGL(kernel, grid, dim3(block), 0, s, ev[0], ev[1], 0, args...);
+  else kernel<<<grid, block, 0, s>>>(args...);
+}
+template <typename K, typename... Args>
 void launch(K kernel, dim3 grid, hipStream_t s, hipEvent_t *ev, Args... args) {
-  if (ev) hipExtLaunchKernelGGL(kernel, grid, dim3(NTHREADS), 0, s, ev[0], ev[1], 0, args...);
-  else kernel<<<grid, NTHREADS, 0, s>>>(args...);
+  launch_b(kernel, grid, NTHREADS, s, ev, args...);
 }
 
 // one step: ev (optional) holds a start/stop pair per kernel
@@ -1898,8 +1909,16 @@ void step_impl(const Launch &L, int gpar, hipStream_t s, hipEvent_t *ev) {
   launch(k_mixed<R, NM>, dim3(L.mix_chunks, L.nprob), s, evk(1), p, L.plist, gpar);
   if (loop) launch(k_remap<R, NM, true>, dim3(grid(2, cb)), s, evk(2), p, cm, cb, gpar);
   else launch(k_remap<R, NM, false>, dim3(cb), s, evk(2), p, cm, cb, gpar);
-  if (loop) launch(k_dual<R, NM, true>, dim3(grid(3, nb)), s, evk(3), p, nm, nb, gpar);
-  else launch(k_dual<R, NM, false>, dim3(nb), s, evk(3), p, nm, nb, gpar);
+  if (loop) {
+    launch(k_dual<R, NM, true, false>, dim3(grid(3, nb)), s, evk(3), p, nm, nb, gpar);
+  } else {
+    bool wide = false;
+    if constexpr (sizeof(R) == 8) {
+      wide = nb <= kWideDualMaxTiles;
+      if (wide) launch_b(k_dual<R, NM, false, true>, dim3(nb), 2 * NTHREADS, s, evk(3), p, nm, nb, gpar);
+    }
+    if (!wide) launch(k_dual<R, NM, false, false>, dim3(nb), s, evk(3), p, nm, nb, gpar);
+  }
 }
 using StepFn = void (*)(const Launch &, int, hipStream_t, hipEvent_t *);
 template <typename R>
