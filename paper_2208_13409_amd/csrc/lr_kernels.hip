@@ -315,7 +315,7 @@ __device__ void mixed_region_partials(const ProbT &P, const R *Vs, int i, int j,
 }
 
 // =========================================================== k_lagrange
-template <typename R, int NM>
+template <typename R, int NM, int BT>
 __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockMap bm, int gpar) {
   const auto &P = *cst(probs + bm.prob);
   const auto &g = P.g;
@@ -335,19 +335,19 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
   __shared__ R sPh[NM][CH][CW];
   __shared__ R sdx[NH][NW], sdy[NH][NW];
   __shared__ R sux[UH][UW], suy[UH][UW];
-  __shared__ int s_mix[NTHREADS];  // the tile's mixed cells (cell index)
+  __shared__ int s_mix[TX * TY];  // the tile's mixed cells (cell index)
   __shared__ int s_nmix, s_mixbase;
 
   // Global loads issued before any is used: the node velocities of the tile
   // (each once, into LDS), the cells' V, M, E (FP32, where the registers allow
   // it) and the owned cell's V, M, E (corrector).
-  constexpr int NITU = (UW * UH + NTHREADS - 1) / NTHREADS;
-  constexpr int NITC = (CW * CH + NTHREADS - 1) / NTHREADS;
+  constexpr int NITU = (UW * UH + BT - 1) / BT;
+  constexpr int NITC = (CW * CH + BT - 1) / BT;
   constexpr bool PREC = sizeof(R) == 4;
   R preu[NITU][2];
 #pragma unroll
   for (int it = 0; it < NITU; ++it) {
-    const int l = tid + it * NTHREADS;
+    const int l = tid + it * BT;
     const int I = I0 - 1 + l % UW, J = J0 - 1 + l / UW;
     const bool ok = l < UW * UH && I >= 0 && J >= 0 && I <= nx && J <= ny;
     preu[it][0] = ok ? ldg(P.ux + (J * (nx + 1) + I)) : R(0);
@@ -372,10 +372,10 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
   R prec[PREC ? NITC : 1][3 * NM];
   if constexpr (PREC) {
 #pragma unroll
-    for (int it = 0; it < NITC; ++it) fetchc(tid + it * NTHREADS, prec[it]);
+    for (int it = 0; it < NITC; ++it) fetchc(tid + it * BT, prec[it]);
   }
   const int a3 = tid % TX, b3 = tid / TX, i3 = I0 + a3, j3 = J0 + b3;
-  const bool own3 = i3 < nx && j3 < ny;
+  const bool own3 = tid < TX * TY && i3 < nx && j3 < ny;  // (BT may exceed the tile)
   const int q3 = own3 ? j3 * nx + i3 : 0;
   R pre3[3 * NM];
 #pragma unroll
@@ -390,7 +390,7 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
 
 #pragma unroll
   for (int it = 0; it < NITU; ++it) {
-    const int l = tid + it * NTHREADS;
+    const int l = tid + it * BT;
     if (l >= UW * UH) continue;
     sux[l / UW][l % UW] = preu[it][0];
     suy[l / UW][l % UW] = preu[it][1];
@@ -404,7 +404,7 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
   // ---- stage 1: predictor per cell (ghost cells mirror the real ones)
 #pragma unroll
   for (int it = 0; it < NITC; ++it) {
-    const int l = tid + it * NTHREADS;
+    const int l = tid + it * BT;
     if (l >= CW * CH) continue;
     const int a = l % CW, b = l / CW;
     const int i = I0 - 1 + a, j = J0 - 1 + b;
@@ -500,7 +500,7 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
   // work runs in the mixed-cell kernel, spread over the whole device)
   if (tid == 0) s_mixbase = s_nmix ? atomicAdd(&S.nmix, s_nmix) : 0;
   __syncthreads();
-  for (int kk = tid; kk < s_nmix; kk += NTHREADS) {
+  for (int kk = tid; kk < s_nmix; kk += BT) {
     const int q = s_mix[kk], pos = s_mixbase + kk;
     if (pos < P.mix_cap) {
       stg(P.mix_cell + pos, q);
@@ -512,7 +512,7 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
   }
 
   // ---- stage 2: nodal mass, gradient of P+Q, u^{n+1/2}, u^{lag}
-  for (int l = tid; l < NW * NH; l += NTHREADS) {
+  for (int l = tid; l < NW * NH; l += BT) {
     const int a = l % NW, b = l / NW;
     const int I = I0 + a, J = J0 + b;
     if (I > nx || J > ny) continue;
@@ -555,7 +555,7 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
   {
     const int a = tid % TX, b = tid / TX;
     const int i = I0 + a, j = J0 + b;
-    if (i < nx && j < ny) {
+    if (tid < TX * TY && i < nx && j < ny) {
       const int q = j * nx + i;
       const R blx = sdx[b][a], bly = sdy[b][a], brx = sdx[b][a + 1], bry = sdy[b][a + 1];
       const R tlx = sdx[b + 1][a], tly = sdy[b + 1][a], trx = sdx[b + 1][a + 1],
@@ -589,16 +589,18 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
 // one block per tile of the map (LOOP false: grid = map), or a grid smaller
 // than the map whose blocks walk it (LOOP true; a separate instantiation,
 // since the loop keeps values live across tiles and costs registers)
-template <typename R, int NM, bool LOOP>
-__global__ void __launch_bounds__(NTHREADS) k_lagrange(const Prob<R> *probs, const BlockMap *map,
-                                                  int nmap, int gpar) {
+// WIDE: 512 threads per tile, for small FP64 launches (as the dual kernel)
+template <typename R, int NM, bool LOOP, bool WIDE>
+__global__ void __launch_bounds__(WIDE ? 2 * NTHREADS : NTHREADS)
+    k_lagrange(const Prob<R> *probs, const BlockMap *map, int nmap, int gpar) {
+  constexpr int BT = WIDE ? 2 * NTHREADS : NTHREADS;
   if constexpr (LOOP) {
     for (int b = blockIdx.x; b < nmap; b += gridDim.x) {
-      lagrange_tile<R, NM>(probs, map_entry(map, b), gpar);
+      lagrange_tile<R, NM, BT>(probs, map_entry(map, b), gpar);
       __syncthreads();  // the next tile reuses the LDS
     }
   } else {
-    if (blockIdx.x < nmap) lagrange_tile<R, NM>(probs, map_entry(map, xcd_tile(blockIdx.x, nmap)), gpar);
+    if (blockIdx.x < nmap) lagrange_tile<R, NM, BT>(probs, map_entry(map, xcd_tile(blockIdx.x, nmap)), gpar);
   }
 }
 
@@ -1606,8 +1608,9 @@ __global__ void __launch_bounds__(WIDE ? 2 * NTHREADS : NTHREADS)
     if (blockIdx.x < nmap) dual_tile<R, NM, BT>(probs, map_entry(map, xcd_tile(blockIdx.x, nmap)), gpar);
   }
 }
-// launches of at most this many node tiles take the wide FP64 dual kernel
-constexpr int kWideDualMaxTiles = 1024;
+// launches of at most this many tiles take the wide FP64 Lagrange and dual
+// kernels
+constexpr int kWideMaxTiles = 1024;
 
 // =========================================================== set-up kernels
 template <typename R>
@@ -1838,7 +1841,7 @@ struct Resident {  // blocks of each step kernel resident on the whole device
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return;
-    const void *fn[kKernels] = {reinterpret_cast<const void *>(&k_lagrange<R, NM, true>),
+    const void *fn[kKernels] = {reinterpret_cast<const void *>(&k_lagrange<R, NM, true, false>),
                                 reinterpret_cast<const void *>(&k_mixed<R, NM>),
                                 reinterpret_cast<const void *>(&k_remap<R, NM, true>),
                                 reinterpret_cast<const void *>(&k_dual<R, NM, true, false>)};
@@ -1904,8 +1907,16 @@ void step_impl(const Launch &L, int gpar, hipStream_t s, hipEvent_t *ev) {
   const int nb = L.node_blocks, cb = L.cell_blocks;
   // the Lagrange kernel runs over the cell tiles: node tiles of a boundary
   // node column or row alone would be one thirty-second or one eighth full
-  if (loop) launch(k_lagrange<R, NM, true>, dim3(grid(0, cb)), s, evk(0), p, cm, cb, gpar);
-  else launch(k_lagrange<R, NM, false>, dim3(cb), s, evk(0), p, cm, cb, gpar);
+  if (loop) {
+    launch(k_lagrange<R, NM, true, false>, dim3(grid(0, cb)), s, evk(0), p, cm, cb, gpar);
+  } else {
+    bool wide = false;
+    if constexpr (sizeof(R) == 8) {
+      wide = cb <= kWideMaxTiles;
+      if (wide) launch_b(k_lagrange<R, NM, false, true>, dim3(cb), 2 * NTHREADS, s, evk(0), p, cm, cb, gpar);
+    }
+    if (!wide) launch(k_lagrange<R, NM, false, false>, dim3(cb), s, evk(0), p, cm, cb, gpar);
+  }
   launch(k_mixed<R, NM>, dim3(L.mix_chunks, L.nprob), s, evk(1), p, L.plist, gpar);
   if (loop) launch(k_remap<R, NM, true>, dim3(grid(2, cb)), s, evk(2), p, cm, cb, gpar);
   else launch(k_remap<R, NM, false>, dim3(cb), s, evk(2), p, cm, cb, gpar);
@@ -1914,7 +1925,7 @@ void step_impl(const Launch &L, int gpar, hipStream_t s, hipEvent_t *ev) {
   } else {
     bool wide = false;
     if constexpr (sizeof(R) == 8) {
-      wide = nb <= kWideDualMaxTiles;
+      wide = nb <= kWideMaxTiles;
       if (wide) launch_b(k_dual<R, NM, false, true>, dim3(nb), 2 * NTHREADS, s, evk(3), p, nm, nb, gpar);
     }
     if (!wide) launch(k_dual<R, NM, false, false>, dim3(nb), s, evk(3), p, nm, nb, gpar);
