@@ -3,19 +3,21 @@
 // (double, or float with FP64 islands) and the number of materials NM.
 //
 // A step is four launches, each over a whole batch of problems (a block map
-// gives every 256-thread block its problem and tile; the mixed-cell kernel
-// has a grid of list chunks x problems):
-//   k_lagrange  node tiles: predictor per cell staged in LDS (EOS, Wilkins Q,
+// gives every block its problem and 32x8 tile; the mixed-cell kernel has a
+// grid of list chunks x problems; small FP64 launches run the Lagrange and
+// dual tiles with 512 threads, the others with 256):
+//   k_lagrange  cell tiles: predictor per cell staged in LDS (EOS, Wilkins Q,
 //               Vol^{n+1/2}, P_a^{n+1/2}; §1.2, §4.1), nodal mass and gradient
-//               of P+Q, u^{n+1/2}, u^{lag}; corrector energies e_a^{lag} of the
-//               tile's cells; the tile's mixed cells join a compact list
+//               of P+Q, u^{n+1/2}, u^{lag} of the tile's nodes; corrector
+//               energies e_a^{lag} of its cells; the tile's mixed cells join a
+//               compact list
 //   k_mixed     the problems' compact lists of mixed cells (FP64, eight
 //               lanes per cell, spread over the device): Youngs normal,
 //               interface on the rectangular approximation of the Lagrangian
 //               cell, partial volumes of the outflow regions, donor-side
 //               clipping (§4.4)
 //   k_remap     cell tiles: node displacements, face volumes and cell records
-//               (Vol^{lagCF}, rho^{lagCF}, centres, widths) staged in LDS with
+//               (Vol^{lagCF}, rho^{lagCF}, centres) staged in LDS with
 //               a two-cell halo; each flux region's order-2 values formed once
 //               (reconstruction §2.1.1, §3.3, §4.2), the positivity guard per
 //               donor; each cell then gathers its nine-point update (§2.3,
@@ -649,14 +651,15 @@ __global__ void __launch_bounds__(NTHREADS) k_mixed(const Prob<R> *probs, const 
 //   P1 node displacements d = dt u^{n+1/2} (2-deep halo, mirrored)
 //   P2 signed volume of every x- and y-face region (the sign bit gives the
 //      donor side: clear = the donor is on the -x / -y side)
-//   P3 cell records (2-deep halo): Vol^{lagCF} from the region volumes,
-//      rho^{lagCF}_a, e^{lag}_a, Lagrangian centre and widths, purity
+//   P3 cell records (2-deep halo): rho^{lagCF}_a (Vol^{lagCF} from the
+//      region volumes), e^{lag}_a, Lagrangian centre, purity; a mixed
+//      record's list position is loaded here and stored after P5
 //   P4 order-2 values (rho, e) of each region whose donor is pure, in the
 //      donor's frame (§2.1.1, §3.3; order 1 next to another material, §4.2)
 //   P5 positivity guard per donor: its order-2 outflow mass and energy
 //   P6 nine-point update of the owned cells, the fluxes formed from the
-//      donor's record, the region values and, for mixed donors, the FP64
-//      partial volumes (§4.4)
+//      donor's record, the region values and, for mixed donors, the
+//      partial volumes formed in FP64 (§4.4)
 template <typename R, int NM>
 struct RemapShared {
   static constexpr int NNX = TX + 5, NNY = TY + 5;  // nodes [i0-2, i0+TX+2]
@@ -1298,13 +1301,12 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
   const int a3 = tid % TX, b3 = tid / TX, I3 = I0 + a3, J3 = J0 + b3;
   const bool own3 = tid < TX * TY && I3 <= nx && J3 <= ny;  // (BT may exceed the tile)
   const int p3 = own3 ? J3 * (nx + 1) + I3 : 0;
-  // (every load is issued unconditionally from a clamped index and its value
-  // zeroed where it is not wanted: loads under branches would be serialised)
-  // (the owned node's values are used by its own thread only; its u^{lag} is
-  // read from the staged node data)
+  // (loaded from a clamped index on every lane, so that no branch holds
+  // them; the owned node's values are used by its own thread only, and its
+  // u^{lag} is read from the staged node data)
   R ux3 = ldg(P.ux + p3), uy3 = ldg(P.uy + p3), mp3 = R(0);
   if (!g.kinematic) mp3 = ldg(P.mp + p3);
-  // (the corner sound speeds are masked where they are used)
+  // (the corner sound speeds likewise, masked where they are used)
   R cs3[4];
   int cs_ok = 0;
 #pragma unroll
