@@ -260,22 +260,23 @@ def test_autotuned_schedule_keeps_results():
         same_fields(b.fields(rid, *FIELDS), g.fields(*FIELDS), p["name"])
 
 
-def test_wide_and_narrow_tiles_give_the_same_bits():
+@pytest.mark.parametrize("nmat", [2, 3])
+def test_wide_and_narrow_tiles_give_the_same_bits(nmat):
     """Small FP64 launches run the Lagrange and dual tiles with 512 threads,
     large ones with 256: the same problem alone (a small launch) and beside
     a large one in a batch (more than 1024 tiles) must give the same bits."""
-    small = inputs.random_mixed(51, 100, 70, nmat=2)
-    big = inputs.random_mixed(52, 700, 500, nmat=2)
+    small = inputs.random_mixed(51, 100, 70, nmat=nmat)
+    big = inputs.random_mixed(52, 700, 500, nmat=nmat)
     steps = 12
     g, n, _ = alone(small, LR_FP64, steps=steps)
     ref = g.fields(*FIELDS)
-    probe = Batch(nmat=2, precision=LR_FP64, max_slots=2, pool_bytes=1 << 20)
+    probe = Batch(nmat=nmat, precision=LR_FP64, max_slots=2, pool_bytes=1 << 20)
     pool = probe.footprint(100, 70) + probe.footprint(700, 500) + (16 << 20)
     probe.close()
-    b = Batch(nmat=2, precision=LR_FP64, max_slots=2, pool_bytes=pool, chunk_steps=4)
+    b = Batch(nmat=nmat, precision=LR_FP64, max_slots=2, pool_bytes=pool, chunk_steps=4)
     rs = b.submit(small, 1e30, max_steps=steps)
     b.submit(big, 1e30, max_steps=steps)
-    say("100x70 beside 700x500 (FP64): 256-thread tiles, against the problem alone")
+    say(f"100x70 beside 700x500 (FP64, {nmat} materials): 256-thread tiles, against the problem alone")
     drain(b)
     rc, st, _ = b.status(rs)
     assert rc == LR_OK and st == steps
