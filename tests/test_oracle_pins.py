@@ -3,6 +3,7 @@
 Each test names the passage it pins.  None of them calls the GPU library.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -120,12 +121,10 @@ def test_ctu_bilinear_first_order(sx, sy):
 
 
 # ------------------------------------------------------------------ P2 -------
-@pytest.mark.parametrize("eps", [0.05, 0.1, 0.2])
-def test_single_node_displacement(eps):
-    """§3.2: one node moved by (eps dx, eps dx).  Exact Lagrangian volume
-    1+eps; DirectCF volume 1 + eps/(1+eps) + eps^2 (the paper's expansion
-    1 + eps + eps^3 + o(eps^3)); corner mass flux / m = eps^2 / that volume
-    (the paper's eps^2 - eps^3 + ...); face flux (dx^2/2) eps/(1+eps)."""
+def _single_node(eps):
+    """§3.2 single-node example on a 5x5 grid of unit cells (dt = 1): the
+    top-right node of the centre cell moves by (eps, eps); first order,
+    prescribed velocities.  Returns the solver after one step."""
     n = 5
     k = np.zeros((2, n, n))
     k[1] = 1.0
@@ -139,6 +138,16 @@ def test_single_node_displacement(eps):
              ux=ux, uy=uy)
     s = _solver(p, recon_order=1, kinematic=True, fixed_dt=1.0)
     s.step()
+    return s
+
+
+@pytest.mark.parametrize("eps", [0.05, 0.1, 0.2])
+def test_single_node_displacement(eps):
+    """§3.2: one node moved by (eps dx, eps dx).  Exact Lagrangian volume
+    1+eps; DirectCF volume 1 + eps/(1+eps) + eps^2 (the paper's expansion
+    1 + eps + eps^3 + o(eps^3)); corner mass flux / m = eps^2 / that volume
+    (the paper's eps^2 - eps^3 + ...); face flux (dx^2/2) eps/(1+eps)."""
+    s = _single_node(eps)
     vcf = 1.0 + eps / (1.0 + eps) + eps ** 2
     assert s.stage("VL")[2, 2] == pytest.approx(1.0 + eps, rel=1e-14)
     assert s.stage("volcf")[2, 2] == pytest.approx(vcf, rel=1e-14)
@@ -149,6 +158,54 @@ def test_single_node_displacement(eps):
     assert m[2, 2] == pytest.approx(1.0 / vcf, rel=1e-13)
     series = eps ** 2 - eps ** 3
     assert abs(m[3, 3] - series) < 4 * eps ** 4
+
+
+def _golden_series(name):
+    """Rows (quantity, scheme) -> third-order coefficients from a fixture of
+    tests/golden (columns: quantity scheme c0 c1 c2 c3)."""
+    rows = {}
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    with open(path) as f:
+        for line in f:
+            line = line.split("#", 1)[0].split()
+            if line:
+                rows[(line[0], line[1])] = [float(c) for c in line[2:]]
+    return rows
+
+
+def test_single_node_series_printed_in_the_paper():
+    """§3.2: the oracle's Lagrangian volumes and corner mass fraction of the
+    single-node example against the third-order series the paper prints
+    (fixture tests/golden/single_node_series.txt): the difference is of
+    fourth order (it falls 16-fold when eps halves), and DirectCF's corner
+    mass agrees with the exact one at the leading, second order only."""
+    rows = _golden_series("single_node_series.txt")
+    assert len(rows) == 4
+    epss = [0.04, 0.02, 0.01, 0.005]
+    got = {key: [] for key in rows}
+    for eps in epss:
+        s = _single_node(eps)
+        m = s.fields("mass")["mass"][0]
+        vals = {("lagrangian_volume", "exact"): s.stage("VL")[2, 2],
+                ("lagrangian_volume", "directcf"): s.stage("volcf")[2, 2],
+                # the corner's receiver gets nothing else; the cell's mass is
+                # the grid's total (1), conserved
+                ("corner_mass_fraction", "directcf"): m[3, 3] / m.sum()}
+        for key, c in rows.items():
+            if key in vals:
+                series = sum(ck * eps ** k for k, ck in enumerate(c))
+                got[key].append(vals[key] - series)
+    # the exact Lagrangian volume is the series itself (a polynomial)
+    assert max(abs(d) for d in got[("lagrangian_volume", "exact")]) < 1e-14
+    for key in (("lagrangian_volume", "directcf"), ("corner_mass_fraction", "directcf")):
+        d = got[key]
+        for eps, x in zip(epss, d):
+            assert abs(x) < 4 * eps ** 4, (key, eps, x)
+        for a, b in zip(d, d[1:]):  # fourth order: halving eps divides by ~16
+            assert 12.0 < a / b < 20.0, (key, d)
+    # the exact and DirectCF corner masses share c0..c2 and differ at eps^3
+    ex, cf = rows[("corner_mass_fraction", "exact")], rows[("corner_mass_fraction", "directcf")]
+    assert ex[:3] == cf[:3] and ex[3] != cf[3]
 
 
 # ------------------------------------------------------------------ P3 -------
