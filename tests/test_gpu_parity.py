@@ -86,11 +86,15 @@ def test_stage_parity_one_step(nmat, seed):
 
 # ------------------------------------------------------------ whole runs -----
 @pytest.mark.parametrize("nx,ny,nmat,seed,steps", [
-    (131, 67, 2, 7, 25),      # several 64x4 tiles and ragged tails
+    (131, 67, 2, 7, 25),      # several 32x8 tiles and ragged tails
     (200, 120, 3, 8, 15),
     (2, 2, 1, 9, 10),         # smallest grid
-    (5, 3, 4, 10, 10),        # four materials on a tiny grid
-    (64, 4, 2, 11, 30),       # exactly one tile wide
+    (5, 3, 4, 10, 10),        # four materials (the most) on a tiny grid
+    (64, 4, 2, 11, 30),       # two tiles wide, half a tile high
+    (32, 8, 2, 12, 20),       # exactly one tile
+    (33, 9, 3, 13, 20),       # one tile and a ragged column and row
+    (2, 50, 2, 14, 15),       # two cells wide: every node on or next to a wall
+    (97, 2, 3, 15, 15),       # two cells high
 ])
 def test_random_mixed_runs(nx, ny, nmat, seed, steps):
     p = inputs.random_mixed(seed, nx, ny, nmat=nmat)
@@ -251,7 +255,8 @@ def compare_fp32(g, r, tag, tol=FP32_L1):
 
 
 @pytest.mark.parametrize("nx,ny,nmat,seed,steps", [(131, 67, 2, 7, 25), (200, 120, 3, 8, 15),
-                                                    (5, 3, 4, 10, 10)])
+                                                    (5, 3, 4, 10, 10), (33, 9, 3, 13, 20),
+                                                    (2, 50, 2, 14, 15)])
 def test_fp32_random_mixed(nx, ny, nmat, seed, steps):
     """FP32 bulk (FP64 interface, clipping and totals) against the FP64 oracle:
     relative L1 of density and pressure <= 1e-4."""
