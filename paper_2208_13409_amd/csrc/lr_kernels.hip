@@ -1272,11 +1272,16 @@ struct DualShared {
   // [J0-1, J0+TY]; (main, anti) corner fluxes at nodes [I0-1, I0+TX] x [J0-1, J0+TY]
   static constexpr int PXW = TX + 2, PXH = TY + 1, PYW = TX + 1, PYH = TY + 2;
   static constexpr int PCW = TX + 2, PCH = TY + 2;
-  R ulx[NY_][NX_], uly[NY_][NX_], dx[NY_][NX_], dy[NY_][NX_];
+  R ulx[NY_][NX_], uly[NY_][NX_];
+  // node displacements (x, y) while the regions are formed; after that their
+  // storage holds the anti-diagonal corners' momentum fluxes (FA)
+  R dxy[2][NY_][NX_];
   R mx[PXH][PXW], my[PYH][PYW], cd[PCH][PCW], ca[PCH][PCW];
   // momentum fluxes (x, y components) of the dual regions; their mass fluxes
   // are re-formed from the staged primal fluxes where the nodes sum them
-  R fx[2][NXF], fy[2][NYF], fd[2][NCN], fa[2][NCN];
+  R fx[2][NXF], fy[2][NYF], fd[2][NCN];
+  static constexpr int FA = NCN;  // component c of corner k at (&dxy[0][0][0])[c * FA + k]
+  static_assert(2 * NCN <= 2 * NX_ * NY_, "the anti-diagonal fluxes fit the displacements' storage");
 };
 
 template <typename R, int NM, int BT>
@@ -1393,8 +1398,8 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
       }
       sh.ulx[b][a] = ulx;
       sh.uly[b][a] = uly;
-      sh.dx[b][a] = dx;
-      sh.dy[b][a] = dy;
+      sh.dxy[0][b][a] = dx;
+      sh.dxy[1][b][a] = dy;
     }
 #pragma unroll
     for (int it = 0; it < ITX; ++it) {
@@ -1446,8 +1451,8 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
     // (sa, sb) projected on (vx, vy), offset `off`
     // Lagrangian position of a staged node: its index times the cell size
     // plus its (mirrored) displacement, for ghost nodes too
-    auto Xp = [&](int la, int lb) { return R(I0 - 2 + la) * Dx + sh.dx[lb][la]; };
-    auto Yp = [&](int la, int lb) { return R(J0 - 2 + lb) * Dy + sh.dy[lb][la]; };
+    auto Xp = [&](int la, int lb) { return R(I0 - 2 + la) * Dx + sh.dxy[0][lb][la]; };
+    auto Yp = [&](int la, int lb) { return R(J0 - 2 + lb) * Dy + sh.dxy[1][lb][la]; };
     auto recon = [&](int la, int lb, int sa, int sb, R vx, R vy, R off, R &u, R &v) {
       u = sh.ulx[lb][la];
       v = sh.uly[lb][la];
@@ -1460,13 +1465,22 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
       u += su * off;
       v += sv * off;
     };
-    auto wxd = [&](int la, int lb) { return Dx + R(0.5) * (sh.dx[lb][la + 1] - sh.dx[lb][la - 1]); };
-    auto wyd = [&](int la, int lb) { return Dy + R(0.5) * (sh.dy[lb + 1][la] - sh.dy[lb - 1][la]); };
+    auto wxd = [&](int la, int lb) { return Dx + R(0.5) * (sh.dxy[0][lb][la + 1] - sh.dxy[0][lb][la - 1]); };
+    auto wyd = [&](int la, int lb) { return Dy + R(0.5) * (sh.dxy[1][lb + 1][la] - sh.dxy[1][lb - 1][la]); };
     const R nrmv = sqrt(Dx * Dx + Dy * Dy);
 
     // ---- stage 2: every dual region of the tile once: x-faces, y-faces,
-    // then the corners, in one pass
-    for (int l = tid; l < SH::NXF + SH::NYF + SH::NCN; l += BT) {
+    // then the corners, in one pass.  The anti-diagonal corner fluxes wait in
+    // registers until every displacement has been read (a thread meets
+    // corners only in its trips from IT2C on), then take the displacements'
+    // storage.
+    constexpr int NREG = SH::NXF + SH::NYF + SH::NCN, IT2 = (NREG + BT - 1) / BT,
+                  IT2C = (SH::NXF + SH::NYF) / BT;
+    R ha[IT2 - IT2C][2];
+#pragma unroll
+    for (int it = 0; it < IT2; ++it) {
+      const int l = tid + it * BT;
+      if (l >= NREG) continue;
       if (l < SH::NXF) {  // dual x-face (I,J): nodes (I-1,J)-(I,J)
         const int a = l % (TX + 1), b = l / (TX + 1);
         const int I = I0 + a, J = J0 + b;
@@ -1474,7 +1488,7 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
         const R phi = R(0.25) * (sh.mx[b][a] + sh.mx[b][a + 1] + sh.mx[b + 1][a] + sh.mx[b + 1][a + 1]);
         const int D = phi > R(0) ? I - 1 : I;
         const R sg = phi > R(0) ? R(1) : R(-1);
-        const R df = R(0.5) * (sh.dx[M_(J)][L(I - 1)] + sh.dx[M_(J)][L(I)]);
+        const R df = R(0.5) * (sh.dxy[0][M_(J)][L(I - 1)] + sh.dxy[0][M_(J)][L(I)]);
         const R off = R(0.5) * (sg * wxd(L(D), M_(J)) - df);
         R u, v;
         recon(L(D), M_(J), 1, 0, R(1), R(0), off, u, v);
@@ -1488,7 +1502,7 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
         const R phi = R(0.25) * (sh.my[b][a] + sh.my[b][a + 1] + sh.my[b + 1][a] + sh.my[b + 1][a + 1]);
         const int D = phi > R(0) ? J - 1 : J;
         const R sg = phi > R(0) ? R(1) : R(-1);
-        const R df = R(0.5) * (sh.dy[M_(J - 1)][L(I)] + sh.dy[M_(J)][L(I)]);
+        const R df = R(0.5) * (sh.dxy[1][M_(J - 1)][L(I)] + sh.dxy[1][M_(J)][L(I)]);
         const R off = R(0.5) * (sg * wyd(L(I), M_(D)) - df);
         R u, v;
         recon(L(I), M_(D), 0, 1, R(0), R(1), off, u, v);
@@ -1503,10 +1517,10 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
         const R d00 = sh.cd[b][a], a00 = sh.ca[b][a], d10 = sh.cd[b][a + 1], a10 = sh.ca[b][a + 1];
         const R d01 = sh.cd[b + 1][a], a01 = sh.ca[b + 1][a], d11 = sh.cd[b + 1][a + 1],
                 a11 = sh.ca[b + 1][a + 1];
-        const R dcx = R(0.25) * (sh.dx[M_(j)][L(i)] + sh.dx[M_(j)][L(i + 1)] + sh.dx[M_(j + 1)][L(i)] +
-                                 sh.dx[M_(j + 1)][L(i + 1)]);
-        const R dcy = R(0.25) * (sh.dy[M_(j)][L(i)] + sh.dy[M_(j)][L(i + 1)] + sh.dy[M_(j + 1)][L(i)] +
-                                 sh.dy[M_(j + 1)][L(i + 1)]);
+        const R dcx = R(0.25) * (sh.dxy[0][M_(j)][L(i)] + sh.dxy[0][M_(j)][L(i + 1)] +
+                                 sh.dxy[0][M_(j + 1)][L(i)] + sh.dxy[0][M_(j + 1)][L(i + 1)]);
+        const R dcy = R(0.25) * (sh.dxy[1][M_(j)][L(i)] + sh.dxy[1][M_(j)][L(i + 1)] +
+                                 sh.dxy[1][M_(j + 1)][L(i)] + sh.dxy[1][M_(j + 1)][L(i + 1)]);
         {  // main diagonal: (i,j) -> (i+1,j+1)
           const R phi = R(0.25) * (d00 + d10 + d01 + d11);
           const R sg = phi > R(0) ? R(1) : R(-1);
@@ -1526,10 +1540,23 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
           R u, v, off = R(0);
           if (o2) off = R(0.5) * ((sg * wxd(L(DI), M_(DJ)) - dcx) * vx + (-sg * wyd(L(DI), M_(DJ)) - dcy) * vy);
           recon(L(DI), M_(DJ), 1, -1, vx, vy, off, u, v);
-          sh.fa[0][k] = phi * u;
-          sh.fa[1][k] = phi * v;
+          if (it >= IT2C) {  // (always so for a corner)
+            ha[it >= IT2C ? it - IT2C : 0][0] = phi * u;
+            ha[it >= IT2C ? it - IT2C : 0][1] = phi * v;
+          }
         }
       }
+    }
+    __syncthreads();  // the displacements are read: their storage takes the anti-diagonal fluxes
+    R *const fa = &sh.dxy[0][0][0];
+#pragma unroll
+    for (int it = IT2C; it < IT2; ++it) {
+      const int k = tid + it * BT - SH::NXF - SH::NYF;
+      if (k < 0 || k >= SH::NCN) continue;
+      const int i = I0 - 1 + k % (TX + 1), j = J0 - 1 + k / (TX + 1);
+      if (i > nx || j > ny) continue;
+      fa[k] = ha[it - IT2C][0];
+      fa[SH::FA + k] = ha[it - IT2C][1];
     }
     __syncthreads();
   }
@@ -1568,8 +1595,9 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
         m -= py(a, b + 1); mu -= sh.fy[0][hN]; mv -= sh.fy[1][hN];
         m += pd(a, b); mu += sh.fd[0][hSW]; mv += sh.fd[1][hSW];
         m -= pd(a + 1, b + 1); mu -= sh.fd[0][hNE]; mv -= sh.fd[1][hNE];
-        m += pa(a, b + 1); mu += sh.fa[0][hNW]; mv += sh.fa[1][hNW];
-        m -= pa(a + 1, b); mu -= sh.fa[0][hSE]; mv -= sh.fa[1][hSE];
+        const R *fa = &sh.dxy[0][0][0];  // anti-diagonal fluxes (x at k, y at FA + k)
+        m += pa(a, b + 1); mu += fa[hNW]; mv += fa[SH::FA + hNW];
+        m -= pa(a + 1, b); mu -= fa[hSE]; mv -= fa[SH::FA + hSE];
         if (!(m > R(0))) atomicOr(&ctl->err, ERR_NODEMASS);
         ux = qdiv(mu, m);
         uy = qdiv(mv, m);
