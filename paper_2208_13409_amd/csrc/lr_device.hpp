@@ -23,18 +23,33 @@ struct Grid {
   double cfl, a1, a2, k_eps, fixed_dt;
   double neg_tol;  // a partial V, M, E below -neg_tol of the cell scale is an error
   double gamma[MAXMAT];
+  int ndt;  // CFL partial minima the problem uses (a power of two, 32..NDT)
 };
 
 // Device-side time control.  Step n of a problem reads slot[n & 1 ^ flip];
 // the remap kernel of step n prepares the other slot for step n+1 and the
 // dual kernel of step n accumulates the CFL bound of the new state into it,
 // so no control kernel and no host round trip is needed between steps.
-constexpr int NDT = 32;  // CFL-bound partial minima, spread to keep atomics uncontended
+// A launch folds each block's CFL bound into one of the problem's g.ndt
+// partial minima (block b into b % g.ndt): device-wide atomics on one address
+// are served one after another, so a large grid needs many partials (about
+// 16 blocks each), while a small one reads fewer in every kernel's prologue.
+constexpr int NDT = 256;
+static_assert(NDT % 64 == 0, "each lane of a wave reads NDT / 64 partials");
+// partials for a grid of nx x ny cells: 32, doubled while there are more
+// than 16 node tiles per partial, at most NDT
+inline int cfl_partials(int nx, int ny) {
+  const long long tiles = (long long)((nx + TX) / TX) * ((ny + TY) / TY);
+  int n = 32;
+  while (n < NDT && 16ll * n < tiles) n *= 2;
+  return n;
+}
 struct Slot {
   double t;                       // time at the start of the step
   double t_end;                   // end of the current run
   unsigned long long dtmin[NDT];  // bits of the CFL bound of the state at t (positive
-                                  // doubles): its min over the NDT entries
+                                  // doubles): its min over the entries; those at or
+                                  // beyond the problem's count stay +inf
   long long step;                 // index of the step
   long long limit;                // the run stops when step reaches it
   int done;                       // no step to take: the kernels return at once
@@ -309,8 +324,8 @@ __device__ __forceinline__ double interface_offset(double x0, double x1, double 
 // time step of the step a slot describes (the CFL bound or the fixed step,
 // shortened to land on t_end)
 // the block's minimum of a per-thread bound (bits of a positive double) goes
-// to one of the NDT partial minima of the slot: one atomic per block
-__device__ __forceinline__ void block_min_to_slot(unsigned long long cand, Slot &s) {
+// to one of the nd partial minima of the slot: one atomic per block
+__device__ __forceinline__ void block_min_to_slot(unsigned long long cand, Slot &s, int nd) {
   __shared__ unsigned long long wmin[16];
   for (int o = 32; o > 0; o >>= 1) {
     const unsigned long long w = __shfl_xor(cand, o, 64);
@@ -322,17 +337,29 @@ __device__ __forceinline__ void block_min_to_slot(unsigned long long cand, Slot 
   if (threadIdx.x == 0) {
     unsigned long long m = wmin[0];
     for (int k = 1; k < nw; ++k) m = wmin[k] < m ? wmin[k] : m;
-    if (m != ~0ull) atomicMin(&s.dtmin[blockIdx.x % NDT], m);
+    if (m != ~0ull) atomicMin(&s.dtmin[blockIdx.x & (nd - 1)], m);
   }
 }
 
-// (called by all 64 lanes of every wave: lane k reads partial k % NDT and
-// the wave combines them with shuffles)
+// (called by all 64 lanes of every wave: lane l reads partial l & 31 at once,
+// waiting for no other load; with more than 32 partials also l, l + 64, ...
+// below the count, and one more exchange step joins the two halves of the
+// wave before the five that give every lane the minimum)
 template <typename GridT>
 __device__ __forceinline__ double slot_dt(const GridT &g, const Slot &s, bool &last) {
-  unsigned long long b = ldg(&s.dtmin[__lane_id() % NDT]);
+  unsigned long long b = ldg(&s.dtmin[__lane_id() & 31]);
+  if (g.ndt > 32) {  // (a multiple of 64)
 #pragma unroll
-  for (int o = NDT / 2; o > 0; o >>= 1) {
+    for (int k = 0; k < NDT / 64; ++k) {
+      if (64 * k >= g.ndt) break;
+      const unsigned long long v = ldg(&s.dtmin[64 * k + __lane_id()]);
+      b = v < b ? v : b;
+    }
+    const unsigned long long w = __shfl_xor(b, 32, 64);
+    b = w < b ? w : b;
+  }
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) {
     const unsigned long long w = __shfl_xor(b, o, 64);
     b = w < b ? w : b;
   }

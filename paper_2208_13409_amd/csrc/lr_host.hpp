@@ -106,6 +106,7 @@ int make_grid(int nx, int ny, int nmat, const lr_eos *eos, const int bc[4], cons
   g.neg_tol = o.precision == LR_FP32 ? 1e-5 : 1e-10;
   if (o.precision == LR_FP32 && g.k_eps < 1e-6) g.k_eps = 1e-6;
   for (int a = 0; a < nmat; ++a) g.gamma[a] = eos[a].gamma;
+  g.ndt = cfl_partials(nx, ny);
   return LR_OK;
 }
 
@@ -167,7 +168,7 @@ int cur_slot(const Ctl &k) { return k.slot[1].step > k.slot[0].step ? 1 : 0; }
 // the time step a slot describes, with the device's arithmetic
 double host_slot_dt(const Grid &g, const Slot &s) {
   unsigned long long b = s.dtmin[0];
-  for (int k = 1; k < NDT; ++k) b = s.dtmin[k] < b ? s.dtmin[k] : b;
+  for (int k = 1; k < g.ndt; ++k) b = s.dtmin[k] < b ? s.dtmin[k] : b;
   double dtmin;
   std::memcpy(&dtmin, &b, sizeof dtmin);
   double dt = g.fixed_dt > 0.0 ? g.fixed_dt : g.cfl * dtmin;

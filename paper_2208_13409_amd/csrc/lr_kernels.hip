@@ -775,19 +775,24 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
     return;
   }
 
-  // the first tile of the problem prepares the next step's slot
-  if (i0 == 0 && j0 == 0 && tid == 0) {
+  // the first tile of the problem prepares the next step's slot (its first
+  // wave clears the CFL partials)
+  if (i0 == 0 && j0 == 0 && tid < 64) {
     Slot &N = ctl->slot[par ^ 1];
-    const long long step = ldg(&S.step) + 1, limit = ldg(&S.limit);
-    const double t = ldg(&S.t), t_end = ldg(&S.t_end);
-    stg(&N.t, last ? t_end : t + dtd);
-    stg(&N.t_end, t_end);
-    stg(&N.step, step);
-    stg(&N.limit, limit);
-    for (int k = 0; k < NDT; ++k) stg(&N.dtmin[k], (unsigned long long)__double_as_longlong(INFINITY));
-    stg(&N.nmix, 0);
-    stg(&N.done, (last || step >= limit) ? 1 : 0);
-    if (!(dtd > 0.0) || !isfinite(dtd)) atomicOr(&ctl->err, ERR_DT);
+#pragma unroll
+    for (int k = 0; k < NDT / 64; ++k)
+      if (tid + 64 * k < g.ndt) stg(&N.dtmin[tid + 64 * k], (unsigned long long)__double_as_longlong(INFINITY));
+    if (tid == 0) {
+      const long long step = ldg(&S.step) + 1, limit = ldg(&S.limit);
+      const double t = ldg(&S.t), t_end = ldg(&S.t_end);
+      stg(&N.t, last ? t_end : t + dtd);
+      stg(&N.t_end, t_end);
+      stg(&N.step, step);
+      stg(&N.limit, limit);
+      stg(&N.nmix, 0);
+      stg(&N.done, (last || step >= limit) ? 1 : 0);
+      if (!(dtd > 0.0) || !isfinite(dtd)) atomicOr(&ctl->err, ERR_DT);
+    }
   }
 
   // local indices: nodes and x-faces from (i0-2, j0-2), records likewise
@@ -1615,7 +1620,7 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
       cand = (unsigned long long)__double_as_longlong(bound);
     }
   }
-  block_min_to_slot(cand, ctl->slot[par ^ 1]);
+  block_min_to_slot(cand, ctl->slot[par ^ 1], g.ndt);
 }
 
 // one block per tile of the map (LOOP false: grid = map), or a grid smaller
@@ -1706,7 +1711,7 @@ __global__ void k_dt_bound(Prob<R> P, int slot) {
                               double(R(g.dy) / (cmax + fabs(P.uy[p]))));
     cand = (unsigned long long)__double_as_longlong(bound);
   }
-  block_min_to_slot(cand, P.ctl->slot[slot]);
+  block_min_to_slot(cand, P.ctl->slot[slot], g.ndt);
 }
 
 // a device input of element type T copied into the FP64 staging array
