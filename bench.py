@@ -21,7 +21,9 @@ memory.  The same JSON line carries
       per launch over its average duration, measured with start/stop HIP
       events recorded by each launch's dispatch on the kernel's stream;
       "traffic" is the HBM bytes per launch that rocprofv3 counted for the
-      same kernel sources (profiles/), else null;
+      same kernel sources (profiles/), else null; "valu" the kernel's VALU
+      issue (its counted VALU instructions per launch over the same measured
+      duration, against the published FP32/FP64 vector rates), else null;
   "cpu_baseline": the FP64 oracle timed on a bounded sample of the plain
       workload on the host (one thread).
 """
@@ -64,6 +66,34 @@ def counted_traffic(kernel, workload, precision):
     if rec.get("kernel_sources_sha256") != kernel_sources_sha256():
         return None
     return rec.get("traffic_bytes_per_launch")
+
+
+def counted_valu(kernel, workload, precision):
+    """Wave64 VALU instructions per launch of `kernel` from the rocprofv3
+    SQ_INSTS_VALU pass recorded beside the traffic, or None (no record, or
+    the kernel sources changed since)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    return rec.get("valu_instr_per_launch")
+
+
+def valu_roofline(instr, seconds, fp32):
+    """VALU issue of a launch against the published vector rates: one wave64
+    instruction per SIMD every 2 cycles in FP32 (157.3 TFLOP/s = 256 CUs x
+    128 lanes x 2 x 2.4 GHz), every 4 in FP64 (78.6 TFLOP/s); 1024 SIMDs."""
+    if instr is None:
+        return None
+    peak = 1024 * 64 * 2.4e9 / (2 if fp32 else 4) / 1e12
+    achieved = instr * 64 / seconds / 1e12
+    return {"achieved": achieved, "peak": peak, "unit": "T lane-instr/s", "frac": achieved / peak,
+            "instr_per_launch": instr}
 
 
 def kernel_bytes(nx, ny, nmat, w=W64):
@@ -272,7 +302,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": counted_traffic(dom, p["name"], args.precision),
-                     "algorithmic_bytes_per_launch": kb[dom], "avg_launch_us": avg_us[dom]},
+                     "algorithmic_bytes_per_launch": kb[dom], "avg_launch_us": avg_us[dom],
+                     "valu": valu_roofline(counted_valu(dom, p["name"], args.precision), dom_s, fp32)},
         "roofline_step": {"bytes_per_cell_update": step_bytes(1, 1, nmat, w),
                           "achieved_GBs": step_bytes(nx, ny, nmat, w) / (wall / n) / 1e9,
                           "frac": step_bytes(nx, ny, nmat, w) / (wall / n) / 1e9 / HBM_PEAK_GBS,
