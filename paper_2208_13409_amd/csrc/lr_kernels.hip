@@ -703,7 +703,7 @@ __device__ __forceinline__ RegionRef region_donor(int kind, int I, int J, bool n
   return neg ? RegionRef{I, J - 1, 6} : RegionRef{I - 1, J, 5};
 }
 
-template <typename R, int NM>
+template <typename R, int NM, bool REST>
 __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap bm, int gpar) {
   using SH = RemapShared<R, NM>;
   __shared__ SH sh;
@@ -968,6 +968,11 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       }
       bool mainc;
       const R sv = region_vol(kind, I, J, mainc);
+      if (REST && sv == R(0)) {  // no flow: zero fluxes, and no slopes to form
+        sh.vm[l] = R(0);
+        sh.vq[l] = R(0);
+        continue;
+      }
       const RegionRef rf = region_donor(kind, I, J, signbit(sv), mainc);
       if (!donor_in(rf.di, rf.dj)) continue;
       const int ca = rf.di - (i0 - 2), cb = rf.dj - (j0 - 2);
@@ -1140,9 +1145,10 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
         }
       }
       R F[8][3 * NM];
-      // FP32: materials that some added region carries (bit m); the sums of
-      // the others only add zeros and are skipped (a wave inside one material
-      // skips them all).  Not worth its instructions in the FP64 sums.
+      // FP32: materials that some added region of nonzero volume carries
+      // (bit m); the sums of the others only add zeros and are skipped (a
+      // wave inside one material, or at rest, skips them all).  Not worth
+      // its instructions in the FP64 sums.
       unsigned used = sizeof(R) == 4 ? 0u : ~0u;
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
@@ -1150,7 +1156,8 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
         for (int k = 0; k < 3 * NM; ++k) F[s][k] = R(0);
         const int pq = pqs[s], d = dd[s];  // donor record, flattened
         const R dir = dirs[s], w = wr[s];
-        if (sizeof(R) == 4 && sgn[s] != R(0)) used |= pq >= 0 ? 1u << (pq & 15) : (pq == -1 ? ~0u : 0u);
+        if (sizeof(R) == 4 && sgn[s] != R(0) && w > R(0))
+          used |= pq >= 0 ? 1u << (pq & 15) : (pq == -1 ? ~0u : 0u);
         if (pq >= 0) {
           const int pm = pq & 15;
           const R rho = (&sh.rcf[pm][0][0])[d], e = (&sh.el[pm][0][0])[d];
@@ -1254,16 +1261,19 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
 // one block per tile of the map (LOOP false: grid = map), or a grid smaller
 // than the map whose blocks walk it (LOOP true; a separate instantiation,
 // since the loop keeps values live across tiles and costs registers)
-template <typename R, int NM, bool LOOP>
+// REST: regions of zero volume (material at rest) skip the order-2 values.
+// Launches of many tiles gain by it; a small FP64 launch, timed by its
+// slowest tile, runs without the test.
+template <typename R, int NM, bool LOOP, bool REST>
 __global__ void __launch_bounds__(NTHREADS) k_remap(const Prob<R> *probs, const BlockMap *map,
                                                   int nmap, int gpar) {
   if constexpr (LOOP) {
     for (int b = blockIdx.x; b < nmap; b += gridDim.x) {
-      remap_tile<R, NM>(probs, map_entry(map, b), gpar);
+      remap_tile<R, NM, REST>(probs, map_entry(map, b), gpar);
       __syncthreads();  // the next tile reuses the LDS
     }
   } else {
-    if (blockIdx.x < nmap) remap_tile<R, NM>(probs, map_entry(map, xcd_tile(blockIdx.x, nmap)), gpar);
+    if (blockIdx.x < nmap) remap_tile<R, NM, REST>(probs, map_entry(map, xcd_tile(blockIdx.x, nmap)), gpar);
   }
 }
 
@@ -1878,7 +1888,7 @@ struct Resident {  // blocks of each step kernel resident on the whole device
       return;
     const void *fn[kKernels] = {reinterpret_cast<const void *>(&k_lagrange<R, NM, true, false>),
                                 reinterpret_cast<const void *>(&k_mixed<R, NM>),
-                                reinterpret_cast<const void *>(&k_remap<R, NM, true>),
+                                reinterpret_cast<const void *>(&k_remap<R, NM, true, true>),
                                 reinterpret_cast<const void *>(&k_dual<R, NM, true, false>)};
     for (int k = 0; k < kKernels; ++k) {
       int per = 0;
@@ -1953,8 +1963,16 @@ void step_impl(const Launch &L, int gpar, hipStream_t s, hipEvent_t *ev) {
     if (!wide) launch(k_lagrange<R, NM, false, false>, dim3(cb), s, evk(0), p, cm, cb, gpar);
   }
   launch(k_mixed<R, NM>, dim3(L.mix_chunks, L.nprob), s, evk(1), p, L.plist, gpar);
-  if (loop) launch(k_remap<R, NM, true>, dim3(grid(2, cb)), s, evk(2), p, cm, cb, gpar);
-  else launch(k_remap<R, NM, false>, dim3(cb), s, evk(2), p, cm, cb, gpar);
+  if (loop) {
+    launch(k_remap<R, NM, true, true>, dim3(grid(2, cb)), s, evk(2), p, cm, cb, gpar);
+  } else {
+    bool small = false;
+    if constexpr (sizeof(R) == 8) {
+      small = cb <= kWideMaxTiles;
+      if (small) launch(k_remap<R, NM, false, false>, dim3(cb), s, evk(2), p, cm, cb, gpar);
+    }
+    if (!small) launch(k_remap<R, NM, false, true>, dim3(cb), s, evk(2), p, cm, cb, gpar);
+  }
   if (loop) {
     launch(k_dual<R, NM, true, false>, dim3(grid(3, nb)), s, evk(3), p, nm, nb, gpar);
   } else {
