@@ -1491,6 +1491,10 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
     // storage.
     constexpr int NREG = SH::NXF + SH::NYF + SH::NCN, IT2 = (NREG + BT - 1) / BT,
                   IT2C = (SH::NXF + SH::NYF) / BT;
+    // regions without mass flux (material at rest) carry no momentum: their
+    // fluxes are written as zero without the reconstruction, except in the
+    // 512-thread tiles of small FP64 launches, timed by their slowest tile
+    constexpr bool REST = BT == NTHREADS;
     R ha[IT2 - IT2C][2];
 #pragma unroll
     for (int it = 0; it < IT2; ++it) {
@@ -1501,6 +1505,11 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
         const int I = I0 + a, J = J0 + b;
         if (I > nx + 1 || J > ny) continue;
         const R phi = R(0.25) * (sh.mx[b][a] + sh.mx[b][a + 1] + sh.mx[b + 1][a] + sh.mx[b + 1][a + 1]);
+        if (REST && phi == R(0)) {
+          sh.fx[0][l] = R(0);
+          sh.fx[1][l] = R(0);
+          continue;
+        }
         const int D = phi > R(0) ? I - 1 : I;
         const R sg = phi > R(0) ? R(1) : R(-1);
         const R df = R(0.5) * (sh.dxy[0][M_(J)][L(I - 1)] + sh.dxy[0][M_(J)][L(I)]);
@@ -1515,6 +1524,11 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
         const int I = I0 + a, J = J0 + b;
         if (I > nx || J > ny + 1) continue;
         const R phi = R(0.25) * (sh.my[b][a] + sh.my[b][a + 1] + sh.my[b + 1][a] + sh.my[b + 1][a + 1]);
+        if (REST && phi == R(0)) {
+          sh.fy[0][k] = R(0);
+          sh.fy[1][k] = R(0);
+          continue;
+        }
         const int D = phi > R(0) ? J - 1 : J;
         const R sg = phi > R(0) ? R(1) : R(-1);
         const R df = R(0.5) * (sh.dxy[1][M_(J - 1)][L(I)] + sh.dxy[1][M_(J)][L(I)]);
@@ -1536,7 +1550,10 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
                                  sh.dxy[0][M_(j + 1)][L(i)] + sh.dxy[0][M_(j + 1)][L(i + 1)]);
         const R dcy = R(0.25) * (sh.dxy[1][M_(j)][L(i)] + sh.dxy[1][M_(j)][L(i + 1)] +
                                  sh.dxy[1][M_(j + 1)][L(i)] + sh.dxy[1][M_(j + 1)][L(i + 1)]);
-        {  // main diagonal: (i,j) -> (i+1,j+1)
+        if (REST && d00 == R(0) && d10 == R(0) && d01 == R(0) && d11 == R(0)) {
+          sh.fd[0][k] = R(0);
+          sh.fd[1][k] = R(0);
+        } else {  // main diagonal: (i,j) -> (i+1,j+1)
           const R phi = R(0.25) * (d00 + d10 + d01 + d11);
           const R sg = phi > R(0) ? R(1) : R(-1);
           const int DI = phi > R(0) ? i : i + 1, DJ = phi > R(0) ? j : j + 1;
@@ -1547,7 +1564,12 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
           sh.fd[0][k] = phi * u;
           sh.fd[1][k] = phi * v;
         }
-        {  // anti-diagonal: (i,j+1) -> (i+1,j)
+        if (REST && a00 == R(0) && a10 == R(0) && a01 == R(0) && a11 == R(0)) {
+          if (it >= IT2C) {
+            ha[it >= IT2C ? it - IT2C : 0][0] = R(0);
+            ha[it >= IT2C ? it - IT2C : 0][1] = R(0);
+          }
+        } else {  // anti-diagonal: (i,j+1) -> (i+1,j)
           const R phi = R(0.25) * (a00 + a10 + a01 + a11);
           const R sg = phi > R(0) ? R(1) : R(-1);
           const int DI = phi > R(0) ? i : i + 1, DJ = phi > R(0) ? j + 1 : j;
