@@ -1100,11 +1100,29 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       const int rk[8] = {0, 0, 1, 1, 2, 2, 2, 2};
       const int rI[8] = {i, i + 1, i, i, i, i + 1, i, i + 1};
       const int rJ[8] = {j, j, j, j + 1, j, j, j + 1, j + 1};
+      // The eight regions of the cell are bounded by its own four nodes' old
+      // and new positions: with those four at rest (REST launches) every
+      // region has zero volume, the cell keeps V^{lagCF}, M and E, and the
+      // regions are not formed (their fluxes and sums below are skipped).
+      bool rest = false;
+      if constexpr (REST) {
+        const int na = NA(i), nb = NB(j);
+        rest = sh.ndx[nb][na] == R(0) && sh.ndy[nb][na] == R(0) && sh.ndx[nb][na + 1] == R(0) &&
+               sh.ndy[nb][na + 1] == R(0) && sh.ndx[nb + 1][na] == R(0) && sh.ndy[nb + 1][na] == R(0) &&
+               sh.ndx[nb + 1][na + 1] == R(0) && sh.ndy[nb + 1][na + 1] == R(0);
+      }
       // first every region's donor, and the loads of the partial volumes of
       // the mixed donors (all issued before any is used), then the fluxes
       R sgn[8], wr[8], dirs[8];
       int dd[8], pqs[8], mss[8];
       R wmx[8][NM];  // unset unless the region's donor is mixed
+      R F[8][3 * NM];
+      // FP32: materials that some added region of nonzero volume carries
+      // (bit m); the sums of the others only add zeros and are skipped (a
+      // wave inside one material, or at rest, skips them all).  Not worth
+      // its instructions in the FP64 sums, except for a cell at rest.
+      unsigned used = (sizeof(R) == 4 || rest) ? 0u : ~0u;
+      if (!rest) {
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
         bool mainc;
@@ -1144,12 +1162,6 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
           }
         }
       }
-      R F[8][3 * NM];
-      // FP32: materials that some added region of nonzero volume carries
-      // (bit m); the sums of the others only add zeros and are skipped (a
-      // wave inside one material, or at rest, skips them all).  Not worth
-      // its instructions in the FP64 sums.
-      unsigned used = sizeof(R) == 4 ? 0u : ~0u;
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
 #pragma unroll
@@ -1187,6 +1199,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
           }
         }
       }
+      }  // !rest
       R Vn[NM], Mn[NM], En[NM], Msa = R(0), Esa = R(0);
       bool bad_nan = false;
 #pragma unroll
@@ -1237,11 +1250,13 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       // total mass flux of the regions this cell owns (left face, bottom face,
       // bottom-left corner) for the momentum remap; walls are zero
       R mx = R(0), my = R(0), mc = R(0);
+      if (!rest) {
 #pragma unroll
-      for (int m = 0; m < NM; ++m) {
-        mx += F[0][NM + m];
-        my += F[2][NM + m];
-        mc += F[4][NM + m];
+        for (int m = 0; m < NM; ++m) {
+          mx += F[0][NM + m];
+          my += F[2][NM + m];
+          mc += F[4][NM + m];
+        }
       }
       stg(P.MX + (j * (nx + 1) + i), i > 0 ? mx : R(0));
       stg(P.MY + (j * nx + i), j > 0 ? my : R(0));
@@ -1249,9 +1264,9 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       if (P.dbg.Wpx) {
         const int nX = (nx + 1) * ny, nY = nx * (ny + 1), nN = (nx + 1) * (ny + 1);
         for (int m = 0; m < NM; ++m) {
-          stg(P.dbg.Wpx + (m * nX + j * (nx + 1) + i), i > 0 ? F[0][m] : R(0));
-          stg(P.dbg.Wpy + (m * nY + j * nx + i), j > 0 ? F[2][m] : R(0));
-          stg(P.dbg.Wpc + (m * nN + j * (nx + 1) + i), (i > 0 && j > 0) ? F[4][m] : R(0));
+          stg(P.dbg.Wpx + (m * nX + j * (nx + 1) + i), (i > 0 && !rest) ? F[0][m] : R(0));
+          stg(P.dbg.Wpy + (m * nY + j * nx + i), (j > 0 && !rest) ? F[2][m] : R(0));
+          stg(P.dbg.Wpc + (m * nN + j * (nx + 1) + i), (i > 0 && j > 0 && !rest) ? F[4][m] : R(0));
         }
       }
     }
