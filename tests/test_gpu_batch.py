@@ -263,11 +263,8 @@ def test_autotuned_schedule_keeps_results():
 @pytest.mark.parametrize("nmat", [2, 3])
 def test_wide_and_narrow_tiles_give_the_same_bits(nmat):
     """Small FP64 launches run the Lagrange and dual tiles with 512 threads,
-    large ones with 256, and only large ones skip the slopes of material at
-    rest (remap regions of zero volume, cells whose nodes are at rest, dual
-    regions without mass flux): the same problem alone (a small launch) and
-    beside a large one in a batch (more than 1024 tiles) must give the same
-    bits."""
+    large ones with 256: the same problem alone (a small launch) and beside
+    a large one in a batch (more than 1024 tiles) must give the same bits."""
     small = inputs.random_mixed(51, 100, 70, nmat=nmat)
     big = inputs.random_mixed(52, 700, 500, nmat=nmat)
     steps = 12
@@ -284,3 +281,30 @@ def test_wide_and_narrow_tiles_give_the_same_bits(nmat):
     rc, st, _ = b.status(rs)
     assert rc == LR_OK and st == steps
     same_fields(b.fields(rs, *FIELDS), ref, "small problem")
+
+
+def test_at_rest_skips_give_the_same_bits():
+    """Only launches of more than 1024 tiles skip the work of material at rest
+    (remap regions of zero volume and cells whose four nodes are at rest,
+    dual regions without mass flux).  The triple point, whose shock has not
+    yet reached most of the grid, alone (a small FP64 launch, no skips) and
+    beside a large problem in a batch (with the skips) must give the same
+    fields."""
+    tp = inputs.triple_point(1)
+    big = inputs.random_mixed(53, 700, 500, nmat=3)
+    steps = 40
+    g, n, _ = alone(tp, LR_FP64, steps=steps)
+    assert n == steps
+    ref = g.fields(*FIELDS)
+    assert np.count_nonzero(ref["ux"] == 0.0) > ref["ux"].size // 2  # mostly at rest still
+    probe = Batch(nmat=3, precision=LR_FP64, max_slots=2, pool_bytes=1 << 20)
+    pool = probe.footprint(tp["nx"], tp["ny"]) + probe.footprint(700, 500) + (16 << 20)
+    probe.close()
+    b = Batch(nmat=3, precision=LR_FP64, max_slots=2, pool_bytes=pool, chunk_steps=4)
+    rs = b.submit(tp, 1e30, max_steps=steps)
+    b.submit(big, 1e30, max_steps=steps)
+    say("triple point 448x192 beside 700x500 (FP64): at-rest skips, against the problem alone")
+    drain(b)
+    rc, st, _ = b.status(rs)
+    assert rc == LR_OK and st == steps
+    same_fields(b.fields(rs, *FIELDS), ref, "triple point")
