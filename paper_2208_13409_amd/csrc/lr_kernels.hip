@@ -813,11 +813,25 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
     sh.ndx[b][a] = dx;
     sh.ndy[b][a] = dy;
   }
-  __syncthreads();
+  // A tile whose cells all have their four nodes at rest (REST launches)
+  // keeps every cell's V, M and E: no region has volume, and P2 to P5 are
+  // skipped (P6 takes Vol^{lagCF} = A and e^{lag} from memory).
+  __syncthreads();  // the staged nodes are complete before anyone reads them
+  bool tile_rest = false;
+  if constexpr (REST) {
+    int mine = 1;
+    if (own6) {
+      const int na = NA(i6), nb = NB(j6);
+      mine = sh.ndx[nb][na] == R(0) && sh.ndy[nb][na] == R(0) && sh.ndx[nb][na + 1] == R(0) &&
+             sh.ndy[nb][na + 1] == R(0) && sh.ndx[nb + 1][na] == R(0) && sh.ndy[nb + 1][na] == R(0) &&
+             sh.ndx[nb + 1][na + 1] == R(0) && sh.ndy[nb + 1][na + 1] == R(0);
+    }
+    tile_rest = __syncthreads_and(mine) != 0;
+  }
 
   // ---- P2: signed face volumes (real faces only: ghost records use the
   // real cell's faces)
-  for (int l = tid; l < SH::XW * SH::XH + SH::YW * SH::YH; l += NTHREADS) {
+  for (int l = tid; !tile_rest && l < SH::XW * SH::XH + SH::YW * SH::YH; l += NTHREADS) {
     if (l < SH::XW * SH::XH) {
       const int a = l % SH::XW, b = l / SH::XW;
       const int I = i0 - 2 + a, j = j0 - 2 + b;
@@ -869,7 +883,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   for (int it = 0; it < NIT3; ++it) {
     ms3[it] = -2;
     const int l = tid + it * NTHREADS;
-    if (l >= SH::NCX * SH::NCY) continue;
+    if (tile_rest || l >= SH::NCX * SH::NCY) continue;
     const int a = l % SH::NCX, b = l / SH::NCX;
     const int i = i0 - 2 + a, j = j0 - 2 + b;
     if (i > nx + 1 || j > ny + 1) continue;
@@ -951,7 +965,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   };
 
   // ---- P4: order-2 values of the regions with a pure donor in the window
-  if (o2) {
+  if (o2 && !tile_rest) {
     for (int l = tid; l < SH::NV; l += NTHREADS) {
       int kind, I, J;
       if (l < SH::VXW * SH::VXH) {
@@ -1088,9 +1102,17 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       const int q = j * nx + i;
       const int ca = a + 2, cb = b + 2;
       // V^{lagCF}_a = k_a Vol^{lagCF}, formed first (few values are live here)
-      R Vcf[NM];
+      R Vcf[NM], elc[NM];
       {
-        const R v = cell_volcf(NA(i), NB(j));
+        R v = A;
+        if (tile_rest) {
+#pragma unroll
+          for (int m = 0; m < NM; ++m) elc[m] = ldg(P.eL + (m * C + q));
+        } else {
+          v = cell_volcf(NA(i), NB(j));
+#pragma unroll
+          for (int m = 0; m < NM; ++m) elc[m] = sh.el[m][cb][ca];
+        }
 #pragma unroll
         for (int m = 0; m < NM; ++m) Vcf[m] = qdiv(V6[m], A) * v;
       }
@@ -1208,7 +1230,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
         Acc<R> V, M, E;
         V.init(Vcf[m]);
         M.init(M0);
-        E.init(M0 * sh.el[m][cb][ca]);
+        E.init(M0 * elc[m]);
         if ((used >> m) & 1u) {
 #pragma unroll
           for (int s = 0; s < 8; ++s) {
