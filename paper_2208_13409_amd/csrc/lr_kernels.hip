@@ -747,9 +747,10 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
     M6[m] = own6 ? ldg(Ms + (m * C + q6)) : R(0);
   }
   // V, M, e^{lag} of record l (the real cell it mirrors); loaded here in
-  // FP32, in P3 in FP64 (issued early it does not pay there: the FP64 block
-  // is held to two per CU by its LDS and hides the latency with the other)
-  constexpr bool PRE3 = sizeof(R) == 4;
+  // FP32 launches without the at-rest skips, else in P3: in FP64 issuing them
+  // early does not pay (the block is held to two per CU by its LDS and hides
+  // the latency with the other), and with the skips a tile at rest reads none
+  constexpr bool PRE3 = sizeof(R) == 4 && !REST;
   auto fetch3 = [&](int l, R *out) {
     const int i = i0 - 2 + l % SH::NCX, j = j0 - 2 + l / SH::NCX;
     if (l >= SH::NCX * SH::NCY || i > nx + 1 || j > ny + 1) return;
