@@ -17,7 +17,10 @@
  *         the linear diagonal corner reconstruction;
  *   §4.4  interface placed on the rectangular approximation of the Lagrangian
  *         cell and partial volume fluxes from its intersection with every
- *         face and corner flux volume.
+ *         face and corner flux volume;
+ *   §5.1, §5.2  perfect-gas and stiffened-gas equations of state.
+ * The alternate-direction remap of §2.1.1-§2.1.2 and §4.2, the paper's
+ * comparator, replaces the DirectCF remap when opts.remap asks for it.
  * Where the paper is silent the readings are the ones written in the design
  * notes of this repository (donor-side volume-fraction clipping, mixture sound
  * speed, CFL formula, boundary mirrors, dual-mesh geometry, ...); each such
@@ -35,6 +38,15 @@
 #include <string.h>
 
 #define G 2 /* ghost layers on every array */
+
+/* branch flags of a cell in one step; counted per step in ctx->counts */
+enum {
+  F_MIXED = 1,      /* two or more materials present: interface reconstructed */
+  F_THREE = 2,      /* three or more materials present                          */
+  F_DEGENERATE = 4, /* a Youngs gradient too small to give a normal             */
+  F_CLIPPED = 8,    /* donor-side limiting of a material's outflow applied      */
+  F_GUARD = 16      /* positivity guard: the donor fell back to order 1         */
+};
 
 struct lr_ref_ctx {
   int nx, ny, nmat;
@@ -58,6 +70,8 @@ struct lr_ref_ctx {
   double *VL, *eL;
   double *volcf, *rhocf, *xcL, *ycL, *dxL, *dyL;
   int *pure; /* material index if exactly one material present, -1 if mixed */
+  int *flags; /* branches a cell took in the last step (F_* bits below) */
+  long counts[LR_REF_NCOUNT]; /* cells that took each branch, summed since set_state */
   double *muX, *muY, *muD, *muA; /* signed total mass fluxes (padded) */
   double *Wx, *Wy, *Wc;          /* signed face / corner volume fluxes (real) */
   double *Wpx, *Wpy, *Wpc;       /* per-material partial volumes [nmat][...] */
@@ -229,6 +243,17 @@ static double van_leer(double dm, double dp) {
   return 0.5 * (phi_r * dp + phi_ri * dm);
 }
 
+/* Equation of state of material a.  §5.1 perfect gas p = (gamma-1) rho e;
+ * §5.2 stiffened gas p = (gamma-1) rho e - pi as the paper writes it (pi = 0
+ * is the perfect gas).  The squared sound speed is (dp/drho) at constant
+ * entropy, (gamma-1)(e + p/rho) = (gamma p + pi)/rho. */
+static double eos_p(const lr_ref_ctx *c, int a, double rho, double e) {
+  return (c->eos[a].gamma - 1.0) * rho * e - c->eos[a].pinf;
+}
+static double eos_k_rho_c2(const lr_ref_ctx *c, int a, double k, double P) {
+  return k * c->eos[a].gamma * P + k * c->eos[a].pinf; /* k rho_a c_a^2 */
+}
+
 /* ------------------------------------------------------------------------ */
 /* allocation                                                                */
 static double *dalloc(size_t n) { return (double *)calloc(n ? n : 1, sizeof(double)); }
@@ -250,7 +275,8 @@ int lr_ref_create(int nx, int ny, int nmat, const lr_ref_eos *eos, const int bc[
     for (int s = 0; s < 4; ++s)
       if (bc[s] != 0) return LR_REF_EINVAL;
   for (int a = 0; a < nmat; ++a)
-    if (!(eos[a].gamma > 1.0) || eos[a].pinf != 0.0) return LR_REF_EINVAL;
+    if (!(eos[a].gamma > 1.0) || !(eos[a].pinf >= 0.0) || !isfinite(eos[a].pinf))
+      return LR_REF_EINVAL;
   lr_ref_ctx *c = (lr_ref_ctx *)calloc(1, sizeof *c);
   if (!c) return LR_REF_ENOMEM;
   c->nx = nx; c->ny = ny; c->nmat = nmat;
@@ -258,6 +284,7 @@ int lr_ref_create(int nx, int ny, int nmat, const lr_ref_eos *eos, const int bc[
   if (opts) c->o = *opts; else lr_ref_default_opts(&c->o);
   if (!(c->o.x1 > c->o.x0) || !(c->o.y1 > c->o.y0) || !(c->o.cfl > 0) ||
       (c->o.recon_order != 1 && c->o.recon_order != 2) || !(c->o.k_eps >= 0) ||
+      (c->o.remap != LR_REF_REMAP_DIRECTCF && c->o.remap != LR_REF_REMAP_AD) ||
       c->o.fixed_dt < 0) {
     free(c);
     return LR_REF_EINVAL;
@@ -279,6 +306,7 @@ int lr_ref_create(int nx, int ny, int nmat, const lr_ref_eos *eos, const int bc[
   c->volcf = dalloc(C); c->rhocf = dalloc(m * C); c->xcL = dalloc(C); c->ycL = dalloc(C);
   c->dxL = dalloc(C); c->dyL = dalloc(C);
   c->pure = (int *)calloc(C, sizeof(int));
+  c->flags = (int *)calloc(C, sizeof(int));
   c->muX = dalloc(nxf(c)); c->muY = dalloc(nyf(c)); c->muD = dalloc(N); c->muA = dalloc(N);
   c->Wx = dalloc(nxf(c)); c->Wy = dalloc(nyf(c)); c->Wc = dalloc(N);
   c->Wpx = dalloc(m * nxf(c)); c->Wpy = dalloc(m * nyf(c)); c->Wpc = dalloc(m * N);
@@ -286,7 +314,7 @@ int lr_ref_create(int nx, int ny, int nmat, const lr_ref_eos *eos, const int bc[
       !c->P_a || !c->Pc || !c->cc || !c->rhoc || !c->Mc || !c->Q || !c->e_half ||
       !c->P_half || !c->Pc_half || !c->S || !c->mp || !c->uhx || !c->uhy || !c->uLx ||
       !c->uLy || !c->dpx || !c->dpy || !c->xLx || !c->xLy || !c->VL || !c->eL ||
-      !c->volcf || !c->rhocf || !c->xcL || !c->ycL || !c->dxL || !c->dyL || !c->pure ||
+      !c->volcf || !c->rhocf || !c->xcL || !c->ycL || !c->dxL || !c->dyL || !c->pure || !c->flags ||
       !c->muX || !c->muY || !c->muD || !c->muA || !c->Wx || !c->Wy || !c->Wc || !c->Wpx ||
       !c->Wpy || !c->Wpc) {
     lr_ref_destroy(c);
@@ -306,6 +334,7 @@ void lr_ref_destroy(lr_ref_ctx *c) {
                     c->Wpc};
   for (size_t a = 0; a < sizeof arrs / sizeof arrs[0]; ++a) free(arrs[a]);
   free(c->pure);
+  free(c->flags);
   free(c);
 }
 
@@ -362,6 +391,7 @@ int lr_ref_set_state(lr_ref_ctx *c, double t, const double *k, const double *rho
   c->t = t;
   c->step = 0;
   c->have_state = 1;
+  memset(c->counts, 0, sizeof c->counts);
   return LR_REF_OK;
 }
 
@@ -371,23 +401,23 @@ static int present(const lr_ref_ctx *c, double V) { return V > c->o.k_eps * c->A
 
 static void derived(lr_ref_ctx *c) {
   int C = ncell(c);
+#pragma omp parallel for schedule(static)
   for (int j = 0; j < c->ny; ++j)
     for (int i = 0; i < c->nx; ++i) {
       int q = CI(c, i, j);
       double Msum = 0.0, Pc = 0.0, rc2 = 0.0;
       for (int a = 0; a < c->nmat; ++a) {
         double V = c->V[a * C + q], M = c->M[a * C + q], E = c->E[a * C + q];
-        double gam = c->eos[a].gamma;
         c->k[a * C + q] = V / c->A;
         if (present(c, V)) {
           double rho = M / V;
           double e = M > 0.0 ? E / M : 0.0;
-          double P = (gam - 1.0) * rho * e; /* perfect gas, §5.1 */
+          double P = eos_p(c, a, rho, e);
           c->rho_a[a * C + q] = rho;
           c->e_a[a * C + q] = e;
           c->P_a[a * C + q] = P;
-          Pc += c->k[a * C + q] * P;          /* §4.1: P_c = sum k P */
-          rc2 += c->k[a * C + q] * gam * P;   /* reading: rho c^2 = sum k rho_a c_a^2 */
+          Pc += c->k[a * C + q] * P;                  /* §4.1: P_c = sum k P */
+          rc2 += eos_k_rho_c2(c, a, c->k[a * C + q], P); /* reading: rho c^2 = sum k rho_a c_a^2 */
         } else {
           c->rho_a[a * C + q] = 0.0;
           c->e_a[a * C + q] = M > 0.0 ? E / M : 0.0;
@@ -415,8 +445,11 @@ static void derived(lr_ref_ctx *c) {
 /* reading: dt = CFL min_c min(dx/(c+max|ux|), dy/(c+max|uy|)) over the four
  * nodes of c, the last step clamped to t_end */
 static double cfl_dt(const lr_ref_ctx *c) {
-  double best = INFINITY;
-  for (int j = 0; j < c->ny; ++j)
+  double *row = dalloc(c->ny);
+  if (!row) return NAN;
+#pragma omp parallel for schedule(static)
+  for (int j = 0; j < c->ny; ++j) {
+    double best = INFINITY;
     for (int i = 0; i < c->nx; ++i) {
       double Ux = 0.0, Uy = 0.0;
       for (int b = 0; b < 2; ++b)
@@ -428,6 +461,11 @@ static double cfl_dt(const lr_ref_ctx *c) {
       double cand = fmin(c->dx / (cs + Ux), c->dy / (cs + Uy));
       best = fmin(best, cand);
     }
+    row[j] = best;
+  }
+  double best = INFINITY;
+  for (int j = 0; j < c->ny; ++j) best = fmin(best, row[j]);
+  free(row);
   return c->o.cfl * best;
 }
 
@@ -435,6 +473,7 @@ static double cfl_dt(const lr_ref_ctx *c) {
  * reading: rho multiplies both terms, div u from the four nodal velocities */
 static void pseudo_viscosity(lr_ref_ctx *c) {
   double L = sqrt(c->A);
+#pragma omp parallel for schedule(static)
   for (int j = 0; j < c->ny; ++j)
     for (int i = 0; i < c->nx; ++i) {
       double uBLx = c->ux[NI(c, i, j)], uBRx = c->ux[NI(c, i + 1, j)];
@@ -454,6 +493,7 @@ static void pseudo_viscosity(lr_ref_ctx *c) {
 
 /* §1.2: nodal mass m_p = 1/4 sum of the four cell masses */
 static void nodal_mass(lr_ref_ctx *c) {
+#pragma omp parallel for schedule(static)
   for (int J = 0; J <= c->ny; ++J)
     for (int I = 0; I <= c->nx; ++I)
       c->mp[NI(c, I, J)] = 0.25 * (c->Mc[CI(c, I - 1, J - 1)] + c->Mc[CI(c, I, J - 1)] +
@@ -472,12 +512,14 @@ static double cell_F(const lr_ref_ctx *c, int i, int j, const double *hx, const 
 static void predictor(lr_ref_ctx *c, double dt) {
   int C = ncell(c), N = nnode(c);
   double *hx = dalloc(N), *hy = dalloc(N);
+#pragma omp parallel for schedule(static)
   for (int J = 0; J <= c->ny; ++J)
     for (int I = 0; I <= c->nx; ++I) {
       int p = NI(c, I, J);
       hx[p] = 0.5 * dt * c->ux[p]; /* x^{n+1/2} - x^n */
       hy[p] = 0.5 * dt * c->uy[p];
     }
+#pragma omp parallel for schedule(static)
   for (int j = 0; j < c->ny; ++j)
     for (int i = 0; i < c->nx; ++i) {
       int q = CI(c, i, j);
@@ -490,7 +532,7 @@ static void predictor(lr_ref_ctx *c, double dt) {
           double Vah = c->k[qa] * Vh;              /* Vol_a^{n+1/2} = k_a Vol_c^{n+1/2} */
           double rho_h = M / Vah;
           double e_h = c->e_a[qa] - (c->P_a[qa] + c->Q[q]) * (1.0 / rho_h - 1.0 / c->rho_a[qa]);
-          double P_h = (c->eos[a].gamma - 1.0) * rho_h * e_h;
+          double P_h = eos_p(c, a, rho_h, e_h);
           c->e_half[qa] = e_h;
           c->P_half[qa] = P_h;
           Pch += c->k[qa] * P_h;
@@ -504,6 +546,7 @@ static void predictor(lr_ref_ctx *c, double dt) {
     }
   ghost_cells(c, c->S);
   /* nodal gradient of P+Q and velocity prediction */
+#pragma omp parallel for schedule(static)
   for (int J = 0; J <= c->ny; ++J)
     for (int I = 0; I <= c->nx; ++I) {
       int p = NI(c, I, J);
@@ -523,6 +566,7 @@ static void predictor(lr_ref_ctx *c, double dt) {
 /* §1.2 eq. "correction" with §4.1 eq. "correction_multi" */
 static void corrector(lr_ref_ctx *c, double dt) {
   int C = ncell(c);
+#pragma omp parallel for schedule(static)
   for (int J = 0; J <= c->ny; ++J)
     for (int I = 0; I <= c->nx; ++I) {
       int p = NI(c, I, J);
@@ -532,6 +576,7 @@ static void corrector(lr_ref_ctx *c, double dt) {
       c->uLy[p] = 2.0 * c->uhy[p] - c->uy[p];
     }
   wall_nodes(c, c->uLx, c->uLy);
+#pragma omp parallel for schedule(static)
   for (int j = 0; j < c->ny; ++j)
     for (int i = 0; i < c->nx; ++i) {
       int q = CI(c, i, j);
@@ -687,31 +732,40 @@ static void youngs(const lr_ref_ctx *c, int a, int i, int j, double *gx, double 
 #undef K
 }
 
-/* §4.4: split every outflow region of mixed donor (i,j) between its present
- * materials with the interface placed on the rectangular approximation of the
- * Lagrangian cell, then the donor-side clipping (reading). */
-static void mixed_donor_partials(const lr_ref_ctx *c, regions *R, int i, int j) {
+/* §4.4: the rectangular approximation of the Lagrangian cell (i,j), through
+ * the midpoints of its four Lagrangian faces, in coordinates local to the
+ * Eulerian cell centre.  mx, my = 0 keep that direction's faces Eulerian (the
+ * X- and Y-Lagrangian cells of the alternate-direction remap, §4.2). */
+static void lagrangian_rectangle(const lr_ref_ctx *c, int i, int j, int mx, int my,
+                                 double *Rx0, double *Rx1, double *Ry0, double *Ry1) {
+  int bl = NI(c, i, j), br = NI(c, i + 1, j), tl = NI(c, i, j + 1), tr = NI(c, i + 1, j + 1);
+  *Rx0 = (mx ? 0.5 * (c->dpx[bl] + c->dpx[tl]) : 0.0) - 0.5 * c->dx;
+  *Rx1 = (mx ? 0.5 * (c->dpx[br] + c->dpx[tr]) : 0.0) + 0.5 * c->dx;
+  *Ry0 = (my ? 0.5 * (c->dpy[bl] + c->dpy[br]) : 0.0) - 0.5 * c->dy;
+  *Ry1 = (my ? 0.5 * (c->dpy[tl] + c->dpy[tr]) : 0.0) + 0.5 * c->dy;
+}
+
+/* §4.4: split every outflow region of mixed donor (i,j) (rs[0..nr-1], the
+ * regions touching it) between its present materials with the interface
+ * placed on the rectangle R of its Lagrangian cell, then the donor-side
+ * clipping (reading) against k_a vlag, vlag its flux-consistent Lagrangian
+ * volume. */
+static void mixed_donor_partials(lr_ref_ctx *c, region **rs, int nr, int i, int j,
+                                 double Rx0, double Rx1, double Ry0, double Ry1,
+                                 double vlag) {
   int C = ncell(c), q = CI(c, i, j), nm = c->nmat;
-  region *rs[8];
-  cell_regions(c, R, i, j, rs);
   int pres[LR_REF_MAXMAT], np = 0;
   double Vp = 0.0;
   for (int a = 0; a < nm; ++a) {
     pres[a] = present(c, c->V[a * C + q]);
     if (pres[a]) { ++np; Vp += c->V[a * C + q]; }
   }
-  /* rectangle through the midpoints of the four Lagrangian faces, in
-   * coordinates local to the Eulerian cell centre */
-  int bl = NI(c, i, j), br = NI(c, i + 1, j), tl = NI(c, i, j + 1), tr = NI(c, i + 1, j + 1);
-  double Rx0 = 0.5 * (c->dpx[bl] + c->dpx[tl]) - 0.5 * c->dx;
-  double Rx1 = 0.5 * (c->dpx[br] + c->dpx[tr]) + 0.5 * c->dx;
-  double Ry0 = 0.5 * (c->dpy[bl] + c->dpy[br]) - 0.5 * c->dy;
-  double Ry1 = 0.5 * (c->dpy[tl] + c->dpy[tr]) + 0.5 * c->dy;
   /* reading: a Youngs gradient below gmin is numerical noise -> no normal */
   double gmin = 1e-10 / fmin(c->dx, c->dy);
 
   double nxv[LR_REF_MAXMAT], nyv[LR_REF_MAXMAT], sv[LR_REF_MAXMAT];
   int degenerate = 0, a0 = -1, b0 = -1;
+  c->flags[q] |= F_MIXED | (np >= 3 ? F_THREE : 0);
   if (np == 2) {
     for (int a = 0; a < nm; ++a)
       if (pres[a]) { if (a0 < 0) a0 = a; else b0 = a; }
@@ -737,8 +791,9 @@ static void mixed_donor_partials(const lr_ref_ctx *c, regions *R, int i, int j) 
       sv[a] = lr_ref_interface_offset(Rx0, Rx1, Ry0, Ry1, nxv[a], nyv[a], c->V[a * C + q] / Vp);
     }
   }
+  if (degenerate) c->flags[q] |= F_DEGENERATE;
   /* partial volumes of each outflow region */
-  for (int s = 0; s < 8; ++s) {
+  for (int s = 0; s < nr; ++s) {
     region *r = rs[s];
     if (!is_donor(r, i, j)) continue;
     for (int a = 0; a < nm; ++a) r->W[a] = 0.0;
@@ -776,9 +831,9 @@ static void mixed_donor_partials(const lr_ref_ctx *c, regions *R, int i, int j) 
   double Vcf[LR_REF_MAXMAT], O[LR_REF_MAXMAT];
   int over[LR_REF_MAXMAT], any_over = 0;
   for (int a = 0; a < nm; ++a) {
-    Vcf[a] = c->k[a * C + q] * c->volcf[q];
+    Vcf[a] = c->k[a * C + q] * vlag;
     O[a] = 0.0;
-    for (int s = 0; s < 8; ++s)
+    for (int s = 0; s < nr; ++s)
       if (is_donor(rs[s], i, j)) O[a] += rs[s]->W[a];
     over[a] = pres[a] && O[a] > Vcf[a];
     any_over |= over[a];
@@ -790,7 +845,8 @@ static void mixed_donor_partials(const lr_ref_ctx *c, regions *R, int i, int j) 
     H += room[a];
   }
   if (!(H > 0.0)) return;
-  for (int s = 0; s < 8; ++s) {
+  c->flags[q] |= F_CLIPPED;
+  for (int s = 0; s < nr; ++s) {
     region *r = rs[s];
     if (!is_donor(r, i, j)) continue;
     double freed = 0.0;
@@ -875,48 +931,86 @@ static double dual_wy(const lr_ref_ctx *c, int I, int J) {
   return c->dy + 0.5 * (c->dpy[NI(c, I, J + 1)] - c->dpy[NI(c, I, J - 1)]);
 }
 
-/* ------------------------------------------------------------------------ */
-static int step_once(lr_ref_ctx *c, double t_end, double *dt_out, int *last) {
-  int C = ncell(c), N = nnode(c), nm = c->nmat, nx = c->nx, ny = c->ny;
-  *last = 0;
-  for (int a = 0; a < nm; ++a) {
-    ghost_cells(c, c->V + a * C);
-    ghost_cells(c, c->M + a * C);
-    ghost_cells(c, c->E + a * C);
-  }
-  ghost_nodes_vec(c, c->ux, c->uy);
-  derived(c);
-
-  /* time step */
-  double dt = c->o.fixed_dt > 0.0 ? c->o.fixed_dt : cfl_dt(c);
-  if (t_end - c->t <= dt) { dt = t_end - c->t; *last = 1; }
-  if (!(dt > 0.0) || !isfinite(dt)) return fail(c, LR_REF_EDT, "time step underflow or not finite");
-  c->last_dt = dt;
-
-  /* Lagrangian phase */
-  if (c->o.kinematic) {
-    for (int q = 0; q < C; ++q) c->Q[q] = 0.0;
-    nodal_mass(c);
-    kinematic_lagrange(c, dt);
+/* outflow partial volumes of donor (i,j): a pure donor sends its material
+ * only, a mixed one is split by its interface (§4.4) */
+static void donor_partials(lr_ref_ctx *c, region **rs, int nr, int i, int j, int mx, int my,
+                           double vlag) {
+  int q = CI(c, i, j), nm = c->nmat;
+  if (c->pure[q] >= 0) {
+    for (int s = 0; s < nr; ++s)
+      if (is_donor(rs[s], i, j)) {
+        for (int a = 0; a < nm; ++a) rs[s]->W[a] = 0.0;
+        rs[s]->W[c->pure[q]] = rs[s]->vol;
+      }
   } else {
-    pseudo_viscosity(c);
-    nodal_mass(c);
-    predictor(c, dt);
-    corrector(c, dt);
+    double Rx0, Rx1, Ry0, Ry1;
+    lagrangian_rectangle(c, i, j, mx, my, &Rx0, &Rx1, &Ry0, &Ry1);
+    mixed_donor_partials(c, rs, nr, i, j, Rx0, Rx1, Ry0, Ry1, vlag);
   }
-  for (int p = 0; p < N; ++p) { c->xLx[p] = 0; c->xLy[p] = 0; }
-  for (int J = 0; J <= ny; ++J)
-    for (int I = 0; I <= nx; ++I) {
-      int p = NI(c, I, J);
-      c->xLx[p] = node_x(c, I) + c->dpx[p];
-      c->xLy[p] = node_y(c, J) + c->dpy[p];
-    }
-  ghost_nodes_vec(c, c->dpx, c->dpy);
-  ghost_nodes_vec(c, c->uhx, c->uhy);
-  ghost_nodes_vec(c, c->uLx, c->uLy);
-  ghost_nodes_pos(c, c->xLx, c->xLy);
-  ghost_nodes_scalar(c, c->mp);
+}
 
+/* reconstruction and mass / energy fluxes of the outflow regions of donor
+ * (i,j) (§2.1.1, §3.3, §4.2) */
+static void donor_fluxes(lr_ref_ctx *c, region **rs, int nr, int i, int j) {
+  int C = ncell(c), q = CI(c, i, j), nm = c->nmat;
+  int order = c->o.recon_order;
+  if (c->pure[q] < 0) order = 1; /* §4.2: mixed donors degenerate to order 1 */
+  for (int pass = 0; pass < 2; ++pass) {
+    double Mout[LR_REF_MAXMAT] = {0}, Eout[LR_REF_MAXMAT] = {0};
+    for (int s = 0; s < nr; ++s) {
+      region *r = rs[s];
+      if (!is_donor(r, i, j)) continue;
+      for (int a = 0; a < nm; ++a) {
+        r->mu[a] = r->eps[a] = r->vrho[a] = r->ve[a] = 0.0;
+        if (!(r->W[a] > 0.0)) continue;
+        double rho = recon(c, r, c->rhocf + a * C, order);
+        double e = recon(c, r, c->eL + a * C, order);
+        r->vrho[a] = rho;
+        r->ve[a] = e;
+        r->mu[a] = rho * r->W[a];
+        r->eps[a] = r->mu[a] * e;
+        Mout[a] += r->mu[a];
+        Eout[a] += r->eps[a];
+      }
+    }
+    if (order == 1) break;
+    /* reading: positivity guard on the donor's (single present) material:
+     * if its order-2 outflow exceeds its mass or Lagrangian internal
+     * energy, the whole donor falls back to order 1 */
+    int a = c->pure[q], qa = a * C + q;
+    if (!(Mout[a] > c->M[qa] || Eout[a] > c->M[qa] * c->eL[qa])) break;
+    order = 1;
+    c->flags[q] |= F_GUARD;
+  }
+}
+
+/* conservative update of cell (i,j) from its regions in the order given
+ * (§2.3, §4.4): V = k vlag + in - out, M = M + in - out, E = M e^lag + in - out */
+static void primal_update(lr_ref_ctx *c, region **rs, int nr, int i, int j, double vlag) {
+  int C = ncell(c), q = CI(c, i, j), nm = c->nmat;
+  for (int a = 0; a < nm; ++a) {
+    int qa = a * C + q;
+    double V = c->k[qa] * vlag;
+    double M = c->M[qa];
+    double E = c->M[qa] * c->eL[qa];
+    for (int s = 0; s < nr; ++s) {
+      region *r = rs[s];
+      if (is_receiver(r, i, j)) { V += r->W[a]; M += r->mu[a]; E += r->eps[a]; }
+      else if (is_donor(r, i, j)) { V -= r->W[a]; M -= r->mu[a]; E -= r->eps[a]; }
+    }
+    c->V[qa] = V;
+    c->M[qa] = M;
+    c->E[qa] = E;
+  }
+}
+
+/* §2.3 DirectCF remap of the Lagrangian state: face and corner regions, the
+ * flux-consistent Lagrangian volume, partial volumes, reconstruction, primal
+ * update, then the dual (momentum) update.  Returns LR_REF_OK or the error
+ * code of the last failed check. */
+static int remap_directcf(lr_ref_ctx *c) {
+  int C = ncell(c), N = nnode(c), nm = c->nmat, nx = c->nx, ny = c->ny;
+  int rc = LR_REF_OK;
   /* remap geometry: corner and face volume fluxes (§2.3) */
   regions R;
   R.xf = (region *)calloc((size_t)(nx + 1) * ny, sizeof(region));
@@ -926,16 +1020,20 @@ static int step_once(lr_ref_ctx *c, double t_end, double *dt_out, int *last) {
     free(R.xf); free(R.yf); free(R.cn);
     return fail(c, LR_REF_ENOMEM, "out of memory");
   }
-  int rc = LR_REF_OK;
+#pragma omp parallel for schedule(static)
   for (int j = 0; j < ny; ++j)
     for (int I = 0; I <= nx; ++I) xface_region(c, I, j, XF(c, &R, I, j));
+#pragma omp parallel for schedule(static)
   for (int J = 0; J <= ny; ++J)
     for (int i = 0; i < nx; ++i) yface_region(c, i, J, YF(c, &R, i, J));
+#pragma omp parallel for schedule(static)
   for (int J = 0; J <= ny; ++J)
     for (int I = 0; I <= nx; ++I) corner_region(c, I, J, CN(c, &R, I, J));
 
   /* flux-consistent Lagrangian volume (reading: + outflow - inflow), the
    * Lagrangian cell centre and widths, purity */
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       int q = CI(c, i, j);
@@ -947,7 +1045,7 @@ static int step_once(lr_ref_ctx *c, double t_end, double *dt_out, int *last) {
         else if (is_receiver(rs[s], i, j)) v -= rs[s]->vol;
       }
       c->volcf[q] = v;
-      if (!(v > 0.0)) rc = fail(c, LR_REF_ENEGATIVE, "flux-consistent Lagrangian volume <= 0");
+      if (!(v > 0.0)) bad = 1;
       int bl = NI(c, i, j), br = NI(c, i + 1, j), tl = NI(c, i, j + 1), tr = NI(c, i + 1, j + 1);
       c->xcL[q] = 0.25 * (c->xLx[bl] + c->xLx[br] + c->xLx[tl] + c->xLx[tr]);
       c->ycL[q] = 0.25 * (c->xLy[bl] + c->xLy[br] + c->xLy[tl] + c->xLy[tr]);
@@ -962,6 +1060,7 @@ static int step_once(lr_ref_ctx *c, double t_end, double *dt_out, int *last) {
       }
       c->pure[q] = np == 1 ? m : -1;
     }
+  if (bad) rc = fail(c, LR_REF_ENEGATIVE, "flux-consistent Lagrangian volume <= 0");
   for (int a = 0; a < nm; ++a) {
     ghost_cells(c, c->rhocf + a * C);
     ghost_cells(c, c->eL + a * C);
@@ -974,78 +1073,30 @@ static int step_once(lr_ref_ctx *c, double t_end, double *dt_out, int *last) {
   ghost_cells_int(c, c->pure);
 
   /* partial volumes (§4.4) */
+#pragma omp parallel for schedule(static)
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
-      int q = CI(c, i, j);
       region *rs[8];
       cell_regions(c, &R, i, j, rs);
-      if (c->pure[q] >= 0) {
-        for (int s = 0; s < 8; ++s)
-          if (is_donor(rs[s], i, j)) {
-            for (int a = 0; a < nm; ++a) rs[s]->W[a] = 0.0;
-            rs[s]->W[c->pure[q]] = rs[s]->vol;
-          }
-      } else {
-        mixed_donor_partials(c, &R, i, j);
-      }
+      donor_partials(c, rs, 8, i, j, 1, 1, c->volcf[CI(c, i, j)]);
     }
 
   /* reconstruction and mass / energy fluxes, donor by donor */
+#pragma omp parallel for schedule(static)
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
-      int q = CI(c, i, j);
       region *rs[8];
       cell_regions(c, &R, i, j, rs);
-      int order = c->o.recon_order;
-      if (c->pure[q] < 0) order = 1; /* §4.2: mixed donors degenerate to order 1 */
-      for (int pass = 0; pass < 2; ++pass) {
-        double Mout[LR_REF_MAXMAT] = {0}, Eout[LR_REF_MAXMAT] = {0};
-        for (int s = 0; s < 8; ++s) {
-          region *r = rs[s];
-          if (!is_donor(r, i, j)) continue;
-          for (int a = 0; a < nm; ++a) {
-            r->mu[a] = r->eps[a] = r->vrho[a] = r->ve[a] = 0.0;
-            if (!(r->W[a] > 0.0)) continue;
-            double rho = recon(c, r, c->rhocf + a * C, order);
-            double e = recon(c, r, c->eL + a * C, order);
-            r->vrho[a] = rho;
-            r->ve[a] = e;
-            r->mu[a] = rho * r->W[a];
-            r->eps[a] = r->mu[a] * e;
-            Mout[a] += r->mu[a];
-            Eout[a] += r->eps[a];
-          }
-        }
-        if (order == 1) break;
-        /* reading: positivity guard on the donor's (single present) material:
-         * if its order-2 outflow exceeds its mass or Lagrangian internal
-         * energy, the whole donor falls back to order 1 */
-        int a = c->pure[q], qa = a * C + q;
-        if (!(Mout[a] > c->M[qa] || Eout[a] > c->M[qa] * c->eL[qa])) break;
-        order = 1;
-      }
+      donor_fluxes(c, rs, 8, i, j);
     }
 
   /* primal update (§2.3, §4.4), regions in the order W, E, S, N, BL, BR, TL, TR */
+#pragma omp parallel for schedule(static)
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
-      int q = CI(c, i, j);
       region *rs[8];
       cell_regions(c, &R, i, j, rs);
-      for (int a = 0; a < nm; ++a) {
-        int qa = a * C + q;
-        double V = c->k[qa] * c->volcf[q];
-        double M = c->M[qa];
-        double E = c->M[qa] * c->eL[qa];
-        for (int s = 0; s < 8; ++s) {
-          region *r = rs[s];
-          if (is_receiver(r, i, j)) { V += r->W[a]; M += r->mu[a]; E += r->eps[a]; }
-          else if (is_donor(r, i, j)) { V -= r->W[a]; M -= r->mu[a]; E -= r->eps[a]; }
-        }
-        c->V[qa] = V;
-        c->M[qa] = M;
-        c->E[qa] = E;
-      }
+      primal_update(c, rs, 8, i, j, c->volcf[CI(c, i, j)]);
     }
 
   /* signed total mass fluxes of every region, then their mirrors */
@@ -1119,6 +1170,7 @@ static int step_once(lr_ref_ctx *c, double t_end, double *dt_out, int *last) {
     /* dual x-face (I,J) between nodes (I-1,J) and (I,J), I in [0,nx+1] */
     int dw = nx + 2, dh = ny + 1;
     double *fxm = dalloc((size_t)dw * dh), *fxu = dalloc((size_t)dw * dh), *fxv = dalloc((size_t)dw * dh);
+#pragma omp parallel for schedule(static)
     for (int J = 0; J <= ny; ++J)
       for (int I = 0; I <= nx + 1; ++I) {
         double phi = 0.25 * (c->muX[XI(c, I - 1, J - 1)] + c->muX[XI(c, I, J - 1)] +
@@ -1140,6 +1192,7 @@ static int step_once(lr_ref_ctx *c, double t_end, double *dt_out, int *last) {
     /* dual y-face (I,J) between nodes (I,J-1) and (I,J), J in [0,ny+1] */
     int ew = nx + 1, eh = ny + 2;
     double *fym = dalloc((size_t)ew * eh), *fyu = dalloc((size_t)ew * eh), *fyv = dalloc((size_t)ew * eh);
+#pragma omp parallel for schedule(static)
     for (int J = 0; J <= ny + 1; ++J)
       for (int I = 0; I <= nx; ++I) {
         double phi = 0.25 * (c->muY[YI(c, I - 1, J - 1)] + c->muY[YI(c, I, J - 1)] +
@@ -1164,6 +1217,7 @@ static int step_once(lr_ref_ctx *c, double t_end, double *dt_out, int *last) {
     int gw = nx + 2, gh = ny + 2;
     double *cdm = dalloc((size_t)gw * gh), *cdu = dalloc((size_t)gw * gh), *cdv = dalloc((size_t)gw * gh);
     double *cam = dalloc((size_t)gw * gh), *cau = dalloc((size_t)gw * gh), *cav = dalloc((size_t)gw * gh);
+#pragma omp parallel for schedule(static)
     for (int j = -1; j <= ny; ++j)
       for (int i = -1; i <= nx; ++i) {
         int h = (j + 1) * gw + (i + 1);
@@ -1201,6 +1255,8 @@ static int step_once(lr_ref_ctx *c, double t_end, double *dt_out, int *last) {
         cam[h] = phi; cau[h] = phi * vu; cav[h] = phi * vv;
       }
     /* nodal momentum update, order W, E, S, N, SW, NE, NW, SE */
+    int badm = 0;
+#pragma omp parallel for schedule(static) reduction(| : badm)
     for (int J = 0; J <= ny; ++J)
       for (int I = 0; I <= nx; ++I) {
         int p = NI(c, I, J);
@@ -1218,18 +1274,344 @@ static int step_once(lr_ref_ctx *c, double t_end, double *dt_out, int *last) {
         m -= cdm[hNE]; mu -= cdu[hNE]; mv -= cdv[hNE];
         m += cam[hNW]; mu += cau[hNW]; mv += cav[hNW];
         m -= cam[hSE]; mu -= cau[hSE]; mv -= cav[hSE];
-        if (!(m > 0.0)) rc = fail(c, LR_REF_ENEGATIVE, "nodal mass <= 0 after remap");
+        if (!(m > 0.0)) badm = 1;
         c->ux[p] = mu / m;
         c->uy[p] = mv / m;
       }
+    if (badm) rc = fail(c, LR_REF_ENEGATIVE, "nodal mass <= 0 after remap");
     wall_nodes(c, c->ux, c->uy);
     free(fxm); free(fxu); free(fxv); free(fym); free(fyu); free(fyv);
     free(cdm); free(cdu); free(cdv); free(cam); free(cau); free(cav);
   }
 
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alternate-direction (AD) remap, the paper's comparator (§2.1.1, §2.1.2,
+ * §4.2): an X pass over the x-faces only, then a Y pass over the y-faces only
+ * (Y then X on every second step, §2.1.2 remark 3), each a one-dimensional
+ * remap of the cell and nodal quantities with its own interface. */
+
+/* §2.1.1: x-face (I,j) flux of the X pass: the rectangle of full cell height
+ * and width w = dt u_f, u_f the mean x-velocity of the face's two nodes */
+static void ad_xface_region(const lr_ref_ctx *c, int I, int j, region *r) {
+  memset(r, 0, sizeof *r);
+  double w = 0.5 * (c->dpx[NI(c, I, j)] + c->dpx[NI(c, I, j + 1)]);
+  r->type = 0; r->I = I; r->J = j;
+  r->vol = fabs(w * c->dy);
+  if (w >= 0.0) { r->di = I - 1; r->dj = j; r->ri = I; r->rj = j; r->sgn = 1; }
+  else { r->di = I; r->dj = j; r->ri = I - 1; r->rj = j; r->sgn = -1; }
+  r->rx0 = fmin(0.0, w); r->rx1 = fmax(0.0, w);
+  r->ry0 = 0.0; r->ry1 = c->dy;
+}
+
+/* §2.1.2: y-face (i,J) flux of the Y pass, x and y exchanged */
+static void ad_yface_region(const lr_ref_ctx *c, int i, int J, region *r) {
+  memset(r, 0, sizeof *r);
+  double w = 0.5 * (c->dpy[NI(c, i, J)] + c->dpy[NI(c, i + 1, J)]);
+  r->type = 1; r->I = i; r->J = J;
+  r->vol = fabs(w * c->dx);
+  if (w >= 0.0) { r->di = i; r->dj = J - 1; r->ri = i; r->rj = J; r->sgn = 1; }
+  else { r->di = i; r->dj = J; r->ri = i; r->rj = J - 1; r->sgn = -1; }
+  r->rx0 = 0.0; r->rx1 = c->dx;
+  r->ry0 = fmin(0.0, w); r->ry1 = fmax(0.0, w);
+}
+
+/* One pass along x (dir 0) or y (dir 1).  Its input is the state (V, M, E)
+ * and the nodal velocity (ux, uy) left by the previous pass (the Lagrangian
+ * state for the first pass: e = e^lag, u = u^lag); it leaves the projected
+ * state in the same arrays. */
+static int ad_pass(lr_ref_ctx *c, int dir, int first) {
+  int C = ncell(c), nm = c->nmat, nx = c->nx, ny = c->ny;
+  int rc = LR_REF_OK;
+  for (int a = 0; a < nm; ++a) {
+    ghost_cells(c, c->V + a * C);
+    ghost_cells(c, c->M + a * C);
+    ghost_cells(c, c->E + a * C);
+  }
+  /* §4.2: the pass starts from the volume fractions, specific energies and
+   * nodal masses of its input state (k^{lagy} = k^{projx}, e^{lagy} = e^{projx}) */
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      int q = CI(c, i, j);
+      double Msum = 0.0;
+      for (int a = 0; a < nm; ++a) {
+        int qa = a * C + q;
+        c->k[qa] = c->V[qa] / c->A;
+        if (!first) c->eL[qa] = c->M[qa] > 0.0 ? c->E[qa] / c->M[qa] : 0.0;
+        Msum += c->M[qa];
+      }
+      c->Mc[q] = Msum;
+    }
+  for (int a = 0; a < nm; ++a) ghost_cells(c, c->k + a * C);
+  ghost_cells(c, c->Mc);
+  nodal_mass(c);
+  ghost_nodes_scalar(c, c->mp);
+  ghost_nodes_vec(c, c->ux, c->uy);
+
+  /* regions of this direction */
+  int nreg = dir == 0 ? (nx + 1) * ny : nx * (ny + 1);
+  region *reg = (region *)calloc((size_t)nreg, sizeof(region));
+  if (!reg) return fail(c, LR_REF_ENOMEM, "out of memory");
+#define ADR(i, j) (dir == 0 ? &reg[(j) * (nx + 1) + (i)] : &reg[(j) * nx + (i)])
+  if (dir == 0) {
+    for (int j = 0; j < ny; ++j)
+      for (int I = 0; I <= nx; ++I) ad_xface_region(c, I, j, ADR(I, j));
+  } else {
+    for (int J = 0; J <= ny; ++J)
+      for (int i = 0; i < nx; ++i) ad_yface_region(c, i, J, ADR(i, J));
+  }
+  /* the two regions of cell (i,j): W, E (X pass) or S, N (Y pass) */
+#define AD_CELL_REGIONS(rs, i, j)                                  \
+  do {                                                             \
+    if (dir == 0) { rs[0] = ADR(i, j); rs[1] = ADR((i) + 1, j); }  \
+    else { rs[0] = ADR(i, j); rs[1] = ADR(i, (j) + 1); }           \
+  } while (0)
+
+  /* the pass's Lagrangian volume (reading R1: A + outflow - inflow),
+   * centre and width along dir, density rho^{lagx} = m / (k Vol^{lagx}) */
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      int q = CI(c, i, j);
+      region *rs[2];
+      AD_CELL_REGIONS(rs, i, j);
+      double v = c->A;
+      for (int s = 0; s < 2; ++s) {
+        if (is_donor(rs[s], i, j)) v += rs[s]->vol;
+        else if (is_receiver(rs[s], i, j)) v -= rs[s]->vol;
+      }
+      c->volcf[q] = v;
+      if (!(v > 0.0)) rc = fail(c, LR_REF_ENEGATIVE, "Lagrangian volume of a pass <= 0");
+      int bl = NI(c, i, j), br = NI(c, i + 1, j), tl = NI(c, i, j + 1), tr = NI(c, i + 1, j + 1);
+      c->xcL[q] = dir == 0 ? 0.25 * (c->xLx[bl] + c->xLx[br] + c->xLx[tl] + c->xLx[tr])
+                           : c->o.x0 + (i + 0.5) * c->dx;
+      c->ycL[q] = dir == 1 ? 0.25 * (c->xLy[bl] + c->xLy[br] + c->xLy[tl] + c->xLy[tr])
+                           : c->o.y0 + (j + 0.5) * c->dy;
+      c->dxL[q] = dir == 0 ? c->dx + 0.5 * ((c->dpx[br] + c->dpx[tr]) - (c->dpx[bl] + c->dpx[tl]))
+                           : c->dx;
+      c->dyL[q] = dir == 1 ? c->dy + 0.5 * ((c->dpy[tl] + c->dpy[tr]) - (c->dpy[bl] + c->dpy[br]))
+                           : c->dy;
+      int np = 0, m = -1;
+      for (int a = 0; a < nm; ++a) {
+        int qa = a * C + q;
+        if (present(c, c->V[qa])) { ++np; m = a; }
+        c->rhocf[qa] = present(c, c->V[qa]) ? c->M[qa] / (c->k[qa] * v) : 0.0;
+      }
+      c->pure[q] = np == 1 ? m : -1;
+    }
+  for (int a = 0; a < nm; ++a) {
+    ghost_cells(c, c->rhocf + a * C);
+    ghost_cells(c, c->eL + a * C);
+  }
+  ghost_cells(c, c->volcf);
+  ghost_cells_coord(c, c->xcL, 0);
+  ghost_cells_coord(c, c->ycL, 1);
+  ghost_cells(c, c->dxL);
+  ghost_cells(c, c->dyL);
+  ghost_cells_int(c, c->pure);
+
+  /* §4.2: partial volumes from the interface placed on the pass's Lagrangian
+   * cell (only its faces along dir move), reconstruction, update */
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      region *rs[2];
+      AD_CELL_REGIONS(rs, i, j);
+      donor_partials(c, rs, 2, i, j, dir == 0, dir == 1, c->volcf[CI(c, i, j)]);
+    }
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      region *rs[2];
+      AD_CELL_REGIONS(rs, i, j);
+      donor_fluxes(c, rs, 2, i, j);
+    }
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      region *rs[2];
+      AD_CELL_REGIONS(rs, i, j);
+      primal_update(c, rs, 2, i, j, c->volcf[CI(c, i, j)]);
+    }
+
+  /* signed total mass fluxes of the pass's faces, mirrored at the walls */
+  if (dir == 0) {
+    for (int p = 0; p < nxf(c); ++p) c->muX[p] = 0.0;
+    for (int j = 0; j < ny; ++j)
+      for (int I = 0; I <= nx; ++I) {
+        region *r = ADR(I, j);
+        double m = 0.0;
+        for (int a = 0; a < nm; ++a) m += r->mu[a];
+        c->muX[XI(c, I, j)] = r->sgn * m;
+      }
+    for (int j = -G; j < ny + G; ++j)
+      for (int I = -G; I <= nx + G; ++I) {
+        int rI = mn(I, nx), rj = mc(j, ny);
+        if (rI == I && rj == j) continue;
+        c->muX[XI(c, I, j)] = (rI != I ? -1.0 : 1.0) * c->muX[XI(c, rI, rj)];
+      }
+  } else {
+    for (int p = 0; p < nyf(c); ++p) c->muY[p] = 0.0;
+    for (int J = 0; J <= ny; ++J)
+      for (int i = 0; i < nx; ++i) {
+        region *r = ADR(i, J);
+        double m = 0.0;
+        for (int a = 0; a < nm; ++a) m += r->mu[a];
+        c->muY[YI(c, i, J)] = r->sgn * m;
+      }
+    for (int J = -G; J <= ny + G; ++J)
+      for (int i = -G; i < nx + G; ++i) {
+        int ri = mc(i, nx), rJ = mn(J, ny);
+        if (ri == i && rJ == J) continue;
+        c->muY[YI(c, i, J)] = (rJ != J ? -1.0 : 1.0) * c->muY[YI(c, ri, rJ)];
+      }
+  }
+  free(reg);
+#undef AD_CELL_REGIONS
+#undef ADR
+
+  /* §2.1.1 dual mesh: nodal momentum through the two dual faces along dir,
+   * each carrying 1/4 of the four same-side primal face mass fluxes; the
+   * velocity reconstructed as on the primal mesh (dual centres at the
+   * Lagrangian node positions, reading) */
+  if (!c->o.kinematic) {
+    int order = c->o.recon_order;
+    int nf = dir == 0 ? (nx + 2) * (ny + 1) : (nx + 1) * (ny + 2);
+    double *fm = dalloc(nf), *fu = dalloc(nf), *fv = dalloc(nf);
+    double *nu = dalloc((size_t)(nx + 1) * (ny + 1)), *nv = dalloc((size_t)(nx + 1) * (ny + 1));
+    if (!fm || !fu || !fv || !nu || !nv) {
+      free(fm); free(fu); free(fv); free(nu); free(nv);
+      return fail(c, LR_REF_ENOMEM, "out of memory");
+    }
+    if (dir == 0) {
+      /* dual x-face (I,J) between nodes (I-1,J) and (I,J), I in [0,nx+1] */
+      for (int J = 0; J <= ny; ++J)
+        for (int I = 0; I <= nx + 1; ++I) {
+          double phi = 0.25 * (c->muX[XI(c, I - 1, J - 1)] + c->muX[XI(c, I, J - 1)] +
+                               c->muX[XI(c, I - 1, J)] + c->muX[XI(c, I, J)]);
+          int D = phi > 0.0 ? I - 1 : I;
+          double sg = phi > 0.0 ? 1.0 : -1.0;
+          int pD = NI(c, D, J);
+          double vu = c->ux[pD], vv = c->uy[pD];
+          if (order == 2) {
+            double df = 0.5 * (c->dpx[NI(c, I - 1, J)] + c->dpx[NI(c, I, J)]);
+            double off = 0.5 * (sg * dual_wx(c, D, J) - df);
+            vu += dual_slope(c, c->ux, D, J, 1, 0, 1.0, 0.0) * off;
+            vv += dual_slope(c, c->uy, D, J, 1, 0, 1.0, 0.0) * off;
+          }
+          int h = J * (nx + 2) + I;
+          fm[h] = phi; fu[h] = phi * vu; fv[h] = phi * vv;
+        }
+    } else {
+      /* dual y-face (I,J) between nodes (I,J-1) and (I,J), J in [0,ny+1] */
+      for (int J = 0; J <= ny + 1; ++J)
+        for (int I = 0; I <= nx; ++I) {
+          double phi = 0.25 * (c->muY[YI(c, I - 1, J - 1)] + c->muY[YI(c, I, J - 1)] +
+                               c->muY[YI(c, I - 1, J)] + c->muY[YI(c, I, J)]);
+          int D = phi > 0.0 ? J - 1 : J;
+          double sg = phi > 0.0 ? 1.0 : -1.0;
+          int pD = NI(c, I, D);
+          double vu = c->ux[pD], vv = c->uy[pD];
+          if (order == 2) {
+            double df = 0.5 * (c->dpy[NI(c, I, J - 1)] + c->dpy[NI(c, I, J)]);
+            double off = 0.5 * (sg * dual_wy(c, I, D) - df);
+            vu += dual_slope(c, c->ux, I, D, 0, 1, 0.0, 1.0) * off;
+            vv += dual_slope(c, c->uy, I, D, 0, 1, 0.0, 1.0) * off;
+          }
+          int h = J * (nx + 1) + I;
+          fm[h] = phi; fu[h] = phi * vu; fv[h] = phi * vv;
+        }
+    }
+    /* m_p^{proj} u^{proj} = m_p u + in - out through the low then high face */
+    for (int J = 0; J <= ny; ++J)
+      for (int I = 0; I <= nx; ++I) {
+        int p = NI(c, I, J);
+        int lo = dir == 0 ? J * (nx + 2) + I : J * (nx + 1) + I;
+        int hi = dir == 0 ? lo + 1 : lo + (nx + 1);
+        double m = c->mp[p];
+        double mu = c->mp[p] * c->ux[p], mv = c->mp[p] * c->uy[p];
+        m += fm[lo]; mu += fu[lo]; mv += fv[lo];
+        m -= fm[hi]; mu -= fu[hi]; mv -= fv[hi];
+        if (!(m > 0.0)) rc = fail(c, LR_REF_ENEGATIVE, "nodal mass <= 0 after a pass");
+        nu[J * (nx + 1) + I] = mu / m;
+        nv[J * (nx + 1) + I] = mv / m;
+      }
+    for (int J = 0; J <= ny; ++J)
+      for (int I = 0; I <= nx; ++I) {
+        c->ux[NI(c, I, J)] = nu[J * (nx + 1) + I];
+        c->uy[NI(c, I, J)] = nv[J * (nx + 1) + I];
+      }
+    wall_nodes(c, c->ux, c->uy);
+    free(fm); free(fu); free(fv); free(nu); free(nv);
+  }
+  return rc;
+}
+
+/* the whole AD remap: X then Y on the first, third, ... step of a run and Y
+ * then X on the others (§2.1.2 remark 3) */
+static int remap_ad(lr_ref_ctx *c) {
+  int N = nnode(c);
+  /* the passes carry the nodal velocity from u^lag on */
+  for (int p = 0; p < N; ++p) { c->ux[p] = c->uLx[p]; c->uy[p] = c->uLy[p]; }
+  int xfirst = (c->step % 2) == 0;
+  int rc1 = ad_pass(c, xfirst ? 0 : 1, 1);
+  if (rc1 == LR_REF_ENOMEM) return rc1;
+  int rc2 = ad_pass(c, xfirst ? 1 : 0, 0);
+  if (rc2 == LR_REF_ENOMEM) return rc2;
+  return rc2 != LR_REF_OK ? rc2 : rc1;
+}
+
+/* ------------------------------------------------------------------------ */
+static int step_once(lr_ref_ctx *c, double t_end, double *dt_out, int *last) {
+  int C = ncell(c), N = nnode(c), nm = c->nmat, nx = c->nx, ny = c->ny;
+  *last = 0;
+  memset(c->flags, 0, (size_t)C * sizeof(int));
+  for (int a = 0; a < nm; ++a) {
+    ghost_cells(c, c->V + a * C);
+    ghost_cells(c, c->M + a * C);
+    ghost_cells(c, c->E + a * C);
+  }
+  ghost_nodes_vec(c, c->ux, c->uy);
+  derived(c);
+
+  /* time step */
+  double dt = c->o.fixed_dt > 0.0 ? c->o.fixed_dt : cfl_dt(c);
+  if (t_end - c->t <= dt) { dt = t_end - c->t; *last = 1; }
+  if (!(dt > 0.0) || !isfinite(dt)) return fail(c, LR_REF_EDT, "time step underflow or not finite");
+  c->last_dt = dt;
+
+  /* Lagrangian phase */
+  if (c->o.kinematic) {
+    for (int q = 0; q < C; ++q) c->Q[q] = 0.0;
+    nodal_mass(c);
+    kinematic_lagrange(c, dt);
+  } else {
+    pseudo_viscosity(c);
+    nodal_mass(c);
+    predictor(c, dt);
+    corrector(c, dt);
+  }
+  for (int p = 0; p < N; ++p) { c->xLx[p] = 0; c->xLy[p] = 0; }
+  for (int J = 0; J <= ny; ++J)
+    for (int I = 0; I <= nx; ++I) {
+      int p = NI(c, I, J);
+      c->xLx[p] = node_x(c, I) + c->dpx[p];
+      c->xLy[p] = node_y(c, J) + c->dpy[p];
+    }
+  ghost_nodes_vec(c, c->dpx, c->dpy);
+  ghost_nodes_vec(c, c->uhx, c->uhy);
+  ghost_nodes_vec(c, c->uLx, c->uLy);
+  ghost_nodes_pos(c, c->xLx, c->xLy);
+  ghost_nodes_scalar(c, c->mp);
+
+  int rc = c->o.remap == LR_REF_REMAP_AD ? remap_ad(c) : remap_directcf(c);
+  if (rc == LR_REF_ENOMEM) return rc;
+
   /* finish */
   c->t = *last ? t_end : c->t + dt;
   c->step += 1;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i)
+      for (int b = 0; b < LR_REF_NCOUNT; ++b)
+        if (c->flags[CI(c, i, j)] & (1 << b)) c->counts[b] += 1;
   *dt_out = dt;
   /* a partial quantity below -1e-10 of the cell's total counts as negative;
    * smaller negatives are the rounding left by a material that moved out */
@@ -1309,7 +1691,7 @@ int lr_ref_get_fields(lr_ref_ctx *c, unsigned mask, double *const *out) {
           double V = c->V[qa], M = c->M[qa], E = c->E[qa];
           int pr = present(c, V);
           double rho = pr ? M / V : 0.0, e = (pr && M > 0) ? E / M : 0.0;
-          double P = pr ? (c->eos[a].gamma - 1.0) * rho * e : 0.0;
+          double P = pr ? eos_p(c, a, rho, e) : 0.0;
           Ms += M; Es += E; Ps += (V / c->A) * P;
           switch (bit) {
             case LR_REF_F_K: o[a * cells + h] = V / c->A; break;
@@ -1429,6 +1811,10 @@ int lr_ref_debug_get(lr_ref_ctx *c, const char *name, double *out) {
     return LR_REF_OK;
   }
   if (!strcmp(name, "dt")) { out[0] = c->last_dt; return LR_REF_OK; }
+  if (!strcmp(name, "counts")) {
+    for (int b = 0; b < LR_REF_NCOUNT; ++b) out[b] = (double)c->counts[b];
+    return LR_REF_OK;
+  }
   if (!strcmp(name, "t")) { out[0] = c->t; return LR_REF_OK; }
   return fail(c, LR_REF_EINVAL, "unknown stage name");
 }

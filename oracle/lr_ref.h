@@ -21,7 +21,15 @@ extern "C" {
 #endif
 
 #define LR_REF_MAXMAT 4
+/* branch counters returned by lr_ref_debug_get(c, "counts", out[LR_REF_NCOUNT]):
+ * cells, summed over the steps since set_state, that were mixed, had three or
+ * more materials, had a degenerate Youngs normal, had a material's outflow
+ * clipped, or fell back to order 1 under the positivity guard */
+#define LR_REF_NCOUNT 5
 
+/* equation of state of one material: p = (gamma - 1) rho e - pinf, the
+ * perfect gas of §5.1 for pinf = 0 and the stiffened gas of §5.2 (the paper's
+ * pi) for pinf > 0; gamma > 1, pinf >= 0 */
 typedef struct { double gamma, pinf; } lr_ref_eos;
 
 typedef struct {
@@ -33,7 +41,12 @@ typedef struct {
   int kinematic;          /* 1 = prescribed node velocities, no forces           */
   double k_eps;           /* material-presence threshold on V/A (default 1e-10)  */
   double fixed_dt;        /* > 0: use this time step instead of the CFL one      */
+  int remap;              /* LR_REF_REMAP_DIRECTCF (default) or LR_REF_REMAP_AD  */
 } lr_ref_opts;
+
+/* remap of the time step: the one-step DirectCF remap (§2.3), or the
+ * alternate-direction comparator (§2.1.1-§2.1.2, §4.2) */
+enum { LR_REF_REMAP_DIRECTCF = 0, LR_REF_REMAP_AD = 1 };
 
 enum { LR_REF_OK = 0, LR_REF_EINVAL = -1, LR_REF_ENOMEM = -2, LR_REF_EDEVICE = -3,
        LR_REF_ENEGATIVE = -4, LR_REF_ENAN = -5, LR_REF_EDT = -6, LR_REF_EAGAIN = -7,
@@ -58,7 +71,7 @@ int lr_ref_get_fields(lr_ref_ctx *c, unsigned mask, double *const *out);
 /* out[3*nmat+3]: sum V_a, sum M_a, sum E_a (per material), sum w m_p u_x,
  * sum w m_p u_y, total energy; w = 1 inside, 1/2 on walls, 1/4 at corners */
 int lr_ref_totals(lr_ref_ctx *c, double *out);
-/* stage arrays of the last step (names listed in lr_ref.c) */
+/* stage arrays of the last step (names listed in lr_ref.c), and "counts" */
 int lr_ref_debug_get(lr_ref_ctx *c, const char *name, double *out);
 const char *lr_ref_last_error(const lr_ref_ctx *c);
 void lr_ref_destroy(lr_ref_ctx *c);

@@ -5,7 +5,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB = None
+_LIBS = {}
+REMAP_DIRECTCF, REMAP_AD = 0, 1
+COUNT_NAMES = ("mixed", "three_or_more", "degenerate_normal", "clipped", "guard")
 
 F_RHO, F_P, F_E, F_K, F_RHOA, F_EA, F_PA, F_UX, F_UY, F_VOL, F_MASS, F_IE = (
     1 << i for i in range(12))
@@ -23,17 +25,19 @@ class Opts(C.Structure):
     _fields_ = [("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double),
                 ("y1", C.c_double), ("cfl", C.c_double), ("a1", C.c_double),
                 ("a2", C.c_double), ("precision", C.c_int), ("recon_order", C.c_int),
-                ("kinematic", C.c_int), ("k_eps", C.c_double), ("fixed_dt", C.c_double)]
+                ("kinematic", C.c_int), ("k_eps", C.c_double), ("fixed_dt", C.c_double),
+                ("remap", C.c_int)]
 
 
-def load():
-    """Load (building first if absent) the oracle library."""
-    global _LIB
-    if _LIB is not None:
-        return _LIB
+def load(omp=False):
+    """Load (building first if absent) the oracle library: the single-threaded
+    build, or with omp=True the OpenMP build (same bits)."""
+    if omp in _LIBS:
+        return _LIBS[omp]
     # LR_REF_SO lets the mutation test point the suite at a deliberately
     # broken copy of the oracle
-    so = os.environ.get("LR_REF_SO") or os.path.join(_HERE, "liblr_ref.so")
+    so = os.environ.get("LR_REF_SO") or os.path.join(
+        _HERE, "liblr_ref_omp.so" if omp else "liblr_ref.so")
     if not os.path.exists(so):
         from .build import build
         build()
@@ -60,7 +64,7 @@ def load():
     for name in ("lr_ref_create", "lr_ref_set_state", "lr_ref_step", "lr_ref_run",
                  "lr_ref_get_fields", "lr_ref_totals", "lr_ref_debug_get"):
         getattr(lib, name).restype = C.c_int
-    _LIB = lib
+    _LIBS[omp] = lib
     return lib
 
 
@@ -86,16 +90,19 @@ class RefSolver:
     """One problem on the oracle; mirrors the GPU binding's ``Solver``."""
 
     def __init__(self, nx, ny, gammas, domain=(0.0, 1.0, 0.0, 1.0), cfl=0.5, a1=0.5,
-                 a2=1.0, recon_order=2, kinematic=False, k_eps=1e-10, fixed_dt=0.0):
-        self.lib = load()
+                 a2=1.0, recon_order=2, kinematic=False, k_eps=1e-10, fixed_dt=0.0,
+                 pinfs=None, remap=REMAP_DIRECTCF, omp=False):
+        self.lib = load(omp)
         self.nx, self.ny, self.nmat = int(nx), int(ny), len(gammas)
-        eos = (Eos * self.nmat)(*[Eos(float(g), 0.0) for g in gammas])
+        pinfs = [0.0] * self.nmat if pinfs is None else list(pinfs)
+        eos = (Eos * self.nmat)(*[Eos(float(g), float(pi)) for g, pi in zip(gammas, pinfs)])
         o = Opts()
         self.lib.lr_ref_default_opts(C.byref(o))
         o.x0, o.x1, o.y0, o.y1 = map(float, domain)
         o.cfl, o.a1, o.a2 = float(cfl), float(a1), float(a2)
         o.recon_order, o.kinematic = int(recon_order), int(bool(kinematic))
         o.k_eps, o.fixed_dt = float(k_eps), float(fixed_dt)
+        o.remap = int(remap)
         bc = (C.c_int * 4)(0, 0, 0, 0)
         h = C.c_void_p()
         rc = self.lib.lr_ref_create(self.nx, self.ny, self.nmat, eos, bc, C.byref(o), C.byref(h))
@@ -159,6 +166,13 @@ class RefSolver:
         out = np.zeros(3 * self.nmat + 3)
         self._check(self.lib.lr_ref_totals(self.h, _dptr(out)))
         return out
+
+    def counts(self):
+        """Cells (summed over the steps since set_state) that took each branch:
+        mixed, three or more materials, degenerate normal, clipped, guard."""
+        out = np.zeros(len(COUNT_NAMES))
+        self._check(self.lib.lr_ref_debug_get(self.h, b"counts", _dptr(out)))
+        return dict(zip(COUNT_NAMES, out.astype(np.int64).tolist()))
 
     def stage(self, name):
         nx, ny, nm = self.nx, self.ny, self.nmat

@@ -15,8 +15,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "lr_ref.c")
 
 MUTATIONS = {
-    "volcf_sign": ("if (is_donor(rs[s], i, j)) v += rs[s]->vol;",
-                   "if (is_donor(rs[s], i, j)) v -= rs[s]->vol;"),
+    "volcf_sign": ("for (int s = 0; s < 8; ++s) {\n        if (is_donor(rs[s], i, j)) v += rs[s]->vol;",
+                   "for (int s = 0; s < 8; ++s) {\n        if (is_donor(rs[s], i, j)) v -= rs[s]->vol;"),
     "face_offset_drops_velocity": ("return aD + 0.5 * d * (r->sgn * c->dxL[q] - uf);",
                                    "return aD + 0.5 * d * (r->sgn * c->dxL[q]);"),
     "anti_corner_offset_sign": ("(-sx * c->dyL[q] - c->dpy[p]) * vy;",
@@ -46,12 +46,34 @@ MUTATIONS = {
     "nodal_mass_half": ("c->mp[NI(c, I, J)] = 0.25 *", "c->mp[NI(c, I, J)] = 0.5 *"),
     "viscosity_in_expansion": ("if (div < 0.0 && !c->o.kinematic)",
                                "if (div > 0.0 && !c->o.kinematic)"),
-    "dual_face_offset_sign": ("double off = 0.5 * (sg * dual_wx(c, D, J) - df);",
-                              "double off = 0.5 * (sg * dual_wx(c, D, J) + df);"),
+    "dual_face_offset_sign": (
+        "double off = 0.5 * (sg * dual_wx(c, D, J) - df);\n          vu += dual_slope(c, c->uLx,",
+        "double off = 0.5 * (sg * dual_wx(c, D, J) + df);\n          vu += dual_slope(c, c->uLx,"),
     "dual_face_slope_dropped": ("vu += dual_slope(c, c->uLx, D, J, 1, 0, 1.0, 0.0) * off;",
                                 "vu += 0.0 * off;"),
     "mixture_pressure_unweighted": ("Pch += c->k[qa] * P_h;", "Pch += P_h;"),
     "no_clipping": ("  if (!any_over) return;", "  return;"),
+    "cfl_without_velocity": ("double cand = fmin(c->dx / (cs + Ux), c->dy / (cs + Uy));",
+                             "double cand = fmin(c->dx / cs, c->dy / cs);"),
+    "sound_speed_without_gamma": ("return k * c->eos[a].gamma * P + k * c->eos[a].pinf;",
+                                  "return k * P + k * c->eos[a].pinf;"),
+    "viscosity_without_linear_term": (
+        "q = c->rhoc[cq] * (c->o.a1 * L * c->cc[cq] * fabs(div) + c->o.a2 * L * L * div * div);",
+        "q = c->rhoc[cq] * (c->o.a2 * L * L * div * div);"),
+    "no_positivity_guard": (
+        "if (!(Mout[a] > c->M[qa] || Eout[a] > c->M[qa] * c->eL[qa])) break;", "break;"),
+    "no_gradient_threshold": ("double gmin = 1e-10 / fmin(c->dx, c->dy);", "double gmin = 0.0;"),
+    "stiffened_gas_sign": ("return (c->eos[a].gamma - 1.0) * rho * e - c->eos[a].pinf;",
+                           "return (c->eos[a].gamma - 1.0) * rho * e + c->eos[a].pinf;"),
+    "stiffened_sound_speed_dropped": ("return k * c->eos[a].gamma * P + k * c->eos[a].pinf;",
+                                      "return k * c->eos[a].gamma * P;"),
+    "ad_without_alternation": ("int xfirst = (c->step % 2) == 0;", "int xfirst = 1;"),
+    "ad_second_pass_keeps_old_fractions": ("        c->k[qa] = c->V[qa] / c->A;\n        if (!first)",
+                                           "        if (first) c->k[qa] = c->V[qa] / c->A;\n        if (!first)"),
+    "ad_volume_sign": ("for (int s = 0; s < 2; ++s) {\n        if (is_donor(rs[s], i, j)) v += rs[s]->vol;",
+                       "for (int s = 0; s < 2; ++s) {\n        if (is_donor(rs[s], i, j)) v -= rs[s]->vol;"),
+    "ad_face_width_one_node": ("double w = 0.5 * (c->dpx[NI(c, I, j)] + c->dpx[NI(c, I, j + 1)]);",
+                               "double w = c->dpx[NI(c, I, j)];"),
     "order2_next_to_interfaces": (
         "return m >= 0 && c->pure[CI(c, i - si, j - sj)] == m && c->pure[CI(c, i + si, j + sj)] == m;",
         "return m >= 0;"),
