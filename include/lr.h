@@ -221,6 +221,39 @@ int lr_batch_schedule(lr_batch *b, int *persistent, int *use_graph, double *rate
 const char *lr_batch_last_error(const lr_batch *b);
 void lr_batch_destroy(lr_batch *b);
 
+/* ------------------------------------------------------- allocation-free
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): lr_create,
+ * lr_set_state_device (FP64 inputs), lr_run and the copy of lr_get_fields in
+ * one call that allocates nothing.  Every device array of the problem (state,
+ * intermediates, control record, block maps) is carved from a static
+ * workspace of LR_NOALLOC_BYTES bytes, one per device, which the library
+ * holds from the first call on that device until the process ends.  The
+ * caller passes the inputs and outputs:
+ *   nx, ny, nmat, eos, bc, opts: as lr_create (opts.stages must be 0);
+ *   t0, t_end, max_steps: the state is at t0; the run stops at t_end or after
+ *     max_steps steps, as lr_run;
+ *   k, rho, e [nmat][ny][nx], ux, uy [ny+1][nx+1]: DEVICE FP64 arrays, the
+ *     initial state with the checks of lr_set_state (run on the device);
+ *   field_mask, out: out[0..popcount(mask)-1] are DEVICE FP64 arrays of the
+ *     shapes of lr_get_fields, written in increasing bit order;
+ *   hip_stream: the hipStream_t to run on (NULL: the null stream);
+ *   steps_out, t_out (may be NULL): steps taken and time reached;
+ *   errbuf[errlen] (may be NULL): the failure text.
+ * A problem whose arrays do not fit in the workspace (about 460 bytes per
+ * cell for FP64 with 3 materials, so up to about 140,000 cells) is LR_ENOMEM,
+ * with the sizes in errbuf.  Every call on a device shares that device's
+ * workspace, and the workspace keeps the last call's contents: calls that
+ * overlap on one device (other host threads, other streams) race, so callers
+ * serialize them.  Synchronizes the stream. */
+#define LR_NOALLOC_BYTES ((size_t)64 << 20)
+int lr_run_noalloc(int nx, int ny, int nmat, const lr_eos *eos, const int bc[4],
+                   const lr_opts *opts, double t0, double t_end, long max_steps,
+                   const double *k, const double *rho, const double *e,
+                   const double *ux, const double *uy, unsigned field_mask,
+                   double *const *out, void *hip_stream, long *steps_out,
+                   double *t_out, char *errbuf, size_t errlen);
+
 /* Text of the last failure on this context; valid until the next call. */
 const char *lr_last_error(const lr_ctx *c);
 

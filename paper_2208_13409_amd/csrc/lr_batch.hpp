@@ -100,8 +100,8 @@ struct lr_batch {
   double *dstage = nullptr;
   size_t stage_bytes = 0;
   hipEvent_t stage_ev = nullptr;
-  double *scratch = nullptr;  // outputs
-  size_t scratch_n = 0;
+  double *outbuf = nullptr;  // outputs
+  size_t outbuf_n = 0;
   hipGraphExec_t gexec = nullptr;
   bool graph_ok = false;
   // schedule autotuning: the first chunks run under each candidate schedule
@@ -153,15 +153,15 @@ int grow_stage(lr_batch *b, size_t bytes) {
   return LR_OK;
 }
 
-int grow_scratch(lr_batch *b, size_t n) {
-  if (n <= b->scratch_n) return LR_OK;
+int grow_outbuf(lr_batch *b, size_t n) {
+  if (n <= b->outbuf_n) return LR_OK;
   HIP_B(b, hipStreamSynchronize(b->stream));
-  if (b->scratch) (void)hipFree(b->scratch);
-  b->scratch = nullptr;
-  b->scratch_n = 0;
-  if (hipMalloc((void **)&b->scratch, n * sizeof(double)) != hipSuccess)
-    return bset(b, LR_ENOMEM, "output scratch");
-  b->scratch_n = n;
+  if (b->outbuf) (void)hipFree(b->outbuf);
+  b->outbuf = nullptr;
+  b->outbuf_n = 0;
+  if (hipMalloc((void **)&b->outbuf, n * sizeof(double)) != hipSuccess)
+    return bset(b, LR_ENOMEM, "output staging");
+  b->outbuf_n = n;
   return LR_OK;
 }
 
@@ -317,7 +317,7 @@ void lr_batch_destroy(lr_batch *b) {
   for (hipEvent_t e : b->tune_ev)
     if (e) (void)hipEventDestroy(e);
   for (void *p : {(void *)b->pool, b->dprobs, (void *)b->ctl, (void *)b->node_map,
-                  (void *)b->cell_map, (void *)b->dstage, (void *)b->scratch, (void *)b->plist})
+                  (void *)b->cell_map, (void *)b->dstage, (void *)b->outbuf, (void *)b->plist})
     if (p) (void)hipFree(p);
   if (b->hctl) (void)hipHostFree(b->hctl);
   if (b->hstage) (void)hipHostFree(b->hstage);
@@ -558,11 +558,11 @@ int lr_batch_get_fields(lr_batch *b, long id, unsigned mask, double *const *out)
   int rc = find_req(b, id, &q);
   if (rc) return rc;
   const Grid &g = q->g;
-  rc = grow_scratch(b, std::max((size_t)g.nmat * g.nx * g.ny, (size_t)(g.nx + 1) * (g.ny + 1)));
+  rc = grow_outbuf(b, std::max((size_t)g.nmat * g.nx * g.ny, (size_t)(g.nx + 1) * (g.ny + 1)));
   if (rc) return rc;
   const int buf = cur_slot(b->hctl[b->where[id]]);
-  return bfp32(b) ? fields_out<float>(q->pf, buf, mask, out, b->scratch, b->stream, b->err)
-                  : fields_out<double>(q->pd, buf, mask, out, b->scratch, b->stream, b->err);
+  return bfp32(b) ? fields_out<float>(q->pf, buf, mask, out, b->outbuf, b->stream, b->err)
+                  : fields_out<double>(q->pd, buf, mask, out, b->outbuf, b->stream, b->err);
 }
 
 int lr_batch_totals(lr_batch *b, long id, double *out) {

@@ -207,10 +207,10 @@ void launch_init(const Prob<R> &P, const double *dk, hipStream_t s) {
   k_dt_bound<R><<<nb, 256, 0, s>>>(P, 0);
 }
 
-// fields of the state in buffer `buf` into host arrays, through `scratch`
+// fields of the state in buffer `buf` into host arrays, through `stage`
 // (device, at least max(nmat*C, N) doubles)
 template <typename R>
-int fields_out(const Prob<R> &P, int buf, unsigned mask, double *const *out, double *scratch,
+int fields_out(const Prob<R> &P, int buf, unsigned mask, double *const *out, double *stage,
                hipStream_t s, std::string &err) {
   const Grid &g = P.g;
   const size_t C = (size_t)g.nx * g.ny, N = (size_t)(g.nx + 1) * (g.ny + 1);
@@ -226,9 +226,9 @@ int fields_out(const Prob<R> &P, int buf, unsigned mask, double *const *out, dou
     const bool per = bit == LR_F_K || bit == LR_F_RHOA || bit == LR_F_EA || bit == LR_F_PA ||
                      bit == LR_F_VOL || bit == LR_F_MASS || bit == LR_F_IE;
     const size_t n = node ? N : (per ? g.nmat * C : C);
-    k_fields<R><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(P, buf, bit, scratch);
+    k_fields<R><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(P, buf, bit, stage);
     HIP_TRY(err, hipGetLastError());
-    HIP_TRY(err, hipMemcpyAsync(o, scratch, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(err, hipMemcpyAsync(o, stage, n * sizeof(double), hipMemcpyDeviceToHost, s));
   }
   HIP_TRY(err, hipStreamSynchronize(s));
   return LR_OK;
@@ -273,7 +273,7 @@ struct lr_ctx {
   std::vector<void *> allocs;
   bool have_state = false;
   std::string err;
-  double *scratch = nullptr;  // staging for outputs
+  double *outbuf = nullptr;  // staging for outputs
   // kernel timing (lr_profile): a start/stop event pair per kernel of each
   // step of one chunk
   bool prof = false;
@@ -515,7 +515,7 @@ int lr_create(int nx, int ny, int nmat, const lr_eos *eos, const int bc[4], cons
   if (rc == LR_OK) rc = fp32(c) ? alloc_prob<float>(c, c->pf) : alloc_prob<double>(c, c->pd);
   if (rc == LR_OK) rc = build_maps(c);
   const size_t N = (size_t)(nx + 1) * (ny + 1), C = (size_t)nx * ny;
-  if (rc == LR_OK) rc = dalloc(c, &c->scratch, std::max((size_t)nmat * C, N));
+  if (rc == LR_OK) rc = dalloc(c, &c->outbuf, std::max((size_t)nmat * C, N));
   if (rc == LR_OK && hipStreamSynchronize(c->own) != hipSuccess) rc = LR_EDEVICE;
   if (rc != LR_OK) {
     lr_destroy(c);
@@ -589,7 +589,8 @@ int lr_set_state_device(lr_ctx *c, double t, const void *k, const void *rho, con
   if (hipGetLastError() != hipSuccess || hipMemsetAsync(bits, 0, sizeof(int), s) != hipSuccess) {
     rc = set_err(c, LR_EDEVICE, "staging copy failed");
   } else {
-    k_check_state<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(nm, (int)C, (int)N, dk, bits);
+    k_check_state<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(
+        nm, (int)C, (int)N, dk, dk + nm * C, dk + 2 * nm * C, dk + 3 * nm * C, dk + 3 * nm * C + N, bits);
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(&hbits, bits, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
@@ -638,8 +639,8 @@ int lr_get_fields(lr_ctx *c, unsigned mask, double *const *out) {
   int rc = read_ctl(c);
   if (rc) return rc;
   const int buf = cur_slot(*c->hctl);
-  return fp32(c) ? fields_out<float>(c->pf, buf, mask, out, c->scratch, c->stream, c->err)
-                 : fields_out<double>(c->pd, buf, mask, out, c->scratch, c->stream, c->err);
+  return fp32(c) ? fields_out<float>(c->pf, buf, mask, out, c->outbuf, c->stream, c->err)
+                 : fields_out<double>(c->pd, buf, mask, out, c->outbuf, c->stream, c->err);
 }
 
 int lr_totals(lr_ctx *c, double *out) {

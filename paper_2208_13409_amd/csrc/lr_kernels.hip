@@ -1791,17 +1791,17 @@ __global__ void k_to_f64(const T *src, double *dst, long long n) {
   if (i < n) dst[i] = double(src[i]);
 }
 
-// the checks of a host-given state, on a staged one: [k | rho | e] per
-// material, then ux, uy; bits: 1 non-finite, 2 fractions outside [0,1] or
-// not summing to 1, 4 rho <= 0 or e < 0 where k > 0
-__global__ void k_check_state(int nmat, int C, int N, const double *dk, int *bits) {
+// the checks of a host-given state, on device arrays k, rho, e [nmat][C]
+// and ux, uy [N]; bits: 1 non-finite, 2 fractions outside [0,1] or not
+// summing to 1, 4 rho <= 0 or e < 0 where k > 0
+__global__ void k_check_state(int nmat, int C, int N, const double *kk, const double *rr,
+                              const double *ee, const double *ux, const double *uy, int *bits) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   int b = 0;
   if (i < C) {
     double ks = 0.0;
     for (int a = 0; a < nmat; ++a) {
-      const double k = dk[(size_t)a * C + i], rho = dk[(size_t)(nmat + a) * C + i],
-                   e = dk[(size_t)(2 * nmat + a) * C + i];
+      const double k = kk[(size_t)a * C + i], rho = rr[(size_t)a * C + i], e = ee[(size_t)a * C + i];
       if (!isfinite(k) || !isfinite(rho) || !isfinite(e)) b |= 1;
       if (k < 0.0 || k > 1.0) b |= 2;
       if (k > 0.0 && (!(rho > 0.0) || e < 0.0)) b |= 4;
@@ -1809,10 +1809,7 @@ __global__ void k_check_state(int nmat, int C, int N, const double *dk, int *bit
     }
     if (!(fabs(ks - 1.0) <= 1e-12)) b |= 2;
   }
-  if (i < N) {
-    const double *u = dk + (size_t)3 * nmat * C;
-    if (!isfinite(u[i]) || !isfinite(u[N + i])) b |= 1;
-  }
+  if (i < N && (!isfinite(ux[i]) || !isfinite(uy[i]))) b |= 1;
   if (b) atomicOr(bits, b);
 }
 
@@ -2059,3 +2056,4 @@ StepFn step_fn(int nmat) {
 
 #include "lr_host.hpp"
 #include "lr_batch.hpp"
+#include "lr_noalloc.hpp"

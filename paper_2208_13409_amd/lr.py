@@ -31,7 +31,7 @@ EXPORTS = ("lr_default_opts", "lr_create", "lr_bind_stream", "lr_set_state", "lr
            "lr_batch_submit", "lr_batch_step", "lr_batch_step_begin", "lr_batch_step_end",
            "lr_batch_poll", "lr_batch_status",
            "lr_batch_get_fields", "lr_batch_totals", "lr_batch_release", "lr_batch_running",
-           "lr_batch_schedule", "lr_batch_last_error", "lr_batch_destroy")
+           "lr_batch_schedule", "lr_batch_last_error", "lr_batch_destroy", "lr_run_noalloc")
 LR_F64_IN, LR_F32_IN = 0, 1  # element types of lr_set_state_device
 
 
@@ -122,6 +122,10 @@ def load():
     lib.lr_batch_last_error.restype = C.c_char_p
     lib.lr_batch_destroy.argtypes = [vp]
     lib.lr_batch_destroy.restype = None
+    lib.lr_run_noalloc.argtypes = [C.c_int, C.c_int, C.c_int, P(lr_eos), P(C.c_int), P(lr_opts),
+                                   C.c_double, C.c_double, C.c_long, vp, vp, vp, vp, vp, C.c_uint,
+                                   P(vp), vp, P(C.c_long), dp, C.c_char_p, C.c_size_t]
+    lib.lr_run_noalloc.restype = C.c_int
     for n in ("lr_create", "lr_bind_stream", "lr_set_state", "lr_set_state_device", "lr_step",
               "lr_run", "lr_get_fields", "lr_totals", "lr_debug_get", "lr_profile",
               "lr_profile_read", "lr_kernel_count", "lr_batch_create", "lr_batch_bind_stream",
@@ -268,6 +272,40 @@ def _fields(fn, h, nx, ny, nmat, check, names, *lead):
     ptrs = (C.POINTER(C.c_double) * len(outs))(*[_dptr(b) for b in outs])
     check(fn(h, *lead, mask, ptrs))
     return {n_: bufs[FIELD_BITS[n_]] for n_ in names}
+
+
+def run_noalloc(nx, ny, gammas, domain, t_end, k, rho, e, ux, uy, names, outs, t0=0.0,
+                max_steps=1 << 40, cfl=0.5, a1=0.5, a2=1.0, recon_order=2, kinematic=False,
+                k_eps=1e-10, fixed_dt=0.0, precision=LR_FP64, stream=None):
+    """lr_run_noalloc: inputs k, rho, e, ux, uy and outputs outs[name] are
+    contiguous float64 device tensors (torch); names are field names in any
+    order (written in the library's bit order).  Returns (steps, t)."""
+    lib = load()
+    o = lr_default_opts()
+    o.x0, o.x1, o.y0, o.y1 = map(float, domain)
+    o.cfl, o.a1, o.a2 = float(cfl), float(a1), float(a2)
+    o.recon_order, o.kinematic = int(recon_order), int(bool(kinematic))
+    o.k_eps, o.fixed_dt, o.precision = float(k_eps), float(fixed_dt), int(precision)
+    eos = (lr_eos * len(gammas))(*[lr_eos(float(g), 0.0) for g in gammas])
+    ins = (k, rho, e, ux, uy)
+    for x in ins + tuple(outs[n_] for n_ in names):
+        if not (x.is_cuda and x.is_contiguous() and str(x.dtype) == "torch.float64"):
+            raise ValueError("contiguous float64 device tensors expected")
+    mask = 0
+    for n_ in names:
+        mask |= FIELD_BITS[n_]
+    order = sorted(names, key=lambda n_: FIELD_BITS[n_])
+    ptrs = (C.c_void_p * max(len(order), 1))(*[outs[n_].data_ptr() for n_ in order])
+    handle = getattr(stream, "cuda_stream", stream) if stream is not None else None
+    steps, t = C.c_long(), C.c_double()
+    err = C.create_string_buffer(256)
+    rc = lib.lr_run_noalloc(int(nx), int(ny), len(gammas), eos, (C.c_int * 4)(0, 0, 0, 0), C.byref(o),
+                            float(t0), float(t_end), int(max_steps),
+                            *[C.c_void_p(x.data_ptr()) for x in ins], mask, ptrs, C.c_void_p(handle),
+                            C.byref(steps), C.byref(t), err, len(err))
+    if rc != LR_OK:
+        raise LRError(rc, err.value.decode())
+    return steps.value, t.value
 
 
 def lr_batch_default_opts():

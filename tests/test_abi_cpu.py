@@ -40,7 +40,7 @@ def test_oracle_exports_the_same_calls():
     lib = load()
     for n in _declared("include/lr.h"):
         if n in ("lr_bind_stream", "lr_profile", "lr_profile_read", "lr_kernel_count",
-                 "lr_kernel_name", "lr_set_state_device") or n.startswith("lr_batch_"):
+                 "lr_kernel_name", "lr_set_state_device", "lr_run_noalloc") or n.startswith("lr_batch_"):
             continue  # host-only oracle: no streams, kernels, device inputs or batches
         assert hasattr(lib, n.replace("lr_", "lr_ref_", 1)), n
 
@@ -97,3 +97,21 @@ def test_batch_argument_validation_without_device():
     assert 0 < f32 < f64 and 3.5 * f32 < big < 4.5 * f32
     assert lib.lr_batch_footprint(1, 64, 2, lr.LR_FP32) == 0
     assert lib.lr_batch_step(None, None) == lr.LR_EINVAL
+
+
+def test_noalloc_rejects_bad_arguments_without_device():
+    """lr_run_noalloc checks sizes and options before any device call, and
+    names the failure in the caller's buffer."""
+    from paper_2208_13409_amd import lr
+    lib = lr.load()
+    o = lr.lr_default_opts()
+    eos = (lr.lr_eos * 1)(lr.lr_eos(1.4, 0.0))
+    err = ctypes.create_string_buffer(128)
+    null = ctypes.c_void_p(0)
+    args = [1.0, 10, ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.c_void_p(1),
+            ctypes.c_void_p(1), 0, None, null, None, None, err, len(err)]
+    assert lib.lr_run_noalloc(1, 4, 1, eos, None, ctypes.byref(o), 0.0, *args) == lr.LR_EINVAL
+    assert b"invalid grid" in err.value
+    o.stages = 1
+    assert lib.lr_run_noalloc(4, 4, 1, eos, None, ctypes.byref(o), 0.0, *args) == lr.LR_EINVAL
+    assert b"stages" in err.value
