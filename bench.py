@@ -5,27 +5,39 @@ A step is one pass of the whole hot path (CFL time step, staggered
 Lagrangian phase, DirectCF remap with VOF partial fluxes, momentum remap)
 over the grid.  The headline workload is the three-material triple point,
 448 x 192 cells, FP64, one problem per context ("FP64 plain"), synthetic
-initial state (no dataset); the metric is cell-updates per second = cells x
-steps / wall time of the timed steps, with the state resident in device
-memory.  The same JSON line carries
+initial state (no dataset), timed in its developed state: the run first
+reaches t = t_end / 2 = 1.75 (untimed), then takes the warm-up and the timed
+steps.  The metric is cell-updates per second = cells x steps / wall time of
+the timed steps, with the state resident in device memory.  The same JSON
+line carries
 
+  "from_rest": the same timing from t = 0 (most of the grid still at rest);
+  "parity": relative L1 of density and pressure of the GPU against the FP64
+      oracle after the oracle's sample steps from the same initial state;
   "fp32_batched": 256 seeded two-material shock-bubble problems (grids from
       64x64 to 512x256) stepped together in FP32, every launch covering the
       tiles of all problems, under the launch schedule the batch's autotuner
-      picked on the first chunks (persistent grid or not, graph replay or
-      not), over a fixed window of steps;
+      picked, timed over a window that starts after every problem has run
+      past half its end time; with the L1 of its smallest problem against
+      the oracle;
+  "triple_point_1792x768": the large triple point in FP64 and FP32 from its
+      developed state (t = 1.75), and the L1 of FP32 against FP64 over the
+      timed window from the same state;
   "serving": a seeded Poisson stream of four-quadrant Riemann problems
       (grids 128^2..1024^2, FP32, t_end 0.25) served with continuous
       batching; p50/p99 latency from arrival to result fields on the host;
-  "roofline": the dominant kernel of the plain step, its algorithmic bytes
-      per launch over its average duration, measured with start/stop HIP
-      events recorded by each launch's dispatch on the kernel's stream;
-      "traffic" is the HBM bytes per launch that rocprofv3 counted for the
-      same kernel sources (profiles/), else null; "valu" the kernel's VALU
-      issue (its counted VALU instructions per launch over the same measured
-      duration, against the published FP32/FP64 vector rates), else null;
+  "roofline": the dominant kernel of the plain step: the step's algorithmic
+      bytes per cell-update (the persistent state read and written once, 176 B
+      for FP64 with three materials) times the cells one launch processes,
+      over the kernel's average duration, measured with start/stop HIP events
+      recorded by each launch's dispatch on the kernel's stream; "traffic" is
+      the HBM bytes per launch that rocprofv3 counted for the same kernel
+      sources (profiles/), else null; "valu" the kernel's VALU issue (its
+      counted VALU instructions per launch over the same measured duration,
+      against the published FP32/FP64 vector rates), else null;
   "cpu_baseline": the FP64 oracle timed on a bounded sample of the plain
-      workload on the host (one thread).
+      workload on the host's cores (OpenMP over grid rows), with the
+      single-threaded figure, the core count and the CPU model beside it.
 """
 import argparse
 import hashlib
@@ -134,22 +146,29 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def batch_leg(n_problems, steps, chunk=8):
-    """FP32 shock-bubble batch: every problem runs one warm-up chunk, then
-    `steps` timed steps (all problems take the same number of steps)."""
+def batch_leg(n_problems, steps, chunk=8, prep_steps=200):
+    """FP32 shock-bubble batch: the autotuner's chunks and `prep_steps`
+    untimed steps (every problem past half its end time, 0.125, by then:
+    the largest grid needs about 190 steps), then `steps` timed steps (all
+    problems take the same number of steps).  The smallest problem's fields
+    are compared with the FP64 oracle's after the same steps."""
+    import numpy as np
+
+    from oracle import RefSolver
     from paper_2208_13409_amd import inputs
     from paper_2208_13409_amd.lr import LR_FP32, Batch
     probs = inputs.shock_bubble_batch(n_problems)
     steps = max(chunk, (steps // chunk) * chunk)
+    prep_steps = (prep_steps // chunk) * chunk
     probe = Batch(nmat=2, precision=LR_FP32, max_slots=1, pool_bytes=1 << 20)
     pool = sum(probe.footprint(p["nx"], p["ny"]) for p in probs) + (64 << 20)
     probe.close()
     b = Batch(nmat=2, precision=LR_FP32, max_slots=len(probs), pool_bytes=pool, chunk_steps=chunk,
               autotune=True)
-    untimed = 5 * chunk  # four chunks timing the candidate schedules, one capturing the chosen one
+    untimed = 5 * chunk + prep_steps  # four chunks timing the candidate schedules, one capturing
     ids = [b.submit(p, 1e30, max_steps=untimed + steps, k_eps=1e-6) for p in probs]
     assert all(i is not None for i in ids)
-    for _ in range(5):
+    for _ in range(untimed // chunk):
         b.step()
     persistent, graph, rates = b.schedule()
     t0 = time.perf_counter()
@@ -161,19 +180,29 @@ def batch_leg(n_problems, steps, chunk=8):
     for rid in ids:
         rc, st, _ = b.status(rid)
         assert rc == 0 and st == untimed + steps, (rid, rc, st)
+    small = min(range(len(probs)), key=lambda i: probs[i]["nx"] * probs[i]["ny"])
+    ps = probs[small]
+    fg = b.fields(ids[small], "rho", "p")
+    r = RefSolver(ps["nx"], ps["ny"], ps["gammas"], ps["domain"], k_eps=1e-6)
+    r.set_state(0.0, ps["k"], ps["rho"], ps["e"], ps["ux"], ps["uy"])
+    r.run(1e30, max_steps=untimed + steps)
+    fr = r.fields("rho", "p")
+    l1 = {k: float(np.abs(fg[k] - fr[k]).sum() / np.abs(fr[k]).sum()) for k in ("rho", "p")}
     cells = sum(p["nx"] * p["ny"] for p in probs)
     value = cells * steps / wall
     bpc = step_bytes(1, 1, 2, 4)
     b.close()
     return {"value": value, "unit": "cell-updates/s", "dtype": "f32",
             "workload": f"shock_bubble_batch_{len(probs)}", "problems": len(probs), "cells": cells,
-            "steps": steps, "ms_per_step": wall * 1e3 / steps, "chunks": chunks,
+            "steps": steps, "timed_from_step": untimed, "ms_per_step": wall * 1e3 / steps, "chunks": chunks,
             "launch": ("persistent grids" if persistent else "one block per tile of every problem")
                       + (f", one HIP graph per chunk of {chunk} steps" if graph else
                          f", chunks of {chunk} steps launched directly"),
-            "autotuner_cell_steps_per_ms": [round(float(r), 1) for r in rates] if rates is not None else None,
+            "autotuner_cell_steps_per_ms": [round(float(r_), 1) for r_ in rates] if rates is not None else None,
             "hbm_bytes_per_cell_update": bpc, "achieved_GBs": value * bpc / 1e9,
-            "frac_hbm": value * bpc / 1e9 / HBM_PEAK_GBS}
+            "frac_hbm": value * bpc / 1e9 / HBM_PEAK_GBS,
+            "l1_vs_oracle": {"problem": small, "grid": f"{ps['nx']}x{ps['ny']}", "steps": untimed + steps,
+                             "rho": l1["rho"], "p": l1["p"]}}
 
 
 def serve_leg(n_requests, rate):
@@ -194,17 +223,110 @@ def serve_leg(n_requests, rate):
             "workload": f"four_quadrant stream, first {n_requests} requests, FP32"}
 
 
+def host_cpu():
+    """CPU model name and logical CPUs of this host (lscpu, nproc)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(p, steps):
+    """The oracle on `steps` steps of the workload from t = 0, with OpenMP over
+    grid rows on the host's cores and single-threaded; the fields it reaches
+    are compared with the GPU's after the same steps from the same input."""
+    import numpy as np
+
     from oracle import RefSolver
-    r = RefSolver(p["nx"], p["ny"], p["gammas"], p["domain"])
-    r.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+    from paper_2208_13409_amd.lr import Solver
+    res = {}
+    fields = None
+    for omp in (True, False):
+        r = RefSolver(p["nx"], p["ny"], p["gammas"], p["domain"], omp=omp)
+        r.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+        t0 = time.perf_counter()
+        n, _ = r.run(p["t_end"], max_steps=steps)
+        res[omp] = (p["nx"] * p["ny"] * n / (time.perf_counter() - t0), time.perf_counter() - t0, n)
+        if fields is None:
+            fields = r.fields("rho", "p")
+    g = Solver(p["nx"], p["ny"], p["gammas"], p["domain"])
+    g.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+    ng, _ = g.run(p["t_end"], max_steps=steps)
+    fg = g.fields("rho", "p")
+    l1 = {k: float(np.abs(fg[k] - fields[k]).sum() / np.abs(fields[k]).sum()) for k in ("rho", "p")}
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    v, el, n = res[True]
+    v1, el1, _ = res[False]
+    host = host_cpu()
+    return {"value": v, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{p['name']} FP64, the first {n} steps from t=0, OpenMP over rows on {threads} "
+                      f"threads ({el:.1f} s); single thread {v1:.3g} cell-updates/s ({el1:.1f} s)",
+            "single_thread": {"value": v1, "cores": 1, "seconds": el1},
+            "host": host,
+            "l1_vs_gpu": {"rho": l1["rho"], "p": l1["p"], "steps": n, "gpu_steps": ng}}
+
+
+def timed_window(g, stream, warmup, steps):
+    """warm-up steps, then `steps` timed steps (wall clock and stream events)"""
+    import torch
+    t_far = 1e30  # the timed steps follow the CFL step and never land on an end time
+    nw, _ = g.run(t_far, max_steps=warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
     t0 = time.perf_counter()
-    n, _ = r.run(p["t_end"], max_steps=steps)
-    el = time.perf_counter() - t0
-    return {"value": p["nx"] * p["ny"] * n / el, "unit": "cell-updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{p['name']} FP64, the first {n} steps from t=0, single thread "
-                      f"({el:.1f} s)"}
+    n, _ = g.run(t_far, max_steps=steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert n == steps, f"only {n} of {steps} steps ran"
+    return nw, n, wall, ev0.elapsed_time(ev1)
+
+
+def large_leg(steps, warmup):
+    """Triple point 1792x768 from its developed state: FP64 reaches t = 1.75;
+    that state starts an FP64 and an FP32 solver, each timed over the same
+    window; L1 of FP32 against FP64 after it."""
+    import numpy as np
+    import torch
+
+    from paper_2208_13409_amd import inputs
+    from paper_2208_13409_amd.lr import LR_FP32, Solver
+    p = workload("triple_point_1792x768")
+    nx, ny, nmat = p["nx"], p["ny"], len(p["gammas"])
+    g = Solver(nx, ny, p["gammas"], p["domain"])
+    g.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+    t_dev = 0.5 * p["t_end"]
+    n_prep, _ = g.run(t_dev)
+    x0, x1, y0, y1 = p["domain"]
+    st = inputs.restart_state(g.fields("vol", "mass", "ie", "ux", "uy"), (x1 - x0) / nx * (y1 - y0) / ny)
+    g.close()
+    out = {"workload": "triple_point_1792x768", "cells": nx * ny, "developed_from_step": n_prep,
+           "t_start": t_dev}
+    fields = {}
+    for prec in ("fp64", "fp32"):
+        stream = torch.cuda.Stream()
+        h = Solver(nx, ny, p["gammas"], p["domain"], stream=stream,
+                   precision=LR_FP32 if prec == "fp32" else 0, k_eps=1e-6 if prec == "fp32" else 1e-10)
+        h.set_state(t_dev, *st)
+        _, n, wall, _ = timed_window(h, stream, warmup, steps)
+        w = 4 if prec == "fp32" else 8
+        bpc = step_bytes(1, 1, nmat, w)
+        v = nx * ny * n / wall
+        out[prec] = {"value": v, "unit": "cell-updates/s", "steps": n, "ms_per_step": wall * 1e3 / n,
+                     "bytes_per_cell_update": bpc, "frac_hbm_cache_resident": v * bpc / 1e9 / HBM_PEAK_GBS}
+        fields[prec] = h.fields("rho", "p")
+        h.close()
+    out["fp32_l1_vs_fp64"] = {k: float(np.abs(fields["fp32"][k] - fields["fp64"][k]).sum()
+                                       / np.abs(fields["fp64"][k]).sum()) for k in ("rho", "p")}
+    return out
 
 
 def main():
@@ -213,6 +335,8 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="triple_point_448x192")
+    ap.add_argument("--develop", type=float, default=0.5,
+                    help="fraction of t_end reached (untimed) before the timed window")
     ap.add_argument("--profile-steps", type=int, default=64,
                     help="steps run again with per-kernel HIP event pairs")
     ap.add_argument("--cpu-steps", type=int, default=150)
@@ -221,6 +345,8 @@ def main():
     ap.add_argument("--batch-problems", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--large-steps", type=int, default=100)
+    ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=40)
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--no-serve", action="store_true")
@@ -255,32 +381,31 @@ def main():
     fp32 = args.precision == "fp32"
     w = 4 if fp32 else 8
     g = Solver(nx, ny, p["gammas"], p["domain"], stream=stream, precision=1 if fp32 else 0)
-    g.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
-    t_end = 1e30  # the timed steps follow the CFL step and never land on t_end
 
-    nw, _ = g.run(t_end, max_steps=args.warmup)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    t0 = time.perf_counter()
-    n, t = g.run(t_end, max_steps=args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    assert n == args.steps, f"only {n} of {args.steps} steps ran"
+    # from rest: most of the grid at rest, which the kernels skip
+    g.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+    nw0, n0, wall0, _ = timed_window(g, stream, args.warmup, args.steps)
+    from_rest = {"value": cells * n0 / wall0, "steps": n0, "warmup": nw0, "ms_per_step": wall0 * 1e3 / n0,
+                 "t_start": 0.0}
+
+    # developed state: t = t_end / 2 reached untimed from rest
+    t_dev = args.develop * p["t_end"]
+    g.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+    n_prep, t_prep = g.run(t_dev)
+    nw, n, wall, gpu_ms = timed_window(g, stream, args.warmup, args.steps)
 
     # the same kind of steps again, with an event pair around every launch
     g.profile(True)
-    g.run(t_end, max_steps=args.profile_steps)
+    g.run(1e30, max_steps=args.profile_steps)
     prof = g.profile_read()
     g.profile(False)
     kb = kernel_bytes(nx, ny, nmat, w)
     avg_us = {k: (ms / cnt * 1e3 if cnt else 0.0) for k, (ms, cnt) in prof.items()}
     dom = max(prof, key=lambda k: prof[k][0])
     dom_s = avg_us[dom] * 1e-6
-    achieved = kb[dom] / dom_s / 1e9
+    # the scope table's per-cell-update bytes times the cells of one launch
+    alg = step_bytes(nx, ny, nmat, w)
+    achieved = alg / dom_s / 1e9
     step_us = sum(avg_us.values())
     value = cells * n / wall
     out = {
@@ -297,26 +422,34 @@ def main():
         "dtype": "f32" if fp32 else "f64",
         "data": "synthetic",
         "config": {"workload": p["name"], "nx": nx, "ny": ny, "nmat": nmat, "precision": args.precision,
-                   "t_start": 0.0, "cfl": 0.5},
+                   "t_start": t_prep, "developed_from_step": n_prep, "cfl": 0.5},
         "gpu_event_ms_per_step": gpu_ms / n,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": counted_traffic(dom, p["name"], args.precision),
-                     "algorithmic_bytes_per_launch": kb[dom], "avg_launch_us": avg_us[dom],
+                     "algorithmic_bytes_per_launch": alg,
+                     "bytes_per_cell_update": step_bytes(1, 1, nmat, w),
+                     "kernel_array_bytes_per_launch": kb[dom], "avg_launch_us": avg_us[dom],
                      "valu": valu_roofline(counted_valu(dom, p["name"], args.precision), dom_s, fp32)},
         "roofline_step": {"bytes_per_cell_update": step_bytes(1, 1, nmat, w),
-                          "achieved_GBs": step_bytes(nx, ny, nmat, w) / (wall / n) / 1e9,
-                          "frac": step_bytes(nx, ny, nmat, w) / (wall / n) / 1e9 / HBM_PEAK_GBS,
+                          "achieved_GBs": alg / (wall / n) / 1e9,
+                          "frac": alg / (wall / n) / 1e9 / HBM_PEAK_GBS,
                           "sum_kernel_us": step_us},
         "kernels_avg_us": avg_us,
+        "from_rest": from_rest,
     }
     if not args.no_batch:
         out["fp32_batched"] = batch_leg(args.batch_problems, args.batch_steps)
         out["fp32_batched"]["vs_fp64_plain"] = out["fp32_batched"]["value"] / value
+    if not args.no_large:
+        out["triple_point_1792x768"] = large_leg(args.large_steps, 10)
     if not args.no_serve:
         out["serving"] = serve_leg(args.serve_requests, args.serve_rate)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
+        out["parity"] = {"vs": "FP64 oracle", "l1_rho": out["cpu_baseline"]["l1_vs_gpu"]["rho"],
+                         "l1_p": out["cpu_baseline"]["l1_vs_gpu"]["p"],
+                         "steps": out["cpu_baseline"]["l1_vs_gpu"]["steps"], "t_start": 0.0}
     print(json.dumps(out), flush=True)
 
 

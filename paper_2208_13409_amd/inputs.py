@@ -279,3 +279,22 @@ def square_advection(n=100, u=(5.0, 5.0), rho_in=10.0, rho_out=0.1, nmat=1, gamm
     uy = np.full((n + 1, n + 1), float(u[1]))
     return dict(name=f"square_advection_{n}", nx=n, ny=n, gammas=gam, domain=domain, k=k,
                 rho=rho, e=e, ux=ux, uy=uy, t_end=0.02)
+
+
+def restart_state(fields, A):
+    """An initial state (k, rho, e, ux, uy) that lr_set_state accepts, from a
+    problem's conserved fields (dict with vol, mass, ie [nmat][ny][nx] and
+    ux, uy [ny+1][nx+1]; A = cell area): traces below 1e-14 of a cell, and
+    any with a non-positive mass or a negative energy, are dropped and their
+    fraction given to the cell's largest material."""
+    V, M, E = fields["vol"], fields["mass"], fields["ie"]
+    keep = (V > 1e-14 * A) & (M > 0.0) & (E >= 0.0)
+    k = np.where(keep, V / A, 0.0)
+    big = np.argmax(k, axis=0)
+    rows = np.arange(k.shape[1])[:, None]
+    cols = np.arange(k.shape[2])[None, :]
+    k[big, rows, cols] = 0.0
+    k[big, rows, cols] = 1.0 - k.sum(0)
+    rho = np.where(keep, M / np.where(keep, V, 1.0), 0.0)
+    e = np.where(keep, E / np.where(keep, M, 1.0), 0.0)
+    return k, rho, e, fields["ux"], fields["uy"]
