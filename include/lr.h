@@ -2,8 +2,8 @@
  * lr.h — C-ABI of the MI355X library for the 2D multimaterial Lagrange–Remap
  * step with the one-step "Direct remap with Corner Fluxes" (DirectCF) of
  * B. Chaudet, arXiv:2208.13409.  One context holds one problem: a regular
- * orthogonal grid of nx x ny cells, nmat perfect-gas materials and reflective
- * walls.  All state lives in device memory owned by the library; every
+ * orthogonal grid of nx x ny cells, nmat perfect-gas or stiffened-gas
+ * materials and reflective walls.  All state lives in device memory owned by the library; every
  * argument pointer below is HOST memory, FP64, row-major with x fastest,
  * unless stated otherwise.
  *
@@ -36,8 +36,10 @@ enum {
 enum { LR_BC_REFLECT = 0 };     /* the only boundary: reflective wall          */
 enum { LR_FP64 = 0, LR_FP32 = 1 };
 
-/* material equation of state: perfect gas p = (gamma-1) rho e (paper §5.1);
- * pinf must be 0 (the stiffened-gas form is not implemented) */
+/* material equation of state p = (gamma-1) rho e - pinf: the perfect gas of
+ * paper §5.1 for pinf = 0, the stiffened gas of §5.2 (the paper's pi, e.g.
+ * water gamma 7, pi 2.1e9 Pa) for pinf > 0; gamma > 1, pinf >= 0 and finite.
+ * The squared sound speed is (gamma p + pinf) / rho. */
 typedef struct { double gamma, pinf; } lr_eos;
 
 typedef struct {

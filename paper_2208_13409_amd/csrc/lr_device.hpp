@@ -23,6 +23,7 @@ struct Grid {
   double cfl, a1, a2, k_eps, fixed_dt;
   double neg_tol;  // a partial V, M, E below -neg_tol of the cell scale is an error
   double gamma[MAXMAT];
+  double pinf[MAXMAT];  // stiffened-gas pi (0: perfect gas)
   int ndt;  // CFL partial minima the problem uses (a power of two, 32..NDT)
 };
 

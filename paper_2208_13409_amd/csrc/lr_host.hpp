@@ -91,7 +91,7 @@ int make_grid(int nx, int ny, int nmat, const lr_eos *eos, const int bc[4], cons
     for (int s = 0; s < 4; ++s)
       if (bc[s] != LR_BC_REFLECT) return LR_EINVAL;
   for (int a = 0; a < nmat; ++a)
-    if (!(eos[a].gamma > 1.0) || eos[a].pinf != 0.0) return LR_EINVAL;
+    if (!(eos[a].gamma > 1.0) || !(eos[a].pinf >= 0.0) || !std::isfinite(eos[a].pinf)) return LR_EINVAL;
   if (!(o.x1 > o.x0) || !(o.y1 > o.y0) || !(o.cfl > 0) || (o.recon_order != 1 && o.recon_order != 2) ||
       !(o.k_eps >= 0) || o.fixed_dt < 0 || (o.precision != LR_FP64 && o.precision != LR_FP32))
     return LR_EINVAL;
@@ -105,7 +105,10 @@ int make_grid(int nx, int ny, int nmat, const lr_eos *eos, const int bc[4], cons
   // that moved out: presence and negativity thresholds above that level
   g.neg_tol = o.precision == LR_FP32 ? 1e-5 : 1e-10;
   if (o.precision == LR_FP32 && g.k_eps < 1e-6) g.k_eps = 1e-6;
-  for (int a = 0; a < nmat; ++a) g.gamma[a] = eos[a].gamma;
+  for (int a = 0; a < nmat; ++a) {
+    g.gamma[a] = eos[a].gamma;
+    g.pinf[a] = eos[a].pinf;
+  }
   g.ndt = cfl_partials(nx, ny);
   return LR_OK;
 }

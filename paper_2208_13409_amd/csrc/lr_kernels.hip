@@ -51,6 +51,19 @@ __device__ __forceinline__ bool present(const GridT &g, R V) {
   return double(V) > g.k_eps * g.A;
 }
 
+// Equation of state of material m: the perfect gas of §5.1 (pinf = 0) or
+// the stiffened gas of §5.2, p = (gamma - 1) rho e - pi.  eos_krc2 is the
+// material's share k rho c^2 of the mixture's bulk modulus, with the squared
+// sound speed (dp/drho at constant entropy) c^2 = (gamma p + pi) / rho.
+template <typename GridT, typename R>
+__device__ __forceinline__ R eos_p(const GridT &g, int m, R rho, R e) {
+  return R(g.gamma[m] - 1.0) * rho * e - R(g.pinf[m]);
+}
+template <typename GridT, typename R>
+__device__ __forceinline__ R eos_krc2(const GridT &g, int m, R k, R P) {
+  return k * R(g.gamma[m]) * P + k * R(g.pinf[m]);
+}
+
 // compensated accumulation (Kahan–Neumaier) for the FP32 cell totals
 template <typename R>
 struct Acc {
@@ -433,8 +446,8 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
         // an absent material's mass can be a float denormal: IEEE quotient
         e[m] = M > R(0) ? E / M : R(0);
         rho[m] = pr[m] ? qdiv(M, V) : R(0);
-        Pa[m] = pr[m] ? R(g.gamma[m] - 1.0) * rho[m] * e[m] : R(0);
-        if (pr[m]) rc2 += k[m] * R(g.gamma[m]) * Pa[m];
+        Pa[m] = pr[m] ? eos_p(g, m, rho[m], e[m]) : R(0);
+        if (pr[m]) rc2 += eos_krc2(g, m, k[m], Pa[m]);
         Msum += M;
       }
       R Qc = R(0), Sc = R(0);
@@ -461,7 +474,7 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
             if (pr[m]) {
               const R rho_h = Mm[m] / (k[m] * Vh);
               const R e_h = e[m] - (Pa[m] + Qc) * (R(1) / rho_h - R(1) / rho[m]);
-              Ph = R(g.gamma[m] - 1.0) * rho_h * e_h;
+              Ph = eos_p(g, m, rho_h, e_h);
               Pch += k[m] * Ph;
             }
             sPh[m][b][a] = Ph;
@@ -476,7 +489,7 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
             if (pr[m]) {
               const R e_h = e[m] - (Pa[m] + Qc) * qdiv(k[m] * dV, Mm[m]);
               const R rho_h = qdiv(Mm[m], k[m] * (A + dV));
-              Ph = R(g.gamma[m] - 1.0) * rho_h * e_h;
+              Ph = eos_p(g, m, rho_h, e_h);
               Pch += k[m] * Ph;
             }
             sPh[m][b][a] = Ph;
@@ -1260,8 +1273,8 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
         if (present(g, Vn[m])) {
           const R rho = qdiv(Mn[m], Vn[m]);
           const R e = Mn[m] > R(0) ? qdiv(En[m], Mn[m]) : R(0);
-          const R Pm = R(g.gamma[m] - 1.0) * rho * e;
-          rc2 += qdiv(Vn[m], A) * R(g.gamma[m]) * Pm;
+          const R Pm = eos_p(g, m, rho, e);
+          rc2 += eos_krc2(g, m, qdiv(Vn[m], A), Pm);
         }
         Msum += Mn[m];
       }
@@ -1753,7 +1766,7 @@ __global__ void k_sound(Prob<R> P, int buf) {
     const R V = P.V[buf][m * C + q], M = P.M[buf][m * C + q], E = P.E[buf][m * C + q];
     if (present(g, V)) {
       const R rho = M / V, e = M > R(0) ? E / M : R(0);
-      rc2 += (V / R(g.A)) * R(g.gamma[m]) * (R(g.gamma[m] - 1.0) * rho * e);
+      rc2 += eos_krc2(g, m, V / R(g.A), eos_p(g, m, rho, e));
     }
     Msum += M;
   }
@@ -1830,7 +1843,7 @@ __global__ void k_fields(Prob<R> P, int buf, unsigned bit, double *out) {
     const double V = P.V[buf][m * C + q], M = P.M[buf][m * C + q], E = P.E[buf][m * C + q];
     const bool pr = V > g.k_eps * g.A;
     const double rho = pr ? M / V : 0.0, e = (pr && M > 0.0) ? E / M : 0.0;
-    const double Pm = pr ? (g.gamma[m] - 1.0) * rho * e : 0.0;
+    const double Pm = pr ? eos_p(g, m, rho, e) : 0.0;
     Ms += M;
     Es += E;
     Ps += (V / g.A) * Pm;

@@ -157,6 +157,58 @@ def shock_bubble(seed, grid=None):
                 mach=mach, radius=r)
 
 
+def _stiff_energy(p, rho, gamma, pinf):
+    """specific internal energy of the stiffened gas p = (gamma-1) rho e - pi"""
+    return (p + pinf) / ((gamma - 1.0) * rho)
+
+
+def water_air_tube(nx=400, ny=4):
+    """Water-air shock tube of §5.2's kind on [0,1] m x [0, ny/nx]: compressed
+    water (rho 1000 kg/m^3, p 1e9 Pa, stiffened gas gamma 7, pi 2.1e9 Pa) for
+    x < 0.5 against air (rho 50, p 1e5, perfect gas gamma 1.4), at rest;
+    t_end 1.2e-4 s (the rarefaction has not reached the wall)."""
+    domain = (0.0, 1.0, 0.0, ny / nx)
+    (X, Y), dx, dy = _cell_centres(nx, ny, domain)
+    left = X < 0.5
+    gam, pinfs = [7.0, 1.4], [2.1e9, 0.0]
+    k = np.stack([left, ~left]).astype(float)
+    rho = np.stack([np.where(left, 1000.0, 0.0), np.where(left, 0.0, 50.0)])
+    e = np.stack([np.where(left, _stiff_energy(1e9, 1000.0, 7.0, 2.1e9), 0.0),
+                  np.where(left, 0.0, _energy(1e5, 50.0, 1.4))])
+    z = np.zeros((ny + 1, nx + 1))
+    return dict(name=f"water_air_tube_{nx}x{ny}", nx=nx, ny=ny, gammas=gam, pinfs=pinfs, domain=domain,
+                k=k, rho=rho, e=e, ux=z, uy=z.copy(), t_end=1.2e-4)
+
+
+def water_impact(scale=1):
+    """Water-drop impact of §5.2 (air perfect gas, water stiffened gas) on
+    the paper's mesh of 320 x 160 cells (times `scale`) over [0, 10] x [0, 5]
+    cm, in SI units.  The paper gives the states (air: rho 1.29, u -1000 m/s;
+    water wall at rest and drop at -1000 m/s, both rho 1000, gamma 7,
+    pi 2.1e9 Pa; p 1e5 Pa everywhere) but not the geometry, which its
+    figures held.  Reading: the water wall fills x < 1 cm, the drop is a disc
+    of radius 1.2 cm centred at (4, 2.5) cm.  Material 0 is air, material 1
+    water (wall and drop).  t_end 6 ms."""
+    nx, ny = 320 * scale, 160 * scale
+    domain = (0.0, 0.1, 0.0, 0.05)
+    (X, Y), dx, dy = _cell_centres(nx, ny, domain)
+    kd = circle_fraction(nx, ny, domain, 0.04, 0.025, 0.012)
+    wall = X < 0.01
+    kw = np.where(wall, 1.0, kd)
+    k = np.stack([1.0 - kw, kw])
+    gam, pinfs = [1.4, 7.0], [0.0, 2.1e9]
+    rho = np.stack([np.full((ny, nx), 1.29), np.full((ny, nx), 1000.0)])
+    e = np.stack([np.full((ny, nx), _energy(1e5, 1.29, 1.4)),
+                  np.full((ny, nx), _stiff_energy(1e5, 1000.0, 7.0, 2.1e9))])
+    rho = np.where(k > 0, rho, 0.0)
+    e = np.where(k > 0, e, 0.0)
+    ucell = np.where(wall, 0.0, -1000.0)
+    mass = (k * rho).sum(0)
+    ux, uy = nodal_velocity(mass, ucell, np.zeros_like(ucell))
+    return dict(name=f"water_impact_{nx}x{ny}", nx=nx, ny=ny, gammas=gam, pinfs=pinfs, domain=domain,
+                k=k, rho=rho, e=e, ux=ux, uy=uy, t_end=6e-3)
+
+
 def shock_bubble_batch(n=256, seed=BASE_SEED):
     return [shock_bubble(seed + b) for b in range(n)]
 

@@ -147,8 +147,15 @@ def lr_default_opts():
     return o
 
 
-def lr_create(nx, ny, gammas, opts):
-    eos = (lr_eos * len(gammas))(*[lr_eos(float(g), 0.0) for g in gammas])
+def _eos(gammas, pinfs=None):
+    pinfs = [0.0] * len(gammas) if pinfs is None else pinfs
+    if len(pinfs) != len(gammas):
+        raise ValueError("one pinf per material expected")
+    return (lr_eos * len(gammas))(*[lr_eos(float(g), float(pi)) for g, pi in zip(gammas, pinfs)])
+
+
+def lr_create(nx, ny, gammas, opts, pinfs=None):
+    eos = _eos(gammas, pinfs)
     bc = (C.c_int * 4)(0, 0, 0, 0)
     h = C.c_void_p()
     rc = load().lr_create(int(nx), int(ny), len(gammas), eos, bc, C.byref(opts), C.byref(h))
@@ -162,7 +169,7 @@ class Solver:
 
     def __init__(self, nx, ny, gammas, domain=(0.0, 1.0, 0.0, 1.0), cfl=0.5, a1=0.5, a2=1.0,
                  recon_order=2, kinematic=False, k_eps=1e-10, fixed_dt=0.0, precision=LR_FP64,
-                 stages=False, stream=None):
+                 stages=False, stream=None, pinfs=None):
         self.lib = load()
         self.nx, self.ny, self.nmat = int(nx), int(ny), len(gammas)
         o = lr_default_opts()
@@ -171,7 +178,7 @@ class Solver:
         o.recon_order, o.kinematic = int(recon_order), int(bool(kinematic))
         o.k_eps, o.fixed_dt, o.precision = float(k_eps), float(fixed_dt), int(precision)
         o.stages = int(bool(stages))
-        self.h = lr_create(nx, ny, gammas, o)
+        self.h = lr_create(nx, ny, gammas, o, pinfs)
         if stream is not None:
             self.bind_stream(stream)
 
@@ -276,7 +283,7 @@ def _fields(fn, h, nx, ny, nmat, check, names, *lead):
 
 def run_noalloc(nx, ny, gammas, domain, t_end, k, rho, e, ux, uy, names, outs, t0=0.0,
                 max_steps=1 << 40, cfl=0.5, a1=0.5, a2=1.0, recon_order=2, kinematic=False,
-                k_eps=1e-10, fixed_dt=0.0, precision=LR_FP64, stream=None):
+                k_eps=1e-10, fixed_dt=0.0, precision=LR_FP64, stream=None, pinfs=None):
     """lr_run_noalloc: inputs k, rho, e, ux, uy and outputs outs[name] are
     contiguous float64 device tensors (torch); names are field names in any
     order (written in the library's bit order).  Returns (steps, t)."""
@@ -286,7 +293,7 @@ def run_noalloc(nx, ny, gammas, domain, t_end, k, rho, e, ux, uy, names, outs, t
     o.cfl, o.a1, o.a2 = float(cfl), float(a1), float(a2)
     o.recon_order, o.kinematic = int(recon_order), int(bool(kinematic))
     o.k_eps, o.fixed_dt, o.precision = float(k_eps), float(fixed_dt), int(precision)
-    eos = (lr_eos * len(gammas))(*[lr_eos(float(g), 0.0) for g in gammas])
+    eos = _eos(gammas, pinfs)
     ins = (k, rho, e, ux, uy)
     for x in ins + tuple(outs[n_] for n_ in names):
         if not (x.is_cuda and x.is_contiguous() and str(x.dtype) == "torch.float64"):
@@ -363,7 +370,7 @@ class Batch:
         gam = prob["gammas"]
         if len(gam) != self.nmat:
             raise LRError(LR_EINVAL, f"{len(gam)} materials in a batch of nmat={self.nmat}")
-        eos = (lr_eos * len(gam))(*[lr_eos(float(g), 0.0) for g in gam])
+        eos = _eos(gam, prob.get("pinfs"))
         arrs = [np.ascontiguousarray(prob[n], dtype=np.float64) for n in ("k", "rho", "e", "ux", "uy")]
         rid = C.c_long()
         rc = self.lib.lr_batch_submit(self.h, int(prob["nx"]), int(prob["ny"]), eos, C.byref(o),

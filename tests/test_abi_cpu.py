@@ -115,3 +115,15 @@ def test_noalloc_rejects_bad_arguments_without_device():
     o.stages = 1
     assert lib.lr_run_noalloc(4, 4, 1, eos, None, ctypes.byref(o), 0.0, *args) == lr.LR_EINVAL
     assert b"stages" in err.value
+
+
+def test_eos_arguments_checked_without_device():
+    """A stiffened-gas pi must be finite and >= 0, gamma > 1: rejected before
+    any device call."""
+    from paper_2208_13409_amd import lr
+    lib = lr.load()
+    o = lr.lr_default_opts()
+    h = ctypes.c_void_p()
+    for g, pi in ((1.4, -1.0), (1.4, float("inf")), (1.0, 0.0)):
+        eos = (lr.lr_eos * 1)(lr.lr_eos(g, pi))
+        assert lib.lr_create(8, 8, 1, eos, None, ctypes.byref(o), ctypes.byref(h)) == lr.LR_EINVAL
