@@ -67,7 +67,7 @@ def test_argument_validation_without_device():
                          ctypes.byref(h)) == lr.LR_EINVAL
     o.precision = 7
     assert lib.lr_create(4, 4, 1, eos, None, ctypes.byref(o), ctypes.byref(h)) == lr.LR_EINVAL
-    bad = (lr.lr_eos * 1)(lr.lr_eos(1.4, 3.0))
+    bad = (lr.lr_eos * 1)(lr.lr_eos(1.4, -3.0))
     o = lr.lr_default_opts()
     assert lib.lr_create(4, 4, 1, bad, None, ctypes.byref(o), ctypes.byref(h)) == lr.LR_EINVAL
     assert lib.lr_step(None, None) == lr.LR_EINVAL
