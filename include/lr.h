@@ -35,6 +35,12 @@ enum {
 
 enum { LR_BC_REFLECT = 0 };     /* the only boundary: reflective wall          */
 enum { LR_FP64 = 0, LR_FP32 = 1 };
+/* remap of the Lagrangian state: the one-step DirectCF remap with corner
+ * fluxes (§2.3, the default), or the paper's comparator, the alternate-
+ * direction remap (§2.1.1, §2.1.2, §4.2): an X pass then a Y pass, in the
+ * other order on every second step, each a one-dimensional remap of the cell
+ * and nodal quantities with its own interface */
+enum { LR_REMAP_DIRECTCF = 0, LR_REMAP_AD = 1 };
 
 /* material equation of state p = (gamma-1) rho e - pinf: the perfect gas of
  * paper §5.1 for pinf = 0, the stiffened gas of §5.2 (the paper's pi, e.g.
@@ -54,6 +60,8 @@ typedef struct {
                             (FP32 uses at least 1e-6)                                     */
   double fixed_dt;       /* > 0: this time step instead of the CFL one                    */
   int stages;            /* 1 = keep the intermediates of each step for lr_debug_get      */
+  int remap;             /* LR_REMAP_DIRECTCF (default) or LR_REMAP_AD; batches and
+                            lr_run_noalloc run DirectCF only                              */
 } lr_opts;
 
 /* field mask bits for lr_get_fields, in the order the output pointers are

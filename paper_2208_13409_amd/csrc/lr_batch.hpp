@@ -402,7 +402,8 @@ int lr_batch_submit(lr_batch *b, int nx, int ny, const lr_eos *eos, const lr_opt
     lr_default_opts(&o);
     o.precision = b->o.precision;
   }
-  if (o.precision != b->o.precision || o.stages) return bset(b, LR_EINVAL, "precision differs from the batch's, or stages set");
+  if (o.precision != b->o.precision || o.stages || o.remap != LR_REMAP_DIRECTCF)
+    return bset(b, LR_EINVAL, "precision differs from the batch's, or stages or the AD remap set");
   if (!(t_end >= 0.0) || max_steps < 0) return bset(b, LR_EINVAL, "t_end < 0 or max_steps < 0");
   Grid g;
   if (make_grid(nx, ny, b->o.nmat, eos, nullptr, o, g) != LR_OK) return bset(b, LR_EINVAL, "bad grid, eos or options");

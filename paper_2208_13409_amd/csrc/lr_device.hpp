@@ -20,11 +20,13 @@ struct Grid {
   int recon_order, kinematic;
   double dx, dy, A;  // cell sizes and area
   double Lx, Ly;     // domain extents x1-x0, y1-y0
+  double x0, x1, y0, y1;  // domain
   double cfl, a1, a2, k_eps, fixed_dt;
   double neg_tol;  // a partial V, M, E below -neg_tol of the cell scale is an error
   double gamma[MAXMAT];
   double pinf[MAXMAT];  // stiffened-gas pi (0: perfect gas)
   int ndt;  // CFL partial minima the problem uses (a power of two, 32..NDT)
+  int remap;  // LR_REMAP_DIRECTCF or LR_REMAP_AD
 };
 
 // Device-side time control.  Step n of a problem reads slot[n & 1 ^ flip];
@@ -71,6 +73,21 @@ struct Dbg {
   R *Wpx, *Wpy, *Wpc;       // per-material signed partial volumes of the regions
 };
 
+// Arrays of the alternate-direction remap (allocated for it only): the
+// state and nodal velocity between its two passes, and each pass's per-cell
+// and per-face intermediates (faces of the pass's direction).
+template <typename R>
+struct AdArrays {
+  R *V, *M, *E;          // [nmat][C] state after the first pass
+  R *ux, *uy;            // [N] nodal velocity after the first pass
+  R *k, *e, *rhocf;      // [nmat][C] pass input fractions, specific energies, rho^{lag}
+  R *vol, *cen, *wid;    // [C] pass Lagrangian volume, centre and width along the direction
+  R *Mc;                 // [C] mixture mass of the pass input
+  int *pure;             // [C] the single present material, or -1
+  R *W, *mu, *eps;       // [nmat][faces] partial volume, mass and energy flux of each face
+  R *muF;                // [faces] signed total mass flux of each face
+};
+
 // Everything a kernel needs to step one problem (device pointers).
 template <typename R>
 struct Prob {
@@ -89,6 +106,7 @@ struct Prob {
                                   // FP64, stored in the bulk precision)
   Ctl *ctl;
   Dbg<R> dbg;
+  AdArrays<R> ad;
 };
 
 // block -> (problem, tile origin) of one launch over a batch

@@ -54,6 +54,17 @@ size_t carve_prob(Prob<R> &P, char *base, const Grid &g, bool stages, Ctl *ctl) 
   P.mix_cell = cv.take<int>(C); P.mix_slot = cv.take<int>(C);
   P.mix_cap = (int)C;
   P.mix_W = cv.take<R>(C * 8 * m);
+  if (g.remap == LR_REMAP_AD) {
+    const size_t nF = std::max(nX, nY);
+    AdArrays<R> &a = P.ad;
+    a.V = cv.take<R>(m * C); a.M = cv.take<R>(m * C); a.E = cv.take<R>(m * C);
+    a.ux = cv.take<R>(N); a.uy = cv.take<R>(N);
+    a.k = cv.take<R>(m * C); a.e = cv.take<R>(m * C); a.rhocf = cv.take<R>(m * C);
+    a.vol = cv.take<R>(C); a.cen = cv.take<R>(C); a.wid = cv.take<R>(C); a.Mc = cv.take<R>(C);
+    a.pure = cv.take<int>(C);
+    a.W = cv.take<R>(m * nF); a.mu = cv.take<R>(m * nF); a.eps = cv.take<R>(m * nF);
+    a.muF = cv.take<R>(nF);
+  }
   if (stages) {
     P.dbg.Q = cv.take<R>(C); P.dbg.S = cv.take<R>(C); P.dbg.VL = cv.take<R>(C);
     P.dbg.Ph = cv.take<R>(m * C); P.dbg.volcf = cv.take<R>(C);
@@ -93,13 +104,16 @@ int make_grid(int nx, int ny, int nmat, const lr_eos *eos, const int bc[4], cons
   for (int a = 0; a < nmat; ++a)
     if (!(eos[a].gamma > 1.0) || !(eos[a].pinf >= 0.0) || !std::isfinite(eos[a].pinf)) return LR_EINVAL;
   if (!(o.x1 > o.x0) || !(o.y1 > o.y0) || !(o.cfl > 0) || (o.recon_order != 1 && o.recon_order != 2) ||
-      !(o.k_eps >= 0) || o.fixed_dt < 0 || (o.precision != LR_FP64 && o.precision != LR_FP32))
+      !(o.k_eps >= 0) || o.fixed_dt < 0 || (o.precision != LR_FP64 && o.precision != LR_FP32) ||
+      (o.remap != LR_REMAP_DIRECTCF && o.remap != LR_REMAP_AD))
     return LR_EINVAL;
   g = Grid{};
   g.nx = nx; g.ny = ny; g.nmat = nmat;
   g.recon_order = o.recon_order; g.kinematic = o.kinematic ? 1 : 0;
   g.dx = (o.x1 - o.x0) / nx; g.dy = (o.y1 - o.y0) / ny; g.A = g.dx * g.dy;
   g.Lx = o.x1 - o.x0; g.Ly = o.y1 - o.y0;
+  g.x0 = o.x0; g.x1 = o.x1; g.y0 = o.y0; g.y1 = o.y1;
+  g.remap = o.remap;
   g.cfl = o.cfl; g.a1 = o.a1; g.a2 = o.a2; g.k_eps = o.k_eps; g.fixed_dt = o.fixed_dt;
   // FP32 rounding leaves residues of about 1e-7 of a cell behind a material
   // that moved out: presence and negativity thresholds above that level
@@ -322,7 +336,7 @@ int alloc_prob(lr_ctx *c, Prob<R> &P) {
   if (dalloc(c, &d, 1)) return LR_ENOMEM;
   c->dprob = d;
   HIP_CHECK(c, hipMemcpyAsync(d, &P, sizeof(Prob<R>), hipMemcpyHostToDevice, c->own));
-  c->step = step_fn<R>(c->g.nmat);
+  c->step = step_fn<R>(c->g.nmat, c->g.remap);
   return LR_OK;
 }
 
@@ -376,7 +390,8 @@ int run_steps(lr_ctx *c, double t_end, long long max_steps) {
   k_start<<<1, 1, 0, c->stream>>>(c->ctl, t_end, max_steps);
   HIP_CHECK(c, hipGetLastError());
   const Launch L{c->dprob,  c->node_map, c->cell_map, c->node_blocks, c->cell_blocks, c->plist, 1,
-                 mix_chunks_for((long long)c->g.nx * c->g.ny), false};
+                 mix_chunks_for((long long)c->g.nx * c->g.ny), false, (long long)c->g.nx * c->g.ny,
+                 (long long)(c->g.nx + 1) * (c->g.ny + 1)};
   for (;;) {
     rc = read_ctl(c);
     if (rc) return rc;
@@ -479,7 +494,7 @@ void lr_default_opts(lr_opts *o) {
   o->x0 = 0; o->x1 = 1; o->y0 = 0; o->y1 = 1;
   o->cfl = 0.5; o->a1 = 0.5; o->a2 = 1.0;
   o->precision = LR_FP64; o->recon_order = 2; o->kinematic = 0;
-  o->k_eps = 1e-10; o->fixed_dt = 0.0; o->stages = 0;
+  o->k_eps = 1e-10; o->fixed_dt = 0.0; o->stages = 0; o->remap = LR_REMAP_DIRECTCF;
 }
 
 void lr_destroy(lr_ctx *c) {

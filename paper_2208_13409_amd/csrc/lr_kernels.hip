@@ -1946,6 +1946,7 @@ struct Launch {
   int nprob;
   int mix_chunks;    // blocks per problem of the mixed-cell kernel
   bool persistent;
+  long long cells, nodes;  // of the problem (single-problem launches of the AD remap)
 };
 
 template <typename R, int NM>
@@ -2055,8 +2056,22 @@ void step_impl(const Launch &L, int gpar, hipStream_t s, hipEvent_t *ev) {
   }
 }
 using StepFn = void (*)(const Launch &, int, hipStream_t, hipEvent_t *);
+
+}  // namespace
+
+#include "lr_ad.hpp"
+
+namespace {
+
+// the step of a problem: the DirectCF remap, or the alternate-direction one
 template <typename R>
-StepFn step_fn(int nmat) {
+StepFn step_fn(int nmat, int remap = LR_REMAP_DIRECTCF) {
+  if (remap == LR_REMAP_AD) switch (nmat) {
+      case 1: return ad_step_impl<R, 1>;
+      case 2: return ad_step_impl<R, 2>;
+      case 3: return ad_step_impl<R, 3>;
+      default: return ad_step_impl<R, 4>;
+    }
   switch (nmat) {
     case 1: return step_impl<R, 1>;
     case 2: return step_impl<R, 2>;

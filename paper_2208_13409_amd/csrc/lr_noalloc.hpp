@@ -233,8 +233,8 @@ extern "C" int lr_run_noalloc(int nx, int ny, int nmat, const lr_eos *eos, const
     noalloc_msg(errbuf, errlen, "invalid grid, materials or options");
     return LR_EINVAL;
   }
-  if (o.stages) {
-    noalloc_msg(errbuf, errlen, "opts.stages must be 0");
+  if (o.stages || o.remap != LR_REMAP_DIRECTCF) {
+    noalloc_msg(errbuf, errlen, "opts.stages must be 0 and opts.remap LR_REMAP_DIRECTCF");
     return LR_EINVAL;
   }
   if (!k || !rho || !e || !ux || !uy || (field_mask && !out) || field_mask > 2 * LR_F_IE - 1 ||

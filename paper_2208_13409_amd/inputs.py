@@ -333,6 +333,38 @@ def square_advection(n=100, u=(5.0, 5.0), rho_in=10.0, rho_out=0.1, nmat=1, gamm
                 rho=rho, e=e, ux=ux, uy=uy, t_end=0.02)
 
 
+def solid_rotation(n=100, omega=2.0 * math.pi, rho_in=10.0, rho_out=0.1, nmat=1, gamma=1.4):
+    """Solid rotation of §5.1: a square of density rho_in in a field of
+    rho_out on [0,1]^2, turning about the centre with the prescribed velocity
+    u = r omega e_theta (kinematic runs keep it at every step); one turn is
+    t = 2 pi / omega (t_end).  The paper does not place the square; here it is
+    the square of side 0.2 centred at (0.5, 0.7).  The rotation is confined to
+    the inscribed disc r <= 0.5 (at rest outside it), so that the flow is
+    tangent to the reflective walls: the rigid rotation of the whole square
+    domain would push into the walls at its corners.  With nmat=2 the square
+    is material 1 and the field material 0."""
+    domain = (0.0, 1.0, 0.0, 1.0)
+    (X, Y), dx, dy = _cell_centres(n, n, domain)
+    sq = (np.abs(X - 0.5) < 0.1) & (np.abs(Y - 0.7) < 0.1)
+    if nmat == 1:
+        k = np.ones((1, n, n))
+        rho = np.where(sq, rho_in, rho_out)[None]
+        e = np.full((1, n, n), 1.0)
+        gam = [gamma]
+    else:
+        k = np.stack([~sq, sq]).astype(float)
+        rho = np.stack([np.where(sq, 0.0, rho_out), np.where(sq, rho_in, 0.0)])
+        e = np.stack([np.where(sq, 0.0, 1.0), np.where(sq, 1.0, 0.0)])
+        gam = [gamma, gamma]
+    xn = np.arange(n + 1) / n
+    XN, YN = np.meshgrid(xn, xn)
+    inside = np.hypot(XN - 0.5, YN - 0.5) <= 0.5
+    ux = np.where(inside, -omega * (YN - 0.5), 0.0)
+    uy = np.where(inside, omega * (XN - 0.5), 0.0)
+    return dict(name=f"solid_rotation_{n}", nx=n, ny=n, gammas=gam, domain=domain, k=k,
+                rho=rho, e=e, ux=ux, uy=uy, t_end=2.0 * math.pi / omega)
+
+
 def restart_state(fields, A):
     """An initial state (k, rho, e, ux, uy) that lr_set_state accepts, from a
     problem's conserved fields (dict with vol, mass, ie [nmat][ny][nx] and

@@ -19,6 +19,7 @@ _LIB = None
 LR_OK, LR_EINVAL, LR_ENOMEM, LR_EDEVICE, LR_ENEGATIVE, LR_ENAN, LR_EDT, LR_EAGAIN, LR_ESTATE = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 LR_FP64, LR_FP32 = 0, 1
+LR_REMAP_DIRECTCF, LR_REMAP_AD = 0, 1
 F_RHO, F_P, F_E, F_K, F_RHOA, F_EA, F_PA, F_UX, F_UY, F_VOL, F_MASS, F_IE = (1 << i for i in range(12))
 PER_MAT = {F_K, F_RHOA, F_EA, F_PA, F_VOL, F_MASS, F_IE}
 NODE = {F_UX, F_UY}
@@ -44,7 +45,7 @@ class lr_opts(C.Structure):
                 ("y1", C.c_double), ("cfl", C.c_double), ("a1", C.c_double),
                 ("a2", C.c_double), ("precision", C.c_int), ("recon_order", C.c_int),
                 ("kinematic", C.c_int), ("k_eps", C.c_double), ("fixed_dt", C.c_double),
-                ("stages", C.c_int)]
+                ("stages", C.c_int), ("remap", C.c_int)]
 
 
 class lr_batch_opts(C.Structure):
@@ -169,7 +170,7 @@ class Solver:
 
     def __init__(self, nx, ny, gammas, domain=(0.0, 1.0, 0.0, 1.0), cfl=0.5, a1=0.5, a2=1.0,
                  recon_order=2, kinematic=False, k_eps=1e-10, fixed_dt=0.0, precision=LR_FP64,
-                 stages=False, stream=None, pinfs=None):
+                 stages=False, stream=None, pinfs=None, remap=0):
         self.lib = load()
         self.nx, self.ny, self.nmat = int(nx), int(ny), len(gammas)
         o = lr_default_opts()
@@ -178,6 +179,7 @@ class Solver:
         o.recon_order, o.kinematic = int(recon_order), int(bool(kinematic))
         o.k_eps, o.fixed_dt, o.precision = float(k_eps), float(fixed_dt), int(precision)
         o.stages = int(bool(stages))
+        o.remap = int(remap)
         self.h = lr_create(nx, ny, gammas, o, pinfs)
         if stream is not None:
             self.bind_stream(stream)
