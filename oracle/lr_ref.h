@@ -14,12 +14,14 @@
  * All functions return 0 on success and a negative code on failure; they
  * never abort.  All arrays are host memory, FP64, row-major with x fastest.
  *
- * Parity unpinned: four readings where the paper is silent are constrained
- * only by conservation, bounds and the physics pins, not by a value the
- * paper or the mathematics fixes: the discrete divergence inside the
- * pseudo-viscosity, the dual-mesh reconstruction geometry, the interface
- * rule for cells with three or more materials, and the way clipping hands a
- * material's excess outflow to the donor's other materials.
+ * Pins: the physics and closed-form pins of the test suite, and a second
+ * reader of the whole step in 50-digit arithmetic on tiny grids.  Four
+ * readings where the paper is silent are fixed by no value the paper prints
+ * (only both readers, conservation and bounds constrain them): the discrete
+ * divergence inside the pseudo-viscosity, the dual-mesh reconstruction
+ * geometry, the interface rule for cells with three or more materials, and
+ * the way clipping hands a material's excess outflow to the donor's other
+ * materials.
  */
 #ifndef LR_REF_H
 #define LR_REF_H
