@@ -283,8 +283,9 @@ int lr_ref_create(int nx, int ny, int nmat, const lr_ref_eos *eos, const int bc[
   memcpy(c->eos, eos, nmat * sizeof *eos);
   if (opts) c->o = *opts; else lr_ref_default_opts(&c->o);
   if (!(c->o.x1 > c->o.x0) || !(c->o.y1 > c->o.y0) || !(c->o.cfl > 0) ||
-      (c->o.recon_order != 1 && c->o.recon_order != 2) || !(c->o.k_eps >= 0) ||
+      c->o.recon_order < 1 || c->o.recon_order > 3 || !(c->o.k_eps >= 0) ||
       (c->o.remap != LR_REF_REMAP_DIRECTCF && c->o.remap != LR_REF_REMAP_AD) ||
+      (c->o.remap == LR_REF_REMAP_AD && c->o.recon_order == 3) ||
       c->o.fixed_dt < 0) {
     free(c);
     return LR_REF_EINVAL;
@@ -877,11 +878,54 @@ static int stencil_pure(const lr_ref_ctx *c, int i, int j, int si, int sj) {
   return m >= 0 && c->pure[CI(c, i - si, j - sj)] == m && c->pure[CI(c, i + si, j + sj)] == m;
 }
 
-/* §2.1.1 and §3.3: value of a donor quantity on region r at order 1 or 2 */
+/* §3.3, multidimensional reconstruction: the plane a_D + G.(x - x_D) over the
+ * 3 x 3 stencil, its gradient G the least-squares fit of the eight
+ * neighbours' values at their Lagrangian centres (the normal equations of
+ * the 2 x 2 system, solved by the cofactor formula), scaled by
+ * phi = min(|d_x|, |d_y|, |d_v|, |d_vperp|) / |G| with the four limited
+ * one-dimensional slopes, and evaluated at the centre of the region's flux
+ * rectangle.  Readings: order 2 only if all nine cells are pure cells of
+ * the donor's material; a degenerate fit or G = 0 gives the donor's value. */
+static double recon_lsq(const lr_ref_ctx *c, const region *r, const double *arr) {
+  int i = r->di, j = r->dj, q = CI(c, i, j);
+  double aD = arr[q];
+  int m = c->pure[q];
+  if (m < 0) return aD;
+  for (int b = -1; b <= 1; ++b)
+    for (int a = -1; a <= 1; ++a)
+      if (c->pure[CI(c, i + a, j + b)] != m) return aD;
+  double s11 = 0.0, s12 = 0.0, s22 = 0.0, b1 = 0.0, b2 = 0.0;
+  for (int b = -1; b <= 1; ++b)
+    for (int a = -1; a <= 1; ++a) {
+      if (a == 0 && b == 0) continue;
+      int k = CI(c, i + a, j + b);
+      double X1 = c->xcL[k] - c->xcL[q], X2 = c->ycL[k] - c->ycL[q], A = arr[k] - aD;
+      s11 += X1 * X1; s12 += X1 * X2; s22 += X2 * X2;
+      b1 += X1 * A; b2 += X2 * A;
+    }
+  double det = s11 * s22 - s12 * s12;
+  if (!(det > 0.0)) return aD;
+  double G1 = (s22 * b1 - s12 * b2) / det, G2 = (s11 * b2 - s12 * b1) / det;
+  double nG = sqrt(G1 * G1 + G2 * G2);
+  if (!(nG > 0.0)) return aD;
+  double nrm = sqrt(c->dx * c->dx + c->dy * c->dy);
+  double lim = fabs(slope_dir(c, arr, i, j, 1, 0, 1.0, 0.0));
+  lim = fmin(lim, fabs(slope_dir(c, arr, i, j, 0, 1, 0.0, 1.0)));
+  lim = fmin(lim, fabs(slope_dir(c, arr, i, j, 1, 1, c->dx / nrm, c->dy / nrm)));
+  lim = fmin(lim, fabs(slope_dir(c, arr, i, j, 1, -1, c->dx / nrm, -c->dy / nrm)));
+  double phi = lim / nG;
+  double xr = node_x(c, r->I) + 0.5 * (r->rx0 + r->rx1);
+  double yr = node_y(c, r->J) + 0.5 * (r->ry0 + r->ry1);
+  return aD + phi * (G1 * (xr - c->xcL[q]) + G2 * (yr - c->ycL[q]));
+}
+
+/* §2.1.1 and §3.3: value of a donor quantity on region r at order 1, 2
+ * (limited linear along the region's direction) or 3 (multidimensional) */
 static double recon(const lr_ref_ctx *c, const region *r, const double *arr, int order) {
   int i = r->di, j = r->dj, q = CI(c, i, j);
   double aD = arr[q];
   if (order == 1) return aD;
+  if (order == 3) return recon_lsq(c, r, arr);
   if (r->type == 0) {
     if (!stencil_pure(c, i, j, 1, 0)) return aD;
     double d = slope_dir(c, arr, i, j, 1, 0, 1.0, 0.0);
@@ -1163,7 +1207,10 @@ static int remap_directcf(lr_ref_ctx *c) {
       c->muA[NI(c, I, J)] = a;
     }
 
-  /* dual remap of the nodal momentum (§2.1.1 dual mesh, §2.3 dual corners) */
+  /* dual remap of the nodal momentum (§2.1.1 dual mesh, §2.3 dual corners);
+   * reading: with the multidimensional reconstruction (order 3) of the cell
+   * quantities, the velocities keep the limited linear one along each
+   * direction */
   if (!c->o.kinematic) {
     int order = c->o.recon_order;
     double nrm = sqrt(c->dx * c->dx + c->dy * c->dy);
@@ -1179,7 +1226,7 @@ static int remap_directcf(lr_ref_ctx *c) {
         double sg = phi > 0.0 ? 1.0 : -1.0;
         int pD = NI(c, D, J);
         double vu = c->uLx[pD], vv = c->uLy[pD];
-        if (order == 2) {
+        if (order >= 2) {
           double df = 0.5 * (c->dpx[NI(c, I - 1, J)] + c->dpx[NI(c, I, J)]);
           double off = 0.5 * (sg * dual_wx(c, D, J) - df);
           vu += dual_slope(c, c->uLx, D, J, 1, 0, 1.0, 0.0) * off;
@@ -1201,7 +1248,7 @@ static int remap_directcf(lr_ref_ctx *c) {
         double sg = phi > 0.0 ? 1.0 : -1.0;
         int pD = NI(c, I, D);
         double vu = c->uLx[pD], vv = c->uLy[pD];
-        if (order == 2) {
+        if (order >= 2) {
           double df = 0.5 * (c->dpy[NI(c, I, J - 1)] + c->dpy[NI(c, I, J)]);
           double off = 0.5 * (sg * dual_wy(c, I, D) - df);
           vu += dual_slope(c, c->uLx, I, D, 0, 1, 0.0, 1.0) * off;
@@ -1231,7 +1278,7 @@ static int remap_directcf(lr_ref_ctx *c) {
         int DI = phi > 0.0 ? i : i + 1, DJ = phi > 0.0 ? j : j + 1;
         double sg = phi > 0.0 ? 1.0 : -1.0;
         double vu = c->uLx[NI(c, DI, DJ)], vv = c->uLy[NI(c, DI, DJ)];
-        if (order == 2) {
+        if (order >= 2) {
           double vx = c->dx / nrm, vy = c->dy / nrm;
           double off = 0.5 * ((sg * dual_wx(c, DI, DJ) - dcx) * vx + (sg * dual_wy(c, DI, DJ) - dcy) * vy);
           vu += dual_slope(c, c->uLx, DI, DJ, 1, 1, vx, vy) * off;
@@ -1246,7 +1293,7 @@ static int remap_directcf(lr_ref_ctx *c) {
         sg = phi > 0.0 ? 1.0 : -1.0;
         vu = c->uLx[NI(c, DI, DJ)];
         vv = c->uLy[NI(c, DI, DJ)];
-        if (order == 2) {
+        if (order >= 2) {
           double vx = c->dx / nrm, vy = -c->dy / nrm;
           double off = 0.5 * ((sg * dual_wx(c, DI, DJ) - dcx) * vx + (-sg * dual_wy(c, DI, DJ) - dcy) * vy);
           vu += dual_slope(c, c->uLx, DI, DJ, 1, -1, vx, vy) * off;

@@ -46,7 +46,9 @@ typedef struct {
   double cfl;             /* CFL number (default 0.5)                            */
   double a1, a2;          /* Wilkins linear / quadratic coefficients (0.5, 1.0)  */
   int precision;          /* ignored by the oracle: always FP64                  */
-  int recon_order;        /* 1 = upwind everywhere, 2 = limited linear (default) */
+  int recon_order;        /* 1 = upwind everywhere, 2 = limited linear along each
+                             direction (default), 3 = the multidimensional
+                             least-squares plane of §3.3 (DirectCF only)         */
   int kinematic;          /* 1 = prescribed node velocities, no forces           */
   double k_eps;           /* material-presence threshold on V/A (default 1e-10)  */
   double fixed_dt;        /* > 0: use this time step instead of the CFL one      */

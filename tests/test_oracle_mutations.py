@@ -74,6 +74,15 @@ MUTATIONS = {
                        "for (int s = 0; s < 2; ++s) {\n        if (is_donor(rs[s], i, j)) v -= rs[s]->vol;"),
     "ad_face_width_one_node": ("double w = 0.5 * (c->dpx[NI(c, I, j)] + c->dpx[NI(c, I, j + 1)]);",
                                "double w = c->dpx[NI(c, I, j)];"),
+    "lsq_limiter_without_diagonals": (
+        "  lim = fmin(lim, fabs(slope_dir(c, arr, i, j, 1, 1, c->dx / nrm, c->dy / nrm)));\n",
+        "\n"),
+    "lsq_gradient_components_swapped": (
+        "return aD + phi * (G1 * (xr - c->xcL[q]) + G2 * (yr - c->ycL[q]));",
+        "return aD + phi * (G2 * (xr - c->xcL[q]) + G1 * (yr - c->ycL[q]));"),
+    "lsq_evaluated_at_region_origin": (
+        "double xr = node_x(c, r->I) + 0.5 * (r->rx0 + r->rx1);",
+        "double xr = node_x(c, r->I);"),
     "order2_next_to_interfaces": (
         "return m >= 0 && c->pure[CI(c, i - si, j - sj)] == m && c->pure[CI(c, i + si, j + sj)] == m;",
         "return m >= 0;"),

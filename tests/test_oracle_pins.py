@@ -466,6 +466,96 @@ def test_diagonal_corner_reconstruction_exact(anti):
             assert mu[J, I] == pytest.approx(d * d * mean, rel=1e-13)
 
 
+# ------------------------------------------ §3.3 multidimensional (order 3) --
+@pytest.mark.parametrize("sx,sy", [(1, 1), (-1, 1)])
+def test_multidimensional_reconstruction_closed_form(sx, sy):
+    """§3.3 multidimensional reconstruction on a linear density rho = a + g.x
+    translated at a constant velocity d per step on unit square cells.  The
+    Lagrangian cells are the Eulerian ones shifted by d, so the least-squares
+    plane over any 3x3 stencil recovers g exactly, the four limited slopes are
+    g.e for e = x, y, v, v_perp (Van Leer of equal slopes), and the limited
+    gradient is phi g with phi = min |g.e| / |g|.  Here g = (0.1, -0.07): the
+    smallest slope is the diagonal one, (0.1 - 0.07)/sqrt(2).  Each region's
+    mass flux is then its volume times a + g.(x_D) + phi g.(x_r - x_D - d),
+    x_r the centre of its flux rectangle (faces and corners alike)."""
+    n = 16
+    a0, g = 5.0, np.array([0.1, -0.07])
+    d = np.array([sx * 0.3, sy * 0.2])
+    p = _uniform_problem(n, n, 1.0, d[0], d[1])
+    xc = np.arange(n) + 0.5
+    X, Y = np.meshgrid(xc, xc)
+    p["rho"][0] = a0 + g[0] * X + g[1] * Y
+    s = _solver(p, kinematic=True, fixed_dt=1.0, recon_order=3)
+    s.step()
+    r2 = np.sqrt(2.0)
+    phi = min(abs(g[0]), abs(g[1]), abs(g.sum()) / r2, abs(g[0] - g[1]) / r2) / np.linalg.norm(g)
+    assert phi == pytest.approx(abs(g.sum()) / r2 / np.linalg.norm(g))
+
+    def value(donor, xr):
+        xD = np.array(donor) + 0.5
+        return a0 + g @ xD + phi * (g @ (xr - xD - d))
+
+    muX, muY = s.stage("muX"), s.stage("muY")
+    mu_c = s.stage("muD" if sx * sy > 0 else "muA")
+    h = 1.0 - abs(d)
+    for J in range(4, n - 4):
+        for I in range(4, n - 4):
+            # x-face (I, J): the rectangle [I, I + dx] x [J + max(0, dy), + h_y]
+            D = (I - 1, J) if d[0] >= 0 else (I, J)
+            xr = np.array([I + 0.5 * d[0], J + max(0.0, d[1]) + 0.5 * h[1]])
+            assert muX[J, I] == pytest.approx(d[0] * h[1] * value(D, xr), rel=1e-13)
+            # y-face (I, J)
+            D = (I, J - 1) if d[1] >= 0 else (I, J)
+            xr = np.array([I + max(0.0, d[0]) + 0.5 * h[0], J + 0.5 * d[1]])
+            assert muY[J, I] == pytest.approx(d[1] * h[0] * value(D, xr), rel=1e-13)
+            # corner at node (I, J): the rectangle between x_p and x_p + d
+            D = (I - (d[0] >= 0), J - (d[1] >= 0))
+            xr = np.array([I, J]) + 0.5 * d
+            flux = abs(d[0] * d[1]) * value(D, xr)
+            assert mu_c[J, I] == pytest.approx(flux if d[0] >= 0 else -flux, rel=1e-13)
+
+
+@pytest.mark.parametrize("nmat,seed", [(2, 13), (3, 14)])
+def test_multidimensional_reconstruction_conservation_and_bounds(nmat, seed):
+    """The multidimensional reconstruction keeps the flux form: per-material
+    masses conserved to 1e-12 over the run, volumes filling the grid,
+    0 <= k <= 1, sum k = 1."""
+    p = inputs.random_mixed(seed, 36, 28, nmat=nmat)
+    s = _solver(p, recon_order=3)
+    area = (p["domain"][1] - p["domain"][0]) * (p["domain"][3] - p["domain"][2])
+    m0 = s.totals()[nmat:2 * nmat]
+    for _ in range(25):
+        s.step()
+        tot = s.totals()
+        assert np.all(np.abs(tot[nmat:2 * nmat] - m0) <= 1e-12 * m0)
+        assert abs(tot[:nmat].sum() - area) < 1e-13 * area
+        k = s.fields("k")["k"]
+        assert k.min() > -1e-13 and k.max() < 1 + 1e-13 and np.abs(k.sum(0) - 1.0).max() < 1e-13
+
+
+def test_multidimensional_reconstruction_sharper_than_upwind():
+    """§3.3: the multidimensional plane, limited, is less diffusive than
+    upwind values on the advected square of §5.1 (L1 distance to the exactly
+    translated square after 40 steps, measured in [0.45, 0.85]^2, clear of
+    what the walls do to the prescribed flow) and makes no new extrema there.
+    Its limiter, the smallest of the four directional slopes, vanishes
+    wherever one direction sees no variation (along the square's sides), so
+    it gains little over upwind here (measured 1.64 against 1.69)."""
+    p = inputs.square_advection(60)
+    xc = (np.arange(60) + 0.5) / 60
+    X, Y = np.meshgrid(xc, xc)
+    inner = (X > 0.45) & (X < 0.85) & (Y > 0.45) & (Y < 0.85)
+    err = {}
+    for order in (1, 3):
+        s = _solver(p, kinematic=True, recon_order=order)
+        n, t = s.run(1.0, max_steps=40)
+        rho = s.fields("rho")["rho"][inner]
+        assert rho.min() >= 0.1 - 1e-12 and rho.max() <= 10.0 + 1e-12
+        sq = ((np.abs(X - 5.0 * t - 0.3) < 0.1) & (np.abs(Y - 5.0 * t - 0.3) < 0.1))[inner]
+        err[order] = np.abs(rho - np.where(sq, 10.0, 0.1)).mean()
+    assert err[3] < err[1], err
+
+
 # --------------------------------------------------------------- contract ----
 def test_set_state_rejects_bad_input():
     from oracle.ref import OracleError
