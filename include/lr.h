@@ -54,7 +54,10 @@ typedef struct {
   double a1, a2;         /* Wilkins linear / quadratic pseudo-viscosity (§1.2); 0.5, 1.0  */
   int precision;         /* LR_FP64 (default) or LR_FP32: FP32 bulk arithmetic and state,
                             FP64 interface, clipping and totals, compensated cell sums    */
-  int recon_order;       /* 1 = upwind everywhere, 2 = limited linear (§2.1.1, §3.3)      */
+  int recon_order;       /* 1 = upwind everywhere, 2 = limited linear along each region's
+                            direction (§2.1.1, §3.3), 3 = the multidimensional least-
+                            squares plane of §3.3 for the cell quantities (DirectCF only;
+                            the nodal velocities keep order 2)                           */
   int kinematic;         /* 1 = node velocities prescribed, no forces, no momentum remap  */
   double k_eps;          /* a material is present where V_a > k_eps * dx*dy; 1e-10
                             (FP32 uses at least 1e-6)                                     */

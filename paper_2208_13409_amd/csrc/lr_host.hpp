@@ -103,7 +103,8 @@ int make_grid(int nx, int ny, int nmat, const lr_eos *eos, const int bc[4], cons
       if (bc[s] != LR_BC_REFLECT) return LR_EINVAL;
   for (int a = 0; a < nmat; ++a)
     if (!(eos[a].gamma > 1.0) || !(eos[a].pinf >= 0.0) || !std::isfinite(eos[a].pinf)) return LR_EINVAL;
-  if (!(o.x1 > o.x0) || !(o.y1 > o.y0) || !(o.cfl > 0) || (o.recon_order != 1 && o.recon_order != 2) ||
+  if (!(o.x1 > o.x0) || !(o.y1 > o.y0) || !(o.cfl > 0) || o.recon_order < 1 || o.recon_order > 3 ||
+      (o.remap == LR_REMAP_AD && o.recon_order == 3) ||
       !(o.k_eps >= 0) || o.fixed_dt < 0 || (o.precision != LR_FP64 && o.precision != LR_FP32) ||
       (o.remap != LR_REMAP_DIRECTCF && o.remap != LR_REMAP_AD))
     return LR_EINVAL;

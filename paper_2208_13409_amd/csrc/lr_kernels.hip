@@ -954,7 +954,9 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   __syncthreads();
 
   const R nrm = sqrt(Dx * Dx + Dy * Dy);
-  const bool o2 = g.recon_order == 2;
+  // order 2: limited linear along each region's direction; order 3: the
+  // multidimensional least-squares plane (§3.3); both form P4's values
+  const bool o2 = g.recon_order >= 2, o3 = g.recon_order == 3;
   // in-tile window of the donors whose regions the tile needs
   auto donor_in = [&](int di, int dj) {
     return di >= i0 - 1 && di <= i0 + TX && dj >= j0 - 1 && dj <= j0 + TY && di >= 0 && dj >= 0 &&
@@ -1020,6 +1022,75 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
         return Dy + R(0.5) * ((sh.ndy[rb + 1][ra] + sh.ndy[rb + 1][ra + 1]) - (sh.ndy[rb][ra] + sh.ndy[rb][ra + 1]));
       };
       const int s = rf.s;
+      if (o3) {
+        // §3.3 multidimensional: the plane over the donor's 3 x 3 records,
+        // its gradient the least-squares fit of the neighbours' values at
+        // their Lagrangian centres (normal equations, cofactor inverse),
+        // scaled to the smallest of the four limited directional slopes,
+        // evaluated at the centre of the region's flux rectangle; order 1
+        // unless all nine records are pure cells of the donor's material
+        bool ok = true;
+#pragma unroll
+        for (int b = -1; b <= 1; ++b)
+#pragma unroll
+          for (int a = -1; a <= 1; ++a) ok = ok && sh.pure[cb + b][ca + a] == pm;
+        if (ok) {
+          const R xD = sh.xc[cb][ca], yD = sh.yc[cb][ca];
+          R s11 = R(0), s12 = R(0), s22 = R(0), br1 = R(0), br2 = R(0), be1 = R(0), be2 = R(0);
+#pragma unroll
+          for (int b = -1; b <= 1; ++b)
+#pragma unroll
+            for (int a = -1; a <= 1; ++a) {
+              if (a == 0 && b == 0) continue;
+              const R X1 = sh.xc[cb + b][ca + a] - xD, X2 = sh.yc[cb + b][ca + a] - yD;
+              const R Ar = sh.rcf[pm][cb + b][ca + a] - rD, Ae = sh.el[pm][cb + b][ca + a] - eD;
+              s11 += X1 * X1; s12 += X1 * X2; s22 += X2 * X2;
+              br1 += X1 * Ar; br2 += X2 * Ar;
+              be1 += X1 * Ae; be2 += X2 * Ae;
+            }
+          const R det = s11 * s22 - s12 * s12;
+          // the centre of the region's flux rectangle (the frame of xc, yc)
+          R xr, yr;
+          if (s < 4) {
+            const bool xf = s < 2;
+            const int I = xf ? rf.di + (s == 1) : rf.di, J = xf ? rf.dj : rf.dj + (s == 3);
+            const int a0 = NA(I), b0 = NB(J);
+            const FaceGeo<R> fg = xf ? face_geo(sh.ndx[b0][a0], sh.ndy[b0][a0], sh.ndx[b0 + 1][a0], sh.ndy[b0 + 1][a0], Dy)
+                                     : face_geo(sh.ndy[b0][a0], sh.ndx[b0][a0], sh.ndy[b0][a0 + 1], sh.ndx[b0][a0 + 1], Dx);
+            xr = xf ? R(I) * Dx + R(0.5) * fg.w : R(I) * Dx + (fg.t0 + R(0.5) * fg.h);
+            yr = xf ? R(J) * Dy + (fg.t0 + R(0.5) * fg.h) : R(J) * Dy + R(0.5) * fg.w;
+          } else {
+            const int cn = s - 4;
+            const int a0 = na + (cn & 1), b0 = nb + (cn >> 1);
+            xr = R(rf.di + (cn & 1)) * Dx + R(0.5) * sh.ndx[b0][a0];
+            yr = R(rf.dj + (cn >> 1)) * Dy + R(0.5) * sh.ndy[b0][a0];
+          }
+          if (det > R(0)) {
+            const R Gr1 = (s22 * br1 - s12 * br2) / det, Gr2 = (s11 * br2 - s12 * br1) / det;
+            const R Ge1 = (s22 * be1 - s12 * be2) / det, Ge2 = (s11 * be2 - s12 * be1) / det;
+            // the four limited slopes: x, y, v, v_perp
+            R limr = R(INFINITY), lime = R(INFINITY);
+#pragma unroll
+            for (int dd = 0; dd < 4; ++dd) {
+              const int si = dd == 1 ? 0 : 1, sj = dd == 0 ? 0 : (dd == 3 ? -1 : 1);
+              const R vx = dd == 0 ? R(1) : (dd == 1 ? R(0) : Dx / nrm);
+              const R vy = dd == 0 ? R(0) : (dd == 1 ? R(1) : (dd == 2 ? Dy / nrm : -Dy / nrm));
+              const int am = ca - si, bmn = cb - sj, ap = ca + si, bp = cb + sj;
+              const R lm = (xD - sh.xc[bmn][am]) * vx + (yD - sh.yc[bmn][am]) * vy;
+              const R lp = (sh.xc[bp][ap] - xD) * vx + (sh.yc[bp][ap] - yD) * vy;
+              limr = fmin(limr, fabs(van_leer_d(rD - sh.rcf[pm][bmn][am], sh.rcf[pm][bp][ap] - rD, lm, lp)));
+              lime = fmin(lime, fabs(van_leer_d(eD - sh.el[pm][bmn][am], sh.el[pm][bp][ap] - eD, lm, lp)));
+            }
+            const R ngr = sqrt(Gr1 * Gr1 + Gr2 * Gr2), nge = sqrt(Ge1 * Ge1 + Ge2 * Ge2);
+            if (ngr > R(0)) vr = rD + (limr / ngr) * (Gr1 * (xr - xD) + Gr2 * (yr - yD));
+            if (nge > R(0)) ve = eD + (lime / nge) * (Ge1 * (xr - xD) + Ge2 * (yr - yD));
+          }
+        }
+        const R mu = vr * fabs(sv);
+        sh.vm[l] = mu;
+        sh.vq[l] = mu * ve;
+        continue;
+      }
       int si, sj;
       R vx, vy, off;
       if (s < 2) {
@@ -1512,7 +1583,9 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
     __syncthreads();
     auto L = [&](int I) { return I - (I0 - 2); };
     auto M_ = [&](int J) { return J - (J0 - 2); };
-    const bool o2 = g.recon_order == 2;
+    // the dual mesh keeps the limited linear values along each direction
+    // with the multidimensional reconstruction of the cell quantities too
+    const bool o2 = g.recon_order >= 2;
     // both velocity components at donor node (la, lb), limited slopes along
     // (sa, sb) projected on (vx, vy), offset `off`
     // Lagrangian position of a staged node: its index times the cell size
