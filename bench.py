@@ -147,8 +147,8 @@ def workload(name):
 
 
 def batch_leg(n_problems, steps, chunk=8, prep_steps=200):
-    """FP32 shock-bubble batch: the autotuner's chunks and `prep_steps`
-    untimed steps (every problem past half its end time, 0.125, by then:
+    """FP32 shock-bubble batch: `prep_steps` untimed steps, the autotuner's
+    chunks among them (every problem past half its end time, 0.125, by then:
     the largest grid needs about 190 steps), then `steps` timed steps (all
     problems take the same number of steps).  The smallest problem's fields
     are compared with the FP64 oracle's after the same steps."""
@@ -156,7 +156,7 @@ def batch_leg(n_problems, steps, chunk=8, prep_steps=200):
 
     from oracle import RefSolver
     from paper_2208_13409_amd import inputs
-    from paper_2208_13409_amd.lr import LR_FP32, Batch
+    from paper_2208_13409_amd.lr import LR_FP32, LR_NSCHED, TILE_SHAPES, Batch
     probs = inputs.shock_bubble_batch(n_problems)
     steps = max(chunk, (steps // chunk) * chunk)
     prep_steps = (prep_steps // chunk) * chunk
@@ -165,12 +165,15 @@ def batch_leg(n_problems, steps, chunk=8, prep_steps=200):
     probe.close()
     b = Batch(nmat=2, precision=LR_FP32, max_slots=len(probs), pool_bytes=pool, chunk_steps=chunk,
               autotune=True)
-    untimed = 5 * chunk + prep_steps  # four chunks timing the candidate schedules, one capturing
+    # the autotuner times each schedule twice (forward, then in reverse); one
+    # more chunk captures the chosen schedule's graph
+    untimed = max(prep_steps, 2 * LR_NSCHED * chunk) + chunk
     ids = [b.submit(p, 1e30, max_steps=untimed + steps, k_eps=1e-6) for p in probs]
     assert all(i is not None for i in ids)
     for _ in range(untimed // chunk):
         b.step()
-    persistent, graph, rates = b.schedule()
+    persistent, graph, tile, rates = b.schedule()
+    assert rates is not None, "the autotuner is still timing"
     t0 = time.perf_counter()
     chunks = 0
     while b.step() > 0:
@@ -198,7 +201,10 @@ def batch_leg(n_problems, steps, chunk=8, prep_steps=200):
             "launch": ("persistent grids" if persistent else "one block per tile of every problem")
                       + (f", one HIP graph per chunk of {chunk} steps" if graph else
                          f", chunks of {chunk} steps launched directly"),
-            "autotuner_cell_steps_per_ms": [round(float(r_), 1) for r_ in rates] if rates is not None else None,
+            "tile": "%dx%d" % TILE_SHAPES[tile],
+            "autotuner_cell_steps_per_ms": {
+                "%dx%d%s%s" % (*TILE_SHAPES[c // 4], "+persistent" if c & 1 else "", "+graph" if c & 2 else ""):
+                round(float(r_), 1) for c, r_ in enumerate(rates)},
             "hbm_bytes_per_cell_update": bpc, "achieved_GBs": value * bpc / 1e9,
             "frac_hbm": value * bpc / 1e9 / HBM_PEAK_GBS,
             "l1_vs_oracle": {"problem": small, "grid": f"{ps['nx']}x{ps['ny']}", "steps": untimed + steps,

@@ -181,11 +181,21 @@ typedef struct {
   int use_graph;        /* 1: replay each chunk from a captured HIP graph        */
   int persistent;       /* 1: grids limited to the blocks resident on the device, each
                            block walking the tile list; 0 (default): one block per tile */
-  int autotune;         /* 1: the first four chunks run under the four schedules
-                           (persistent x use_graph), each timed on the device; the
-                           fastest per cell-step is kept (persistent and use_graph
-                           above are then ignored).  Results do not depend on it. */
+  int autotune;         /* 1: the first chunks time every schedule (persistent x
+                           use_graph x tile, LR_NSCHED of them) on the device, in
+                           one order and then the reverse (a drift of the cost as
+                           the flow develops cancels to first order); the fastest
+                           per cell-step is kept (persistent, use_graph and tile
+                           are then ignored).  Results do not depend on it. */
+  int tile;             /* tile shape of the step kernels: LR_TILE_32x8 (default),
+                           LR_TILE_16x16 or LR_TILE_32x16 (cells per block in x by
+                           y; 32x16 blocks have 512 threads).  Results do not
+                           depend on it. */
 } lr_batch_opts;
+enum { LR_TILE_32x8 = 0, LR_TILE_16x16 = 1, LR_TILE_32x16 = 2 };
+#define LR_NTILE 3
+/* schedules the autotuner times: c = persistent + 2*use_graph + 4*tile */
+#define LR_NSCHED (4 * LR_NTILE)
 typedef struct lr_batch lr_batch;
 
 void lr_batch_default_opts(lr_batch_opts *o);
@@ -227,10 +237,10 @@ int lr_batch_totals(lr_batch *b, long id, double *out);
 /* free the problem's slot and pool range */
 int lr_batch_release(lr_batch *b, long id);
 int lr_batch_running(lr_batch *b);
-/* the schedule in use; rates[4] (may be NULL) receives the cell-steps per ms
- * the autotuner measured for schedules c = persistent + 2*use_graph.
- * LR_EAGAIN while the autotuner is still timing. */
-int lr_batch_schedule(lr_batch *b, int *persistent, int *use_graph, double *rates);
+/* the schedule in use (any pointer may be NULL); rates[LR_NSCHED] receives
+ * the cell-steps per ms the autotuner measured for schedules
+ * c = persistent + 2*use_graph + 4*tile.  LR_EAGAIN while it is still timing. */
+int lr_batch_schedule(lr_batch *b, int *persistent, int *use_graph, int *tile, double *rates);
 const char *lr_batch_last_error(const lr_batch *b);
 void lr_batch_destroy(lr_batch *b);
 

@@ -704,10 +704,12 @@ void ad_step_impl(const Launch &L, int gpar, hipStream_t s, hipEvent_t *ev) {
   if constexpr (sizeof(R) == 8) {
     wide = L.cell_blocks <= kWideMaxTiles;
     if (wide)
-      launch_b(k_lagrange<R, NM, false, true>, dim3(L.cell_blocks), 2 * NTHREADS, s, ev, p, L.cell_map,
-               L.cell_blocks, gpar);
+      launch_b(k_lagrange<R, NM, false, true, TileDefault>, dim3(L.cell_blocks), 2 * NTHREADS, s, ev, p,
+               L.cell_map, L.cell_blocks, gpar);
   }
-  if (!wide) launch(k_lagrange<R, NM, false, false>, dim3(L.cell_blocks), s, ev, p, L.cell_map, L.cell_blocks, gpar);
+  if (!wide)
+    launch(k_lagrange<R, NM, false, false, TileDefault>, dim3(L.cell_blocks), s, ev, p, L.cell_map, L.cell_blocks,
+           gpar);
   for (int pass = 0; pass < 2; ++pass) {
     k_ad_cells<R, NM><<<cb, 256, 0, s>>>(p, gpar, pass);
     k_ad_donor<R, NM><<<cb, 256, 0, s>>>(p, gpar, pass);

@@ -89,7 +89,8 @@ struct lr_batch {
   bool inflight = false;    // a chunk launched by lr_batch_step_begin, not yet ended
   bool chunk_timed = false;  // ... and timed for the autotuner
   long long chunk_cells = 0;
-  StepFn step = nullptr;
+  StepFn step = nullptr;              // the step on the current tile shape
+  StepFn steps[kTileShapes] = {};     // ... on each shape
   std::vector<BatchReq> slots;
   std::unordered_map<long, int> where;  // request id -> slot
   std::deque<long> finished;
@@ -105,10 +106,13 @@ struct lr_batch {
   hipGraphExec_t gexec = nullptr;
   bool graph_ok = false;
   // schedule autotuning: the first chunks run under each candidate schedule
-  // (persistent grid x graph replay), timed with events around the launches
-  static constexpr int kCand = 4;
-  int tune_next = 0;      // next candidate to time (kCand: done)
-  double tune_rate[kCand] = {0, 0, 0, 0};  // cell-steps per ms
+  // (persistent grid x graph replay x tile shape), timed with events around
+  // the launches, in one order and then the reverse
+  static constexpr int kCand = LR_NSCHED;
+  int tune_next = 0;               // next timing, 0 .. 2 kCand (done)
+  double tune_ms[kCand] = {};      // time of the candidate's chunks
+  double tune_work[kCand] = {};    // ... and their cell-steps
+  double tune_rate[kCand] = {};    // cell-steps per ms
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
   std::string err;
 };
@@ -172,7 +176,7 @@ int rebuild_maps(lr_batch *b) {
   long long cmax = 0;
   for (size_t s = 0; s < b->slots.size(); ++s)
     if (b->slots[s].running) {
-      tile_maps(b->slots[s].g, (int)s, nm, cm);
+      tile_maps(b->slots[s].g, (int)s, nm, cm, kTileX[b->o.tile], kTileY[b->o.tile]);
       pl.push_back((int)s);
       cmax = std::max(cmax, (long long)b->slots[s].g.nx * b->slots[s].g.ny);
     }
@@ -246,7 +250,7 @@ int batch_chunk(lr_batch *b) {
   const Launch L{b->dprobs, b->node_map, b->cell_map, b->node_blocks, b->cell_blocks,
                  b->plist,  b->nprob,    b->mix_chunks, b->o.persistent != 0};
   const int n = b->o.chunk_steps;
-  const bool timed = b->o.autotune && b->tune_next < lr_batch::kCand;
+  const bool timed = b->chunk_timed;
   if (!b->o.use_graph) {
     if (timed) HIP_B(b, hipEventRecord(b->tune_ev[0], b->stream));
     for (int st = 0; st < n; ++st) b->step(L, st & 1, b->stream, nullptr);
@@ -277,13 +281,21 @@ int batch_chunk(lr_batch *b) {
   return LR_OK;
 }
 
-// candidate schedule c: bit 0 persistent grid, bit 1 graph replay
+// candidate schedule c: bit 0 persistent grid, bit 1 graph replay, c / 4
+// the tile shape (whose block maps differ: rebuilt before the next chunk)
 void set_schedule(lr_batch *b, int c) {
-  const int pers = c & 1, graph = (c >> 1) & 1;
+  const int pers = c & 1, graph = (c >> 1) & 1, tile = c >> 2;
   if (pers != b->o.persistent || graph != b->o.use_graph) b->graph_ok = false;
+  if (tile != b->o.tile) b->maps_dirty = true;
   b->o.persistent = pers;
   b->o.use_graph = graph;
+  b->o.tile = tile;
+  b->step = b->steps[tile];
 }
+// the candidate of timing k: 0 .. kCand-1, then back down; a cost that
+// drifts linearly over the tuning chunks adds the same to every candidate
+int tune_candidate(int k) { return k < lr_batch::kCand ? k : 2 * lr_batch::kCand - 1 - k; }
+bool tuning(const lr_batch *b) { return b->o.autotune && b->tune_next < 2 * lr_batch::kCand; }
 
 int find_req(lr_batch *b, long id, BatchReq **q) {
   auto it = b->where.find(id);
@@ -307,6 +319,7 @@ void lr_batch_default_opts(lr_batch_opts *o) {
   o->use_graph = 1;
   o->persistent = 0;
   o->autotune = 0;
+  o->tile = LR_TILE_32x8;
 }
 
 void lr_batch_destroy(lr_batch *b) {
@@ -333,7 +346,7 @@ int lr_batch_create(const lr_batch_opts *opts, lr_batch **out) {
   else lr_batch_default_opts(&o);
   if (o.max_slots < 1 || o.max_slots > (1 << 20) || o.pool_bytes < 256 || o.nmat < 1 ||
       o.nmat > LR_MAXMAT || (o.precision != LR_FP64 && o.precision != LR_FP32) ||
-      o.chunk_steps < 2 || (o.chunk_steps & 1))
+      o.chunk_steps < 2 || (o.chunk_steps & 1) || o.tile < 0 || o.tile >= LR_NTILE)
     return LR_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return LR_EDEVICE;
@@ -360,9 +373,10 @@ int lr_batch_create(const lr_batch_opts *opts, lr_batch **out) {
   if (rc == LR_OK) {
     std::memset(b->hctl, 0, sizeof(Ctl) * o.max_slots);
     b->ranges.init(b->o.pool_bytes);
-    b->step = bfp32(b) ? step_fn<float>(o.nmat) : step_fn<double>(o.nmat);
-    if (bfp32(b)) warm_resident<float>(o.nmat);
-    else warm_resident<double>(o.nmat);
+    // every shape's step, its resident block counts queried before any capture
+    for (int t = 0; t < kTileShapes; ++t)
+      b->steps[t] = bfp32(b) ? step_fn_tile<float>(o.nmat, t) : step_fn_tile<double>(o.nmat, t);
+    b->step = b->steps[o.tile];
     if (hipEventRecord(b->stage_ev, b->stream) != hipSuccess) rc = LR_EDEVICE;
   }
   if (rc != LR_OK) {
@@ -451,16 +465,15 @@ int lr_batch_step_begin(lr_batch *b) {
   if (!b) return LR_EINVAL;
   if (b->inflight) return bset(b, LR_EINVAL, "a chunk is already in flight");
   int rc = LR_OK;
+  b->chunk_timed = tuning(b);
+  if (b->chunk_timed) set_schedule(b, tune_candidate(b->tune_next));
   if (b->maps_dirty) rc = rebuild_maps(b);
   if (rc) return rc;
   if (b->node_blocks == 0) return LR_OK;  // nothing runs; the end call only counts
-  b->chunk_timed = b->o.autotune && b->tune_next < lr_batch::kCand;
   b->chunk_cells = 0;
-  if (b->chunk_timed) {
-    set_schedule(b, b->tune_next);
+  if (b->chunk_timed)
     for (const auto &q : b->slots)
       if (q.running) b->chunk_cells += (long long)q.g.nx * q.g.ny;
-  }
   rc = batch_chunk(b);
   if (rc) return rc;
   HIP_B(b, hipMemcpyAsync(b->hctl, b->ctl, sizeof(Ctl) * b->slots.size(), hipMemcpyDeviceToHost,
@@ -489,11 +502,15 @@ int lr_batch_step_end(lr_batch *b, int *n_running) {
   if (b->chunk_timed) {
     float ms = 0.0f;
     HIP_B(b, hipEventElapsedTime(&ms, b->tune_ev[0], b->tune_ev[1]));
-    b->tune_rate[b->tune_next] = ms > 0.0f ? double(b->chunk_cells) * b->o.chunk_steps / ms : 0.0;
-    if (++b->tune_next == lr_batch::kCand) {
+    const int c = tune_candidate(b->tune_next);
+    b->tune_ms[c] += ms;
+    b->tune_work[c] += double(b->chunk_cells) * b->o.chunk_steps;
+    if (++b->tune_next == 2 * lr_batch::kCand) {
       int best = 0;
-      for (int c = 1; c < lr_batch::kCand; ++c)
-        if (b->tune_rate[c] > b->tune_rate[best]) best = c;
+      for (int k = 0; k < lr_batch::kCand; ++k) {
+        b->tune_rate[k] = b->tune_ms[k] > 0.0 ? b->tune_work[k] / b->tune_ms[k] : 0.0;
+        if (b->tune_rate[k] > b->tune_rate[best]) best = k;
+      }
       set_schedule(b, best);
     }
   }
@@ -590,13 +607,14 @@ int lr_batch_release(lr_batch *b, long id) {
   return LR_OK;
 }
 
-int lr_batch_schedule(lr_batch *b, int *persistent, int *use_graph, double *rates) {
+int lr_batch_schedule(lr_batch *b, int *persistent, int *use_graph, int *tile, double *rates) {
   if (!b) return LR_EINVAL;
   if (persistent) *persistent = b->o.persistent;
   if (use_graph) *use_graph = b->o.use_graph;
+  if (tile) *tile = b->o.tile;
   if (rates)
     for (int c = 0; c < lr_batch::kCand; ++c) rates[c] = b->tune_rate[c];
-  return (b->o.autotune && b->tune_next < lr_batch::kCand) ? LR_EAGAIN : LR_OK;
+  return tuning(b) ? LR_EAGAIN : LR_OK;
 }
 
 const char *lr_batch_last_error(const lr_batch *b) { return b ? b->err.c_str() : "null batch"; }

@@ -11,8 +11,20 @@
 namespace lr {
 
 constexpr int MAXMAT = LR_MAXMAT;
-constexpr int TX = 32, TY = 8;  // tile of cells or nodes handled by one 256-thread block
-constexpr int NTHREADS = TX * TY;
+constexpr int NTHREADS = 256;  // block of the kernels that work on lists or whole arrays
+
+// Tile of cells (or nodes) handled by one block of the step kernels, one
+// thread per cell.  The default shape serves single problems; the batch's
+// autotuner also times the others (each compiled in a translation unit of
+// its own).  Every shape computes the same bits: the tile only decides which
+// block forms a value, never how.
+template <int X, int Y>
+struct TileShape {
+  static constexpr int TX = X, TY = Y, NT = X * Y;
+};
+using TileDefault = TileShape<32, 8>;
+constexpr int kTileShapes = LR_NTILE;
+constexpr int kTileX[kTileShapes] = {32, 16, 32}, kTileY[kTileShapes] = {8, 16, 16};
 
 // Problem constants (FP64 whatever the bulk precision).
 struct Grid {
@@ -42,7 +54,8 @@ static_assert(NDT % 64 == 0, "each lane of a wave reads NDT / 64 partials");
 // partials for a grid of nx x ny cells: 32, doubled while there are more
 // than 16 node tiles per partial, at most NDT
 inline int cfl_partials(int nx, int ny) {
-  const long long tiles = (long long)((nx + TX) / TX) * ((ny + TY) / TY);
+  const long long tiles = (long long)((nx + TileDefault::TX) / TileDefault::TX) *
+                          ((ny + TileDefault::TY) / TileDefault::TY);
   int n = 32;
   while (n < NDT && 16ll * n < tiles) n *= 2;
   return n;
@@ -113,6 +126,26 @@ struct Prob {
 struct BlockMap {
   int prob, i0, j0, n;  // n: blocks of this problem (list kernels)
 };
+
+// one step's launches: the block maps of node and cell tiles of every
+// problem; `persistent` limits each grid to the blocks the device holds at
+// once (each block then walks the map)
+struct Launch {
+  const void *probs;
+  const BlockMap *node_map, *cell_map;
+  int node_blocks, cell_blocks;
+  const int *plist;  // the problems of the launch (for the mixed-cell kernel)
+  int nprob;
+  int mix_chunks;    // blocks per problem of the mixed-cell kernel
+  bool persistent;
+  long long cells, nodes;  // of the problem (single-problem launches of the AD remap)
+};
+using StepFn = void (*)(const Launch &, int, hipStream_t, hipEvent_t *);
+// the DirectCF step on the tile shapes other than the default, for a bulk
+// precision (fp32: 1) and a material count; each defined in its own
+// translation unit
+StepFn step_fn_tile16x16(int fp32, int nmat);
+StepFn step_fn_tile32x16(int fp32, int nmat);
 // Workgroups are dispatched to the eight XCDs in turn (block b to XCD b % 8),
 // each XCD with its own L2.  Block b takes map entry xcd_tile(b, n) instead of
 // b, so that each XCD works through a contiguous run of the map and

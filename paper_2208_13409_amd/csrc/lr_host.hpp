@@ -204,12 +204,14 @@ int err_code(int bits, const char **msg) {
   return LR_OK;
 }
 
-// node tiles cover nodes [0, nx] x [0, ny], cell tiles cells [0, nx) x [0, ny)
-void tile_maps(const Grid &g, int prob, std::vector<BlockMap> &nm, std::vector<BlockMap> &cm) {
-  for (int j = 0; j <= g.ny; j += TY)
-    for (int i = 0; i <= g.nx; i += TX) nm.push_back({prob, i, j, 0});
-  for (int j = 0; j < g.ny; j += TY)
-    for (int i = 0; i < g.nx; i += TX) cm.push_back({prob, i, j, 0});
+// node tiles cover nodes [0, nx] x [0, ny], cell tiles cells [0, nx) x [0, ny);
+// tiles of tx x ty
+void tile_maps(const Grid &g, int prob, std::vector<BlockMap> &nm, std::vector<BlockMap> &cm,
+               int tx = TileDefault::TX, int ty = TileDefault::TY) {
+  for (int j = 0; j <= g.ny; j += ty)
+    for (int i = 0; i <= g.nx; i += tx) nm.push_back({prob, i, j, 0});
+  for (int j = 0; j < g.ny; j += ty)
+    for (int i = 0; i < g.nx; i += tx) cm.push_back({prob, i, j, 0});
 }
 
 // initial state from the FP64 staging array [k | rho | e | ux | uy]:

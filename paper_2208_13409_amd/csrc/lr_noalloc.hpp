@@ -88,6 +88,7 @@ __global__ void k_noalloc_setup(Prob<R> P, Prob<R> *dprob, int *plist, int *bits
     *plist = 0;
     *bits = 0;
   }
+  constexpr int TX = TileDefault::TX, TY = TileDefault::TY;
   const int nbx = nx / TX + 1, cbx = (nx + TX - 1) / TX;
   if (b < node_blocks) node_map[b] = BlockMap{0, (b % nbx) * TX, (b / nbx) * TY, 0};
   if (b < cell_blocks) cell_map[b] = BlockMap{0, (b % cbx) * TX, (b / cbx) * TY, 0};
@@ -107,6 +108,7 @@ struct NoallocArgs {
 template <typename R>
 int noalloc_run(const Grid &g, char *base, NoallocArgs &a, NoallocErr &err) {
   const size_t C = (size_t)g.nx * g.ny, N = (size_t)(g.nx + 1) * (g.ny + 1);
+  constexpr int TX = TileDefault::TX, TY = TileDefault::TY;
   const int node_blocks = (g.nx / TX + 1) * (g.ny / TY + 1);
   const int cell_blocks = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
   // layout: control record, descriptor, problem list, check word, block

@@ -20,6 +20,10 @@ LR_OK, LR_EINVAL, LR_ENOMEM, LR_EDEVICE, LR_ENEGATIVE, LR_ENAN, LR_EDT, LR_EAGAI
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 LR_FP64, LR_FP32 = 0, 1
 LR_REMAP_DIRECTCF, LR_REMAP_AD = 0, 1
+LR_TILE_32x8, LR_TILE_16x16, LR_TILE_32x16 = 0, 1, 2
+LR_NTILE = 3
+LR_NSCHED = 4 * LR_NTILE
+TILE_SHAPES = ((32, 8), (16, 16), (32, 16))
 F_RHO, F_P, F_E, F_K, F_RHOA, F_EA, F_PA, F_UX, F_UY, F_VOL, F_MASS, F_IE = (1 << i for i in range(12))
 PER_MAT = {F_K, F_RHOA, F_EA, F_PA, F_VOL, F_MASS, F_IE}
 NODE = {F_UX, F_UY}
@@ -51,7 +55,7 @@ class lr_opts(C.Structure):
 class lr_batch_opts(C.Structure):
     _fields_ = [("max_slots", C.c_int), ("pool_bytes", C.c_size_t), ("nmat", C.c_int),
                 ("precision", C.c_int), ("chunk_steps", C.c_int), ("use_graph", C.c_int),
-                ("persistent", C.c_int), ("autotune", C.c_int)]
+                ("persistent", C.c_int), ("autotune", C.c_int), ("tile", C.c_int)]
 
 
 class LRError(RuntimeError):
@@ -117,7 +121,7 @@ def load():
     lib.lr_batch_totals.argtypes = [vp, C.c_long, dp]
     lib.lr_batch_release.argtypes = [vp, C.c_long]
     lib.lr_batch_running.argtypes = [vp]
-    lib.lr_batch_schedule.argtypes = [vp, P(C.c_int), P(C.c_int), dp]
+    lib.lr_batch_schedule.argtypes = [vp, P(C.c_int), P(C.c_int), P(C.c_int), dp]
     lib.lr_batch_schedule.restype = C.c_int
     lib.lr_batch_last_error.argtypes = [vp]
     lib.lr_batch_last_error.restype = C.c_char_p
@@ -329,12 +333,13 @@ class Batch:
     no room now (LR_EAGAIN)."""
 
     def __init__(self, nmat=2, precision=LR_FP32, max_slots=256, pool_bytes=4 << 30,
-                 chunk_steps=16, use_graph=True, persistent=False, autotune=False, stream=None):
+                 chunk_steps=16, use_graph=True, persistent=False, autotune=False, tile=LR_TILE_32x8,
+                 stream=None):
         self.lib = load()
         o = lr_batch_default_opts()
         o.max_slots, o.pool_bytes, o.nmat, o.precision = int(max_slots), int(pool_bytes), int(nmat), int(precision)
         o.chunk_steps, o.use_graph, o.persistent = int(chunk_steps), int(bool(use_graph)), int(bool(persistent))
-        o.autotune = int(bool(autotune))
+        o.autotune, o.tile = int(bool(autotune)), int(tile)
         self.nmat, self.precision = int(nmat), int(precision)
         h = C.c_void_p()
         rc = self.lib.lr_batch_create(C.byref(o), C.byref(h))
@@ -429,8 +434,9 @@ class Batch:
         return int(self.lib.lr_batch_running(self.h))
 
     def schedule(self):
-        """(persistent, use_graph, measured rates or None while tuning)"""
-        pe, ug = C.c_int(), C.c_int()
-        rates = np.zeros(4)
-        rc = self.lib.lr_batch_schedule(self.h, C.byref(pe), C.byref(ug), _dptr(rates))
-        return bool(pe.value), bool(ug.value), (rates if rc == LR_OK else None)
+        """(persistent, use_graph, tile, measured rates or None while tuning);
+        rates[c] is schedule c = persistent + 2 use_graph + 4 tile"""
+        pe, ug, ti = C.c_int(), C.c_int(), C.c_int()
+        rates = np.zeros(LR_NSCHED)
+        rc = self.lib.lr_batch_schedule(self.h, C.byref(pe), C.byref(ug), C.byref(ti), _dptr(rates))
+        return bool(pe.value), bool(ug.value), int(ti.value), (rates if rc == LR_OK else None)

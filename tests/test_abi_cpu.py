@@ -91,6 +91,10 @@ def test_batch_argument_validation_without_device():
     o = lr.lr_batch_default_opts()
     o.nmat = 0
     assert lib.lr_batch_create(ctypes.byref(o), ctypes.byref(h)) == lr.LR_EINVAL
+    o = lr.lr_batch_default_opts()
+    assert o.tile == lr.LR_TILE_32x8
+    o.tile = lr.LR_NTILE
+    assert lib.lr_batch_create(ctypes.byref(o), ctypes.byref(h)) == lr.LR_EINVAL
     f32 = lib.lr_batch_footprint(64, 64, 2, lr.LR_FP32)
     f64 = lib.lr_batch_footprint(64, 64, 2, lr.LR_FP64)
     big = lib.lr_batch_footprint(128, 128, 2, lr.LR_FP32)

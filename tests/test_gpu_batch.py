@@ -14,7 +14,8 @@ import pytest
 
 from oracle import RefSolver
 from paper_2208_13409_amd import inputs
-from paper_2208_13409_amd.lr import LR_EAGAIN, LR_FP32, LR_FP64, LR_OK, Batch, LRError, Solver
+from paper_2208_13409_amd.lr import (LR_EAGAIN, LR_FP32, LR_FP64, LR_NSCHED, LR_OK, LR_TILE_16x16,
+                                     LR_TILE_32x16, TILE_SHAPES, Batch, LRError, Solver)
 
 pytestmark = pytest.mark.gpu
 
@@ -245,19 +246,50 @@ def test_set_state_device_float32_inputs():
 
 
 def test_autotuned_schedule_keeps_results():
-    """The autotuner times the four launch schedules on the first chunks and
-    keeps the fastest; every schedule runs the same arithmetic."""
+    """The autotuner times the twelve schedules (persistent grid x graph
+    replay x tile shape) on the first chunks, forward then in reverse, and
+    keeps the fastest; every schedule runs the same arithmetic, so the
+    results equal the problems' alone, whatever it chose."""
     ps = problems()
+    steps = 2 * 2 * LR_NSCHED + 6  # the tuning chunks of 2 steps, then three more
     b = Batch(nmat=2, precision=LR_FP32, max_slots=8, pool_bytes=64 << 20, chunk_steps=2, autotune=True)
-    ids = [b.submit(p, 1e30, max_steps=14, k_eps=1e-6) for p in ps]
-    assert b.schedule()[2] is None  # still timing
+    ids = [b.submit(p, 1e30, max_steps=steps, k_eps=1e-6) for p in ps]
+    assert b.schedule()[3] is None  # still timing
+    say(f"autotuner: {LR_NSCHED} schedules over {steps} steps of 4 problems")
     drain(b)
-    persistent, graph, rates = b.schedule()
-    assert rates is not None and np.all(rates > 0)
-    assert int(persistent) + 2 * int(graph) == int(np.argmax(rates))
+    persistent, graph, tile, rates = b.schedule()
+    assert rates is not None and rates.shape == (LR_NSCHED,) and np.all(rates > 0)
+    assert int(persistent) + 2 * int(graph) + 4 * tile == int(np.argmax(rates))
     for p, rid in zip(ps, ids):
-        g, n, _ = alone(p, LR_FP32, steps=14)
+        g, n, _ = alone(p, LR_FP32, steps=steps)
         same_fields(b.fields(rid, *FIELDS), g.fields(*FIELDS), p["name"])
+
+
+@pytest.mark.parametrize("tile", [LR_TILE_16x16, LR_TILE_32x16])
+@pytest.mark.parametrize("precision,nmat,persistent", [(LR_FP64, 3, False), (LR_FP32, 2, True)])
+def test_tile_shapes_give_the_same_bits(tile, precision, nmat, persistent):
+    """The step kernels on 16x16 and 32x16 tiles (the autotuner's other
+    shapes) give the bits of the default 32x8 tiles of a problem alone, on
+    ragged grids smaller and larger than one tile and on one of more than
+    1024 tiles (where the launches skip material at rest)."""
+    sizes = ((40, 24), (33, 65), (96, 17), (15, 9), (700, 400))
+    ps = [inputs.random_mixed(60 + i, nx, ny, nmat=nmat) for i, (nx, ny) in enumerate(sizes)]
+    steps = 10
+    say(f"tile {TILE_SHAPES[tile]} precision {precision} nmat {nmat} persistent {persistent}: against alone")
+    probe = Batch(nmat=nmat, precision=precision, max_slots=1, pool_bytes=1 << 20)
+    pool = sum(probe.footprint(p["nx"], p["ny"]) for p in ps) + (16 << 20)
+    probe.close()
+    b = Batch(nmat=nmat, precision=precision, max_slots=len(ps), pool_bytes=pool, chunk_steps=4,
+              tile=tile, persistent=persistent)
+    kw = dict(k_eps=1e-6) if precision == LR_FP32 else {}
+    ids = [b.submit(p, 1e30, max_steps=steps, **kw) for p in ps]
+    drain(b)
+    assert b.schedule()[2] == tile
+    for p, rid in zip(ps, ids):
+        rc, st, _ = b.status(rid)
+        assert rc == LR_OK and st == steps
+        g, n, _ = alone(p, precision, steps=steps)
+        same_fields(b.fields(rid, *FIELDS), g.fields(*FIELDS), f"{p['name']} on tile {TILE_SHAPES[tile]}")
 
 
 @pytest.mark.parametrize("nmat", [2, 3])
