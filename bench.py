@@ -19,7 +19,8 @@ line carries
       tiles of all problems, under the launch schedule the batch's autotuner
       picked, timed over a window that starts after every problem has run
       past half its end time; with the L1 of its smallest problem against
-      the oracle;
+      the oracle (from the CPU-baseline leg), beside that of the oracle
+      with its state stored in FP32 between steps;
   "triple_point_1792x768": the large triple point in FP64 and FP32 from its
       developed state (t = 1.75), and the L1 of FP32 against FP64 over the
       timed window from the same state;
@@ -38,6 +39,8 @@ line carries
   "cpu_baseline": the FP64 oracle timed on a bounded sample of the plain
       workload on the host's cores (OpenMP over grid rows), with the
       single-threaded figure, the core count and the CPU model beside it.
+      This leg is the only one that runs the oracle: it also forms the
+      other legs' L1 figures against it.
 """
 import argparse
 import hashlib
@@ -52,7 +55,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 W64 = 8
-KERNEL_SOURCES = ("paper_2208_13409_amd/csrc/lr_kernels.hip", "paper_2208_13409_amd/csrc/lr_device.hpp")
+KERNEL_SOURCES = ("paper_2208_13409_amd/csrc/lr_step.hpp", "paper_2208_13409_amd/csrc/lr_device.hpp")
 
 
 def kernel_sources_sha256():
@@ -150,11 +153,9 @@ def batch_leg(n_problems, steps, chunk=8, prep_steps=200):
     """FP32 shock-bubble batch: `prep_steps` untimed steps, the autotuner's
     chunks among them (every problem past half its end time, 0.125, by then:
     the largest grid needs about 190 steps), then `steps` timed steps (all
-    problems take the same number of steps).  The smallest problem's fields
-    are compared with the FP64 oracle's after the same steps."""
-    import numpy as np
-
-    from oracle import RefSolver
+    problems take the same number of steps).  Returns the leg's record and
+    the smallest problem's fields, which the CPU-baseline leg compares with
+    the FP64 oracle's after the same steps."""
     from paper_2208_13409_amd import inputs
     from paper_2208_13409_amd.lr import LR_FP32, LR_NSCHED, TILE_SHAPES, Batch
     probs = inputs.shock_bubble_batch(n_problems)
@@ -185,12 +186,8 @@ def batch_leg(n_problems, steps, chunk=8, prep_steps=200):
         assert rc == 0 and st == untimed + steps, (rid, rc, st)
     small = min(range(len(probs)), key=lambda i: probs[i]["nx"] * probs[i]["ny"])
     ps = probs[small]
-    fg = b.fields(ids[small], "rho", "p")
-    r = RefSolver(ps["nx"], ps["ny"], ps["gammas"], ps["domain"], k_eps=1e-6)
-    r.set_state(0.0, ps["k"], ps["rho"], ps["e"], ps["ux"], ps["uy"])
-    r.run(1e30, max_steps=untimed + steps)
-    fr = r.fields("rho", "p")
-    l1 = {k: float(np.abs(fg[k] - fr[k]).sum() / np.abs(fr[k]).sum()) for k in ("rho", "p")}
+    check = {"problem": ps, "index": small, "steps": untimed + steps, "k_eps": 1e-6,
+             "gpu": b.fields(ids[small], "rho", "p"), "fp32": True}
     cells = sum(p["nx"] * p["ny"] for p in probs)
     value = cells * steps / wall
     bpc = step_bytes(1, 1, 2, 4)
@@ -206,9 +203,7 @@ def batch_leg(n_problems, steps, chunk=8, prep_steps=200):
                 "%dx%d%s%s" % (*TILE_SHAPES[c // 4], "+persistent" if c & 1 else "", "+graph" if c & 2 else ""):
                 round(float(r_), 1) for c, r_ in enumerate(rates)},
             "hbm_bytes_per_cell_update": bpc, "achieved_GBs": value * bpc / 1e9,
-            "frac_hbm": value * bpc / 1e9 / HBM_PEAK_GBS,
-            "l1_vs_oracle": {"problem": small, "grid": f"{ps['nx']}x{ps['ny']}", "steps": untimed + steps,
-                             "rho": l1["rho"], "p": l1["p"]}}
+            "frac_hbm": value * bpc / 1e9 / HBM_PEAK_GBS}, check
 
 
 def serve_leg(n_requests, rate):
@@ -276,6 +271,28 @@ def cpu_baseline(p, steps):
             "single_thread": {"value": v1, "cores": 1, "seconds": el1},
             "host": host,
             "l1_vs_gpu": {"rho": l1["rho"], "p": l1["p"], "steps": n, "gpu_steps": ng}}
+
+
+def oracle_check(chk):
+    """Part of the CPU-baseline leg: the oracle on another leg's problem for
+    the same steps, L1 of density and pressure of the GPU's fields against
+    it; for an FP32 result also the oracle with its state stored in FP32
+    between steps (oracle/fp32_state.py), the floor that single-precision
+    storage sets through the presence-threshold branches."""
+    import numpy as np
+
+    from oracle import RefSolver
+    from oracle.fp32_state import run_stored
+    p, n = chk["problem"], chk["steps"]
+    r = RefSolver(p["nx"], p["ny"], p["gammas"], p["domain"], k_eps=chk["k_eps"])
+    r.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+    r.run(1e30, max_steps=n)
+    fr = r.fields("rho", "p")
+    l1 = lambda a: {k: float(np.abs(a[k] - fr[k]).sum() / np.abs(fr[k]).sum()) for k in ("rho", "p")}
+    out = {"problem": chk["index"], "grid": f"{p['nx']}x{p['ny']}", "steps": n, **l1(chk["gpu"])}
+    if chk.get("fp32"):
+        out["oracle_fp32_state_control"] = l1(run_stored(p, n, {n}, chk["k_eps"])[n])
+    return out
 
 
 def timed_window(g, stream, warmup, steps):
@@ -444,8 +461,9 @@ def main():
         "kernels_avg_us": avg_us,
         "from_rest": from_rest,
     }
+    checks = {}
     if not args.no_batch:
-        out["fp32_batched"] = batch_leg(args.batch_problems, args.batch_steps)
+        out["fp32_batched"], checks["fp32_batched"] = batch_leg(args.batch_problems, args.batch_steps)
         out["fp32_batched"]["vs_fp64_plain"] = out["fp32_batched"]["value"] / value
     if not args.no_large:
         out["triple_point_1792x768"] = large_leg(args.large_steps, 10)
@@ -456,6 +474,8 @@ def main():
         out["parity"] = {"vs": "FP64 oracle", "l1_rho": out["cpu_baseline"]["l1_vs_gpu"]["rho"],
                          "l1_p": out["cpu_baseline"]["l1_vs_gpu"]["p"],
                          "steps": out["cpu_baseline"]["l1_vs_gpu"]["steps"], "t_start": 0.0}
+        for key, chk in checks.items():
+            out[key]["l1_vs_oracle"] = oracle_check(chk)
     print(json.dumps(out), flush=True)
 
 
