@@ -83,6 +83,7 @@ template <typename R>
 struct Dbg {
   R *Q, *S, *VL, *Ph;       // [C], [C], [C], [nmat][C]
   R *volcf, *rhocf;         // [C], [nmat][C]
+  R *dxL, *dyL;             // [C] widths of the Lagrangian cell's rectangle
   R *Wpx, *Wpy, *Wpc;       // per-material signed partial volumes of the regions
 };
 

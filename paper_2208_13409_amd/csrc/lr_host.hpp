@@ -69,6 +69,7 @@ size_t carve_prob(Prob<R> &P, char *base, const Grid &g, bool stages, Ctl *ctl) 
     P.dbg.Q = cv.take<R>(C); P.dbg.S = cv.take<R>(C); P.dbg.VL = cv.take<R>(C);
     P.dbg.Ph = cv.take<R>(m * C); P.dbg.volcf = cv.take<R>(C);
     P.dbg.rhocf = cv.take<R>(m * C);
+    P.dbg.dxL = cv.take<R>(C); P.dbg.dyL = cv.take<R>(C);
     P.dbg.Wpx = cv.take<R>(m * nX); P.dbg.Wpy = cv.take<R>(m * nY);
     P.dbg.Wpc = cv.take<R>(m * N);
   }
@@ -288,7 +289,11 @@ struct lr_ctx {
   int *plist = nullptr;  // device {0}: the problem list of the mixed-cell launch
   StepFn step = nullptr;
   Ctl *ctl = nullptr;   // device
-  Ctl *hctl = nullptr;  // pinned host mirror
+  Ctl *hctl = nullptr;  // pinned host mirror [3]: the context's, then two for
+                        // the chunks of a run in flight
+  hipEvent_t ctl_ev[2] = {nullptr, nullptr};  // ... their copies done
+  hipGraphExec_t chunk_graph[2] = {nullptr, nullptr};  // a full chunk from parity 0 / 1
+  bool graph_failed = false;  // capture refused: chunks are launched directly
   hipStream_t own = nullptr, stream = nullptr;
   std::vector<void *> allocs;
   bool have_state = false;
@@ -384,35 +389,105 @@ int collect_profile(lr_ctx *c) {
   return LR_OK;
 }
 
-// step until done (t_end reached, max_steps taken, or an error); the host
-// checks completion once per chunk of steps
+Launch ctx_launch(const lr_ctx *c) {
+  return Launch{c->dprob,  c->node_map, c->cell_map, c->node_blocks, c->cell_blocks, c->plist, 1,
+                mix_chunks_for((long long)c->g.nx * c->g.ny), false, (long long)c->g.nx * c->g.ny,
+                (long long)(c->g.nx + 1) * (c->g.ny + 1)};
+}
+
+// a full chunk of kChunk steps from parity gpar, replayed from a HIP graph
+// captured at its first use (launched directly if the capture fails)
+int launch_chunk_graph(lr_ctx *c, int gpar) {
+  hipGraphExec_t &x = c->chunk_graph[gpar];
+  if (!x) {
+    const Launch L = ctx_launch(c);
+    hipGraph_t graph = nullptr;
+    HIP_CHECK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    for (int st = 0; st < kChunk; ++st) c->step(L, gpar ^ (st & 1), c->stream, nullptr);
+    const hipError_t le = hipGetLastError();
+    const hipError_t e = hipStreamEndCapture(c->stream, &graph);
+    if (le != hipSuccess || e != hipSuccess || !graph ||
+        hipGraphInstantiate(&x, graph, nullptr, nullptr, 0) != hipSuccess) {
+      x = nullptr;
+      c->graph_failed = true;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    if (!x) {  // the same steps, launched directly
+      for (int st = 0; st < kChunk; ++st) c->step(L, gpar ^ (st & 1), c->stream, nullptr);
+      HIP_CHECK(c, hipGetLastError());
+      return LR_OK;
+    }
+  }
+  HIP_CHECK(c, hipGraphLaunch(x, c->stream));
+  return LR_OK;
+}
+
+// step until done (t_end reached, max_steps taken, or an error).  Chunks of
+// kChunk steps; chunk k+1 is queued before the host reads chunk k's control
+// record (copied after it into one of two pinned mirrors), so the device
+// does not wait for the host between chunks.  A chunk queued after the run
+// ended (at t_end, which the host learns only from the record) does nothing:
+// its kernels see the done flag and return.  Full chunks replay a HIP graph,
+// except while kernels are timed.
 int run_steps(lr_ctx *c, double t_end, long long max_steps) {
   int rc = read_ctl(c);
   if (rc) return rc;
   int gpar = cur_slot(*c->hctl);
+  {
+    const Slot &s0 = c->hctl->slot[gpar];
+    if (max_steps <= 0 || c->hctl->err || s0.t >= t_end) {
+      k_start<<<1, 1, 0, c->stream>>>(c->ctl, t_end, max_steps);
+      HIP_CHECK(c, hipGetLastError());
+      rc = read_ctl(c);
+      return rc ? rc : ctx_err(c, c->hctl->err);
+    }
+  }
   k_start<<<1, 1, 0, c->stream>>>(c->ctl, t_end, max_steps);
   HIP_CHECK(c, hipGetLastError());
-  const Launch L{c->dprob,  c->node_map, c->cell_map, c->node_blocks, c->cell_blocks, c->plist, 1,
-                 mix_chunks_for((long long)c->g.nx * c->g.ny), false, (long long)c->g.nx * c->g.ny,
-                 (long long)(c->g.nx + 1) * (c->g.ny + 1)};
+  const Launch L = ctx_launch(c);
+  for (hipEvent_t &e : c->ctl_ev)
+    if (!e) HIP_CHECK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  long long queued = 0;  // steps launched (at most max_steps)
+  int chunk = 0, pending = 0;
   for (;;) {
-    rc = read_ctl(c);
-    if (rc) return rc;
-    rc = collect_profile(c);
-    if (rc) return rc;
-    const Ctl &k = *c->hctl;
-    const Slot &s = k.slot[cur_slot(k)];
-    if (s.done || k.err) break;
-    const long long left = s.limit - s.step;
-    const long long n = left < kChunk ? left : kChunk;
-    for (long long st = 0; st < n; ++st) {
-      hipEvent_t *ev = nullptr;
-      if (c->prof && c->prof_steps < kChunk) ev = &c->ev[(size_t)c->prof_steps++ * 2 * kKernels];
-      c->step(L, gpar, c->stream, ev);
-      gpar ^= 1;
+    if (queued < max_steps) {
+      const long long left = max_steps - queued;
+      const int n = left < kChunk ? (int)left : kChunk;
+      if (n == kChunk && !c->prof && !c->graph_failed) {
+        rc = launch_chunk_graph(c, gpar);
+        if (rc) return rc;
+      } else {
+        for (int st = 0; st < n; ++st) {
+          hipEvent_t *ev = nullptr;
+          if (c->prof && c->prof_steps < kChunk) ev = &c->ev[(size_t)c->prof_steps++ * 2 * kKernels];
+          c->step(L, gpar ^ (st & 1), c->stream, ev);
+        }
+        HIP_CHECK(c, hipGetLastError());
+      }
+      gpar ^= n & 1;
+      queued += n;
+      const int m = chunk & 1;
+      HIP_CHECK(c, hipMemcpyAsync(c->hctl + 1 + m, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+      HIP_CHECK(c, hipEventRecord(c->ctl_ev[m], c->stream));
+      ++chunk;
+      ++pending;
+      if (c->prof) {  // timed chunks one at a time: the event pairs are reused
+        rc = collect_profile(c);
+        if (rc) return rc;
+      }
+      if (pending < 2 && queued < max_steps) continue;  // keep two chunks in flight
     }
-    HIP_CHECK(c, hipGetLastError());
+    // the oldest chunk in flight: its record says whether the run goes on
+    const int m = (chunk - pending) & 1;
+    HIP_CHECK(c, hipEventSynchronize(c->ctl_ev[m]));
+    --pending;
+    const Ctl &k = c->hctl[1 + m];
+    if (k.slot[cur_slot(k)].done || k.err || (queued >= max_steps && pending == 0)) break;
   }
+  rc = read_ctl(c);  // the record after everything queued
+  if (rc) return rc;
+  rc = collect_profile(c);
+  if (rc) return rc;
   return ctx_err(c, c->hctl->err);
 }
 
@@ -457,6 +532,8 @@ int debug_impl(lr_ctx *c, Prob<R> &P, const std::string &n, double *out) {
   if (n == "P_half") return debug_copy(c, P.dbg.Ph, m * C, out);
   if (n == "volcf") return debug_copy(c, P.dbg.volcf, C, out);
   if (n == "rhocf") return debug_copy(c, P.dbg.rhocf, m * C, out);
+  if (n == "dxL") return debug_copy(c, P.dbg.dxL, C, out);
+  if (n == "dyL") return debug_copy(c, P.dbg.dyL, C, out);
   if (n == "eL") return debug_copy(c, P.eL, m * C, out);
   if (n == "mp") return debug_copy(c, P.mp, N, out);
   if (n == "uhx") return debug_copy(c, P.uhx, N, out);
@@ -504,6 +581,10 @@ void lr_destroy(lr_ctx *c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->ctl_ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipGraphExec_t x : c->chunk_graph)
+    if (x) (void)hipGraphExecDestroy(x);
   for (void *p : c->allocs) (void)hipFree(p);
   if (c->hctl) (void)hipHostFree(c->hctl);
   if (c->own) (void)hipStreamDestroy(c->own);
@@ -531,7 +612,7 @@ int lr_create(int nx, int ny, int nmat, const lr_eos *eos, const int bc[4], cons
   }
   c->stream = c->own;
   int rc = dalloc(c, &c->ctl, 1);
-  if (rc == LR_OK && hipHostMalloc((void **)&c->hctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess)
+  if (rc == LR_OK && hipHostMalloc((void **)&c->hctl, 3 * sizeof(Ctl), hipHostMallocDefault) != hipSuccess)
     rc = LR_ENOMEM;
   if (rc == LR_OK) rc = fp32(c) ? alloc_prob<float>(c, c->pf) : alloc_prob<double>(c, c->pd);
   if (rc == LR_OK) rc = build_maps(c);

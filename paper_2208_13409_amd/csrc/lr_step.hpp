@@ -953,6 +953,10 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
     if (ri == i && rj == j && a >= 2 && b >= 2 && a < TX + 2 && b < TY + 2) {
       if (!(v > R(0))) atomicOr(&ctl->err, ERR_VOLCF);
       if (P.dbg.volcf) stg(P.dbg.volcf + q, v);
+      if (P.dbg.dxL) {  // the widths P4 forms for this cell as a donor
+        stg(P.dbg.dxL + q, Dx + R(0.5) * ((brx + trx) - (blx + tlx)));
+        stg(P.dbg.dyL + q, Dy + R(0.5) * ((tly + try_) - (bly + bry)));
+      }
       if (P.dbg.rhocf)
         for (int m = 0; m < NM; ++m) stg(P.dbg.rhocf + (m * C + q), sh.rcf[m][b][a]);
     }

@@ -72,7 +72,7 @@ def test_stage_parity_one_step(nmat, seed):
     dg, dr = g.step(), r.step()
     assert dg == dr
     for name in ("Q", "S", "volcf", "VL", "mp", "uhx", "uhy", "uLx", "uLy", "eL", "rhocf",
-                 "P_half"):
+                 "P_half", "dxL", "dyL"):
         a, b = g.stage(name), r.stage(name)
         if name in ("eL",):  # energies of absent materials are not defined
             k = r.fields("k")["k"]
