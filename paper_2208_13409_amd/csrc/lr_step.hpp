@@ -1229,16 +1229,31 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
                sh.ndx[nb + 1][na + 1] == R(0) && sh.ndy[nb + 1][na + 1] == R(0);
       }
       // first every region's donor, and the loads of the partial volumes of
-      // the mixed donors (all issued before any is used), then the fluxes
+      // the mixed donors (all issued before any is used); then each region's
+      // fluxes, added at once to the cell's sums.  Each sum takes its terms
+      // in region order; a region adds only to the materials it carries (a
+      // pure donor's to one), the others' terms being zero.
       R sgn[8], wr[8], dirs[8];
       int dd[8], pqs[8], mss[8];
       R wmx[8][NM];  // unset unless the region's donor is mixed
-      R F[8][3 * NM];
-      // FP32: materials that some added region of nonzero volume carries
-      // (bit m); the sums of the others only add zeros and are skipped (a
-      // wave inside one material, or at rest, skips them all).  Not worth
-      // its instructions in the FP64 sums, except for a cell at rest.
-      unsigned used = (sizeof(R) == 4 || rest) ? 0u : ~0u;
+      Acc<R> Va[NM], Ma[NM], Ea[NM];
+#pragma unroll
+      for (int m = 0; m < NM; ++m) {
+        Va[m].init(Vcf[m]);
+        Ma[m].init(M6[m]);
+        Ea[m].init(M6[m] * elc[m]);
+      }
+      // total mass flux of the regions this cell owns (left face, bottom face,
+      // bottom-left corner) for the momentum remap; walls are zero
+      R mx = R(0), my = R(0), mc = R(0);
+      const bool dbg_w = P.dbg.Wpx != nullptr;
+      const int nX = (nx + 1) * ny, nY = nx * (ny + 1), nN = (nx + 1) * (ny + 1);
+      if (dbg_w && rest)
+        for (int m = 0; m < NM; ++m) {
+          stg(P.dbg.Wpx + (m * nX + j * (nx + 1) + i), R(0));
+          stg(P.dbg.Wpy + (m * nY + j * nx + i), R(0));
+          stg(P.dbg.Wpc + (m * nN + j * (nx + 1) + i), R(0));
+        }
       if (!rest) {
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
@@ -1281,12 +1296,12 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       }
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
+        R F[3 * NM];  // this region's V, M, E per material, signed along its orientation
 #pragma unroll
-        for (int k = 0; k < 3 * NM; ++k) F[s][k] = R(0);
+        for (int k = 0; k < 3 * NM; ++k) F[k] = R(0);
         const int pq = pqs[s], d = dd[s];  // donor record, flattened
         const R dir = dirs[s], w = wr[s];
-        if (sizeof(R) == 4 && sgn[s] != R(0) && w > R(0))
-          used |= pq >= 0 ? 1u << (pq & 15) : (pq == -1 ? ~0u : 0u);
+        const R sg = sgn[s];
         if (pq >= 0) {
           const int pm = pq & 15;
           const R rho = (&sh.rcf[pm][0][0])[d], e = (&sh.el[pm][0][0])[d];
@@ -1300,9 +1315,11 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
 #pragma unroll
           for (int m = 0; m < NM; ++m)
             if (m == pm) {
-              F[s][m] = dir * w;
-              F[s][NM + m] = dir * mu;
-              F[s][2 * NM + m] = dir * ep;
+              F[m] = dir * w;
+              F[NM + m] = dir * mu;
+              F[2 * NM + m] = dir * ep;
+              if (sg > R(0)) { Va[m].add(F[m]); Ma[m].add(F[NM + m]); Ea[m].add(F[2 * NM + m]); }
+              else if (sg < R(0)) { Va[m].add(-F[m]); Ma[m].add(-F[NM + m]); Ea[m].add(-F[2 * NM + m]); }
             }
         } else if (pq == -1 && mss[s] >= 0) {
 #pragma unroll
@@ -1310,10 +1327,26 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
             const R wm = wmx[s][m];
             const R mu = wm > R(0) ? (&sh.rcf[m][0][0])[d] * wm : R(0);
             const R ep = wm > R(0) ? mu * (&sh.el[m][0][0])[d] : R(0);
-            F[s][m] = dir * wm;
-            F[s][NM + m] = dir * mu;
-            F[s][2 * NM + m] = dir * ep;
+            F[m] = dir * wm;
+            F[NM + m] = dir * mu;
+            F[2 * NM + m] = dir * ep;
+            if (sg > R(0)) { Va[m].add(F[m]); Ma[m].add(F[NM + m]); Ea[m].add(F[2 * NM + m]); }
+            else if (sg < R(0)) { Va[m].add(-F[m]); Ma[m].add(-F[NM + m]); Ea[m].add(-F[2 * NM + m]); }
           }
+        }
+        if (s == 0 || s == 2 || s == 4) {
+          R f = R(0);
+#pragma unroll
+          for (int m = 0; m < NM; ++m) f += F[NM + m];
+          if (s == 0) mx = f;
+          else if (s == 2) my = f;
+          else mc = f;
+          if (dbg_w)
+            for (int m = 0; m < NM; ++m) {
+              if (s == 0) stg(P.dbg.Wpx + (m * nX + j * (nx + 1) + i), i > 0 ? F[m] : R(0));
+              else if (s == 2) stg(P.dbg.Wpy + (m * nY + j * nx + i), j > 0 ? F[m] : R(0));
+              else stg(P.dbg.Wpc + (m * nN + j * (nx + 1) + i), (i > 0 && j > 0) ? F[m] : R(0));
+            }
         }
       }
       }  // !rest
@@ -1321,23 +1354,9 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       bool bad_nan = false;
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
-        const R M0 = M6[m];
-        Acc<R> V, M, E;
-        V.init(Vcf[m]);
-        M.init(M0);
-        E.init(M0 * elc[m]);
-        if ((used >> m) & 1u) {
-#pragma unroll
-          for (int s = 0; s < 8; ++s) {
-            if (sgn[s] == R(0)) continue;
-            const R w = F[s][m], mu = F[s][NM + m], ep = F[s][2 * NM + m];
-            if (sgn[s] > R(0)) { V.add(w); M.add(mu); E.add(ep); }
-            else { V.add(-w); M.add(-mu); E.add(-ep); }
-          }
-        }
-        Vn[m] = V.get();
-        Mn[m] = M.get();
-        En[m] = E.get();
+        Vn[m] = Va[m].get();
+        Mn[m] = Ma[m].get();
+        En[m] = Ea[m].get();
         stg(Vd + (m * C + q), Vn[m]);
         stg(Md + (m * C + q), Mn[m]);
         stg(Ed + (m * C + q), En[m]);
@@ -1364,28 +1383,9 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       const R rhoc = qdiv(Msum, A);
       const R c2 = rhoc > R(0) ? qdiv(rc2, rhoc) : R(0);
       stg(P.cs + q, c2 > R(0) ? sqrt(c2) : R(0));
-      // total mass flux of the regions this cell owns (left face, bottom face,
-      // bottom-left corner) for the momentum remap; walls are zero
-      R mx = R(0), my = R(0), mc = R(0);
-      if (!rest) {
-#pragma unroll
-        for (int m = 0; m < NM; ++m) {
-          mx += F[0][NM + m];
-          my += F[2][NM + m];
-          mc += F[4][NM + m];
-        }
-      }
       stg(P.MX + (j * (nx + 1) + i), i > 0 ? mx : R(0));
       stg(P.MY + (j * nx + i), j > 0 ? my : R(0));
       stg(P.MC + (j * (nx + 1) + i), (i > 0 && j > 0) ? mc : R(0));
-      if (P.dbg.Wpx) {
-        const int nX = (nx + 1) * ny, nY = nx * (ny + 1), nN = (nx + 1) * (ny + 1);
-        for (int m = 0; m < NM; ++m) {
-          stg(P.dbg.Wpx + (m * nX + j * (nx + 1) + i), (i > 0 && !rest) ? F[0][m] : R(0));
-          stg(P.dbg.Wpy + (m * nY + j * nx + i), (j > 0 && !rest) ? F[2][m] : R(0));
-          stg(P.dbg.Wpc + (m * nN + j * (nx + 1) + i), (i > 0 && j > 0 && !rest) ? F[4][m] : R(0));
-        }
-      }
     }
   }
 }
