@@ -702,6 +702,7 @@ struct RemapShared {
     int slot;
   } mps[NCY][NCX];
   R rcf[NM][NCY][NCX], el[NM][NCY][NCX];
+  R vcfo[TY][TX];  // Vol^{lagCF} of the owned cells (P3 for P6)
   // per region (x-faces, then y-faces, then corners): the order-2 mass and
   // energy fluxes of a pure donor in the window (set for those regions only)
   R vm[NV], vq[NV];
@@ -872,8 +873,8 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   __syncthreads();
 
   // Vol^{lagCF} of the real cell whose BL node is staged at (na, nb):
-  // A + outflow - inflow over W, E, S, N, BL, BR, TL, TR (formed where it is
-  // used, P3 and P6, by the same operations)
+  // A + outflow - inflow over W, E, S, N, BL, BR, TL, TR (formed in P3 for
+  // every record; P6 reads the owned cells' from LDS)
   auto cell_volcf = [&](int na, int nb) {
     R v = A;
     const R xw = sh.xv[nb][na], xe = sh.xv[nb][na + 1], ys = sh.yv[nb][na], yn = sh.yv[nb + 1][na];
@@ -929,6 +930,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
     if (rj != j) yc = (j < 0 ? R(0) : R(2.0 * g.Ly)) - yc;
     sh.xc[b][a] = xc;
     sh.yc[b][a] = yc;
+    if (a >= 2 && b >= 2 && a < TX + 2 && b < TY + 2) sh.vcfo[b - 2][a - 2] = v;
     int np = 0, pm = -1;
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
@@ -964,6 +966,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   __syncthreads();
 
   const R nrm = sqrt(Dx * Dx + Dy * Dy);
+  const R dgx = Dx / nrm, dgy = Dy / nrm;  // unit vector of the main diagonal
   // order 2: limited linear along each region's direction; order 3: the
   // multidimensional least-squares plane (§3.3); both form P4's values
   const bool o2 = g.recon_order >= 2, o3 = g.recon_order == 3;
@@ -1083,8 +1086,8 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
 #pragma unroll
             for (int dd = 0; dd < 4; ++dd) {
               const int si = dd == 1 ? 0 : 1, sj = dd == 0 ? 0 : (dd == 3 ? -1 : 1);
-              const R vx = dd == 0 ? R(1) : (dd == 1 ? R(0) : Dx / nrm);
-              const R vy = dd == 0 ? R(0) : (dd == 1 ? R(1) : (dd == 2 ? Dy / nrm : -Dy / nrm));
+              const R vx = dd == 0 ? R(1) : (dd == 1 ? R(0) : dgx);
+              const R vy = dd == 0 ? R(0) : (dd == 1 ? R(1) : (dd == 2 ? dgy : -dgy));
               const int am = ca - si, bmn = cb - sj, ap = ca + si, bp = cb + sj;
               const R lm = (xD - sh.xc[bmn][am]) * vx + (yD - sh.yc[bmn][am]) * vy;
               const R lp = (sh.xc[bp][ap] - xD) * vx + (sh.yc[bp][ap] - yD) * vy;
@@ -1119,10 +1122,10 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
         const R cdx = sh.ndx[nb + (cn >> 1)][na + (cn & 1)], cdy = sh.ndy[nb + (cn >> 1)][na + (cn & 1)];
         const R sx = cdx >= R(0) ? R(1) : R(-1);
         if (corner_main(cdx, cdy)) {
-          si = 1; sj = 1; vx = Dx / nrm; vy = Dy / nrm;
+          si = 1; sj = 1; vx = dgx; vy = dgy;
           off = (sx * dxL - cdx) * vx + (sx * dyL - cdy) * vy;
         } else {
-          si = 1; sj = -1; vx = Dx / nrm; vy = -Dy / nrm;
+          si = 1; sj = -1; vx = dgx; vy = -dgy;
           off = (sx * dxL - cdx) * vx + (-sx * dyL - cdy) * vy;
         }
       }
@@ -1204,7 +1207,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
 #pragma unroll
           for (int m = 0; m < NM; ++m) elc[m] = ldg(P.eL + (m * C + q));
         } else {
-          v = cell_volcf(NA(i), NB(j));
+          v = sh.vcfo[b][a];
 #pragma unroll
           for (int m = 0; m < NM; ++m) elc[m] = sh.el[m][cb][ca];
         }
@@ -1619,6 +1622,7 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
     auto wxd = [&](int la, int lb) { return Dx + R(0.5) * (sh.dxy[0][lb][la + 1] - sh.dxy[0][lb][la - 1]); };
     auto wyd = [&](int la, int lb) { return Dy + R(0.5) * (sh.dxy[1][lb + 1][la] - sh.dxy[1][lb - 1][la]); };
     const R nrmv = sqrt(Dx * Dx + Dy * Dy);
+    const R dgx = Dx / nrmv, dgy = Dy / nrmv;  // unit vector of the main diagonal
 
     // ---- stage 2: every dual region of the tile once: x-faces, y-faces,
     // then the corners, in one pass.  The anti-diagonal corner fluxes wait in
@@ -1632,6 +1636,14 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
     // 512-thread tiles of small FP64 launches, timed by their slowest tile
     constexpr bool REST = BT == T::NT;
     R ha[IT2 - IT2C][2];
+    // each region's mass flux, kept for stage 3 (written over the primal
+    // fluxes once stage 2 has read them); the anti-diagonal corners' in pa
+    R pm[IT2], pa[IT2 - IT2C];
+#pragma unroll
+    for (int it = 0; it < IT2; ++it) {
+      pm[it] = R(0);
+      if (it >= IT2C) pa[it - IT2C] = R(0);
+    }
 #pragma unroll
     for (int it = 0; it < IT2; ++it) {
       const int l = tid + it * BT;
@@ -1641,6 +1653,7 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
         const int I = I0 + a, J = J0 + b;
         if (I > nx + 1 || J > ny) continue;
         const R phi = R(0.25) * (sh.mx[b][a] + sh.mx[b][a + 1] + sh.mx[b + 1][a] + sh.mx[b + 1][a + 1]);
+        pm[it] = phi;
         if (REST && phi == R(0)) {
           sh.fx[0][l] = R(0);
           sh.fx[1][l] = R(0);
@@ -1660,6 +1673,7 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
         const int I = I0 + a, J = J0 + b;
         if (I > nx || J > ny + 1) continue;
         const R phi = R(0.25) * (sh.my[b][a] + sh.my[b][a + 1] + sh.my[b + 1][a] + sh.my[b + 1][a + 1]);
+        pm[it] = phi;
         if (REST && phi == R(0)) {
           sh.fy[0][k] = R(0);
           sh.fy[1][k] = R(0);
@@ -1686,14 +1700,16 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
                                  sh.dxy[0][M_(j + 1)][L(i)] + sh.dxy[0][M_(j + 1)][L(i + 1)]);
         const R dcy = R(0.25) * (sh.dxy[1][M_(j)][L(i)] + sh.dxy[1][M_(j)][L(i + 1)] +
                                  sh.dxy[1][M_(j + 1)][L(i)] + sh.dxy[1][M_(j + 1)][L(i + 1)]);
+        pm[it] = R(0.25) * (d00 + d10 + d01 + d11);
+        if (it >= IT2C) pa[it >= IT2C ? it - IT2C : 0] = R(0.25) * (a00 + a10 + a01 + a11);
         if (REST && d00 == R(0) && d10 == R(0) && d01 == R(0) && d11 == R(0)) {
           sh.fd[0][k] = R(0);
           sh.fd[1][k] = R(0);
         } else {  // main diagonal: (i,j) -> (i+1,j+1)
-          const R phi = R(0.25) * (d00 + d10 + d01 + d11);
+          const R phi = pm[it];
           const R sg = phi > R(0) ? R(1) : R(-1);
           const int DI = phi > R(0) ? i : i + 1, DJ = phi > R(0) ? j : j + 1;
-          const R vx = Dx / nrmv, vy = Dy / nrmv;
+          const R vx = dgx, vy = dgy;
           R u, v, off = R(0);
           if (o2) off = R(0.5) * ((sg * wxd(L(DI), M_(DJ)) - dcx) * vx + (sg * wyd(L(DI), M_(DJ)) - dcy) * vy);
           recon(L(DI), M_(DJ), 1, 1, vx, vy, off, u, v);
@@ -1706,10 +1722,10 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
             ha[it >= IT2C ? it - IT2C : 0][1] = R(0);
           }
         } else {  // anti-diagonal: (i,j+1) -> (i+1,j)
-          const R phi = R(0.25) * (a00 + a10 + a01 + a11);
+          const R phi = pa[it >= IT2C ? it - IT2C : 0];
           const R sg = phi > R(0) ? R(1) : R(-1);
           const int DI = phi > R(0) ? i : i + 1, DJ = phi > R(0) ? j + 1 : j;
-          const R vx = Dx / nrmv, vy = -Dy / nrmv;
+          const R vx = dgx, vy = -dgy;
           R u, v, off = R(0);
           if (o2) off = R(0.5) * ((sg * wxd(L(DI), M_(DJ)) - dcx) * vx + (-sg * wyd(L(DI), M_(DJ)) - dcy) * vy);
           recon(L(DI), M_(DJ), 1, -1, vx, vy, off, u, v);
@@ -1720,16 +1736,28 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
         }
       }
     }
-    __syncthreads();  // the displacements are read: their storage takes the anti-diagonal fluxes
+    // the displacements and the primal fluxes are read: the displacements'
+    // storage takes the anti-diagonal momentum fluxes, the primal fluxes'
+    // the regions' mass fluxes
+    __syncthreads();
     R *const fa = &sh.dxy[0][0][0];
 #pragma unroll
-    for (int it = IT2C; it < IT2; ++it) {
-      const int k = tid + it * BT - SH::NXF - SH::NYF;
-      if (k < 0 || k >= SH::NCN) continue;
-      const int i = I0 - 1 + k % (TX + 1), j = J0 - 1 + k / (TX + 1);
-      if (i > nx || j > ny) continue;
-      fa[k] = ha[it - IT2C][0];
-      fa[SH::FA + k] = ha[it - IT2C][1];
+    for (int it = 0; it < IT2; ++it) {
+      const int l = tid + it * BT;
+      if (l >= NREG) continue;
+      if (l < SH::NXF) {
+        (&sh.mx[0][0])[l] = pm[it];
+      } else if (l < SH::NXF + SH::NYF) {
+        (&sh.my[0][0])[l - SH::NXF] = pm[it];
+      } else if (it >= IT2C) {  // (always so for a corner)
+        const int k = l - SH::NXF - SH::NYF;
+        (&sh.cd[0][0])[k] = pm[it];
+        (&sh.ca[0][0])[k] = pa[it - IT2C];
+        const int i = I0 - 1 + k % (TX + 1), j = J0 - 1 + k / (TX + 1);
+        if (i > nx || j > ny) continue;
+        fa[k] = ha[it - IT2C][0];
+        fa[SH::FA + k] = ha[it - IT2C][1];
+      }
     }
     __syncthreads();
   }
@@ -1749,28 +1777,17 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
         const int hNW = (b + 1) * (TX + 1) + a, hSE = b * (TX + 1) + a + 1;  // cells (I-1,J), (I,J-1)
         R m = mp3;
         R mu = m * sh.ulx[b + 2][a + 2], mv = m * sh.uly[b + 2][a + 2];  // u^{lag} of the node
-        // mass fluxes of the eight dual regions, as stage 2 forms them
-        auto px = [&](int a_, int b_) {  // dual x-face at staged (a_, b_)
-          return R(0.25) * (sh.mx[b_][a_] + sh.mx[b_][a_ + 1] + sh.mx[b_ + 1][a_] + sh.mx[b_ + 1][a_ + 1]);
-        };
-        auto py = [&](int a_, int b_) {
-          return R(0.25) * (sh.my[b_][a_] + sh.my[b_][a_ + 1] + sh.my[b_ + 1][a_] + sh.my[b_ + 1][a_ + 1]);
-        };
-        auto pd = [&](int a_, int b_) {
-          return R(0.25) * (sh.cd[b_][a_] + sh.cd[b_][a_ + 1] + sh.cd[b_ + 1][a_] + sh.cd[b_ + 1][a_ + 1]);
-        };
-        auto pa = [&](int a_, int b_) {
-          return R(0.25) * (sh.ca[b_][a_] + sh.ca[b_][a_ + 1] + sh.ca[b_ + 1][a_] + sh.ca[b_ + 1][a_ + 1]);
-        };
-        m += px(a, b); mu += sh.fx[0][hW]; mv += sh.fx[1][hW];
-        m -= px(a + 1, b); mu -= sh.fx[0][hE]; mv -= sh.fx[1][hE];
-        m += py(a, b); mu += sh.fy[0][hS]; mv += sh.fy[1][hS];
-        m -= py(a, b + 1); mu -= sh.fy[0][hN]; mv -= sh.fy[1][hN];
-        m += pd(a, b); mu += sh.fd[0][hSW]; mv += sh.fd[1][hSW];
-        m -= pd(a + 1, b + 1); mu -= sh.fd[0][hNE]; mv -= sh.fd[1][hNE];
+        // mass fluxes of the eight dual regions, as stage 2 formed them
+        const R *fmx = &sh.mx[0][0], *fmy = &sh.my[0][0], *fmd = &sh.cd[0][0], *fma = &sh.ca[0][0];
+        m += fmx[hW]; mu += sh.fx[0][hW]; mv += sh.fx[1][hW];
+        m -= fmx[hE]; mu -= sh.fx[0][hE]; mv -= sh.fx[1][hE];
+        m += fmy[hS]; mu += sh.fy[0][hS]; mv += sh.fy[1][hS];
+        m -= fmy[hN]; mu -= sh.fy[0][hN]; mv -= sh.fy[1][hN];
+        m += fmd[hSW]; mu += sh.fd[0][hSW]; mv += sh.fd[1][hSW];
+        m -= fmd[hNE]; mu -= sh.fd[0][hNE]; mv -= sh.fd[1][hNE];
         const R *fa = &sh.dxy[0][0][0];  // anti-diagonal fluxes (x at k, y at FA + k)
-        m += pa(a, b + 1); mu += fa[hNW]; mv += fa[SH::FA + hNW];
-        m -= pa(a + 1, b); mu -= fa[hSE]; mv -= fa[SH::FA + hSE];
+        m += fma[hNW]; mu += fa[hNW]; mv += fa[SH::FA + hNW];
+        m -= fma[hSE]; mu -= fa[hSE]; mv -= fa[SH::FA + hSE];
         if (!(m > R(0))) atomicOr(&ctl->err, ERR_NODEMASS);
         ux = qdiv(mu, m);
         uy = qdiv(mv, m);
