@@ -25,8 +25,10 @@ line carries
       developed state (t = 1.75), and the L1 of FP32 against FP64 over the
       timed window from the same state;
   "serving": a seeded Poisson stream of four-quadrant Riemann problems
-      (grids 128^2..1024^2, FP32, t_end 0.25) served with continuous
-      batching; p50/p99 latency from arrival to result fields on the host;
+      (grids 128^2..1024^2, FP32, t_end 0.25; 1000 requests at 50/s) served
+      with continuous batching; p50/p99 latency from arrival to result fields
+      on the host, overall and per quarter of the arrivals, with the served
+      and the offered cell-updates/s;
   "roofline": the dominant kernel of the plain step: the step's algorithmic
       bytes per cell-update (the persistent state read and written once, 176 B
       for FP64 with three materials) times the cells one launch processes,
@@ -206,22 +208,77 @@ def batch_leg(n_problems, steps, chunk=8, prep_steps=200):
             "frac_hbm": value * bpc / 1e9 / HBM_PEAK_GBS}, check
 
 
+class FourQuadrantStream:
+    """The serving workload's requests, built ahead of their admission by
+    host threads (requests arrive built; the whole stream at once would take
+    tens of GB of host memory).  Read in arrival order."""
+
+    def __init__(self, n, ahead=48, workers=4):
+        from concurrent.futures import ThreadPoolExecutor
+        self.n, self.ahead = n, ahead
+        self.pool = ThreadPoolExecutor(workers)
+        self.futures = {}
+        self.next = 0
+
+    def _build(self, i):
+        from paper_2208_13409_amd import inputs
+        return inputs.four_quadrant(inputs.BASE_SEED + i)
+
+    def __len__(self):
+        return self.n
+
+    def __getitem__(self, i):
+        while self.next < min(self.n, i + self.ahead):
+            self.futures[self.next] = self.pool.submit(self._build, self.next)
+            self.next += 1
+        return self.futures.pop(i).result()
+
+    def warm(self, k):
+        """start building, and wait for the first k"""
+        while self.next < min(self.n, self.ahead):
+            self.futures[self.next] = self.pool.submit(self._build, self.next)
+            self.next += 1
+        for i in range(min(k, self.n)):
+            self.futures[i].result()
+
+    def close(self):
+        self.pool.shutdown(wait=False, cancel_futures=True)
+
+
 def serve_leg(n_requests, rate):
+    """The seeded Poisson stream of four-quadrant problems served with
+    continuous batching: served and offered cell-updates/s (offered = the
+    work of the stream over its arrival span), the share of wall time with a
+    chunk in flight, p50/p99 latency overall and per quarter of the arrivals
+    (a growing backlog shows as latencies growing from quarter to quarter)."""
+    import numpy as np
+
     from paper_2208_13409_amd import inputs
     from paper_2208_13409_amd.lr import LR_FP32, Batch
-    from paper_2208_13409_amd.serve import serve
-    reqs = [inputs.four_quadrant(inputs.BASE_SEED + i) for i in range(n_requests)]
+    from paper_2208_13409_amd.serve import percentile, serve
+    reqs = FourQuadrantStream(n_requests)
+    reqs.warm(8)  # the first requests built before the clock starts
     arrivals = inputs.poisson_arrivals(n_requests, rate=rate)
     b = Batch(nmat=2, precision=LR_FP32, max_slots=64, pool_bytes=16 << 30, chunk_steps=8)
     out = serve(b, reqs, arrivals)
     b.close()
-    served = sum(c * s for c, s in zip(out["cells"], out["steps"]))
-    assert all(rc == 0 for rc in out["rc"])
+    reqs.close()
+    # a failed request stops at its failing step: its steps count as served,
+    # its latency is that of its error report
+    failed = [{"request": i, "grid": int(round(c ** 0.5)), "rc": rc, "steps": st}
+              for i, (rc, c, st) in enumerate(zip(out["rc"], out["cells"], out["steps"])) if rc != 0]
+    work = np.array(out["cells"], dtype=float) * np.array(out["steps"], dtype=float)
+    offered = float(work.sum() / arrivals[-1])
+    lat = np.array(out["latency"])
+    quarters = np.array_split(np.argsort(arrivals), 4)
     return {"p50_s": out["p50"], "p99_s": out["p99"], "requests": n_requests, "rate_per_s": rate,
-            "cell_updates_per_s": out["cell_updates_per_s"], "wall_s": out["wall"],
-            "gpu_busy": out["busy"], "max_running": out["max_running"],
-            "offered_cell_updates_per_s": served / float(arrivals[-1]),
-            "workload": f"four_quadrant stream, first {n_requests} requests, FP32"}
+            "cell_updates_per_s": out["cell_updates_per_s"], "offered_cell_updates_per_s": offered,
+            "served_over_offered": out["cell_updates_per_s"] / offered, "wall_s": out["wall"],
+            "arrival_span_s": float(arrivals[-1]), "gpu_busy": out["busy"], "max_running": out["max_running"],
+            "latency_by_arrival_quarter": [{"p50_s": percentile(lat[q], 50), "p99_s": percentile(lat[q], 99)}
+                                           for q in quarters],
+            "failed_requests": failed,
+            "workload": f"four_quadrant stream, first {n_requests} requests of the seeded stream, FP32"}
 
 
 def host_cpu():
@@ -370,7 +427,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--large-steps", type=int, default=100)
     ap.add_argument("--no-large", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

@@ -95,14 +95,24 @@ struct lr_batch {
   std::unordered_map<long, int> where;  // request id -> slot
   std::deque<long> finished;
   long next_id = 0;
-  // input staging: pinned host and device copies of one request's FP64
-  // arrays, reused once the previous request's set-up kernels ran
-  char *hstage = nullptr;
-  double *dstage = nullptr;
-  size_t stage_bytes = 0;
-  hipEvent_t stage_ev = nullptr;
-  double *outbuf = nullptr;  // outputs
+  // input staging: a ring of pinned host and device buffers, each holding
+  // one request's FP64 arrays until that request's set-up kernels ran; with
+  // a chunk in flight, kStage admissions proceed without waiting for it
+  static constexpr int kStage = 4;
+  char *hstage[kStage] = {};
+  double *dstage[kStage] = {};
+  size_t stage_bytes[kStage] = {};
+  hipEvent_t stage_ev[kStage] = {};
+  int stage_next = 0;
+  // outputs: copied on a stream of their own, so that the results of
+  // finished requests come back while the next chunk runs
+  hipStream_t io = nullptr;
+  hipEvent_t io_wait = nullptr;
+  std::vector<hipEvent_t> ready;  // per slot: recorded after its request's set-up kernels
+  double *outbuf = nullptr;   // device
   size_t outbuf_n = 0;
+  double *houtbuf = nullptr;  // pinned host
+  size_t houtbuf_n = 0;
   hipGraphExec_t gexec = nullptr;
   bool graph_ok = false;
   // schedule autotuning: the first chunks run under each candidate schedule
@@ -141,31 +151,44 @@ size_t prob_bytes(const Grid &g, int precision) {
   return carve_prob(P, nullptr, g, false, nullptr);
 }
 
-int grow_stage(lr_batch *b, size_t bytes) {
-  if (bytes <= b->stage_bytes) return LR_OK;
-  HIP_B(b, hipStreamSynchronize(b->stream));
-  const size_t n = std::max(bytes, b->stage_bytes * 2);
-  if (b->hstage) (void)hipHostFree(b->hstage);
-  if (b->dstage) (void)hipFree(b->dstage);
-  b->hstage = nullptr;
-  b->dstage = nullptr;
-  b->stage_bytes = 0;
-  if (hipHostMalloc((void **)&b->hstage, n, hipHostMallocDefault) != hipSuccess ||
-      hipMalloc((void **)&b->dstage, n) != hipSuccess)
+// staging buffer r, free (its last request's set-up ran) and of `bytes` at least
+int take_stage(lr_batch *b, int r, size_t bytes) {
+  HIP_B(b, hipEventSynchronize(b->stage_ev[r]));
+  if (bytes <= b->stage_bytes[r]) return LR_OK;
+  const size_t n = std::max(bytes, b->stage_bytes[r] * 2);
+  if (b->hstage[r]) (void)hipHostFree(b->hstage[r]);
+  if (b->dstage[r]) (void)hipFree(b->dstage[r]);
+  b->hstage[r] = nullptr;
+  b->dstage[r] = nullptr;
+  b->stage_bytes[r] = 0;
+  if (hipHostMalloc((void **)&b->hstage[r], n, hipHostMallocDefault) != hipSuccess ||
+      hipMalloc((void **)&b->dstage[r], n) != hipSuccess)
     return bset(b, LR_ENOMEM, "input staging");
-  b->stage_bytes = n;
+  b->stage_bytes[r] = n;
   return LR_OK;
 }
 
-int grow_outbuf(lr_batch *b, size_t n) {
-  if (n <= b->outbuf_n) return LR_OK;
-  HIP_B(b, hipStreamSynchronize(b->stream));
-  if (b->outbuf) (void)hipFree(b->outbuf);
-  b->outbuf = nullptr;
-  b->outbuf_n = 0;
-  if (hipMalloc((void **)&b->outbuf, n * sizeof(double)) != hipSuccess)
-    return bset(b, LR_ENOMEM, "output staging");
-  b->outbuf_n = n;
+// output staging: n doubles on the device, nh pinned on the host
+int grow_outbuf(lr_batch *b, size_t n, size_t nh) {
+  if (n <= b->outbuf_n && nh <= b->houtbuf_n) return LR_OK;
+  HIP_B(b, hipStreamSynchronize(b->io));
+  if (n > b->outbuf_n) {
+    if (b->outbuf) (void)hipFree(b->outbuf);
+    b->outbuf = nullptr;
+    b->outbuf_n = 0;
+    if (hipMalloc((void **)&b->outbuf, n * sizeof(double)) != hipSuccess)
+      return bset(b, LR_ENOMEM, "output staging");
+    b->outbuf_n = n;
+  }
+  if (nh > b->houtbuf_n) {
+    const size_t m = std::max(nh, 2 * b->houtbuf_n);
+    if (b->houtbuf) (void)hipHostFree(b->houtbuf);
+    b->houtbuf = nullptr;
+    b->houtbuf_n = 0;
+    if (hipHostMalloc((void **)&b->houtbuf, m * sizeof(double), hipHostMallocDefault) != hipSuccess)
+      return bset(b, LR_ENOMEM, "output staging");
+    b->houtbuf_n = m;
+  }
   return LR_OK;
 }
 
@@ -217,17 +240,18 @@ int batch_admit(lr_batch *b, int s, BatchReq &q, Prob<R> &P, const double *const
   if (rc) return rc;
   const size_t nd = 3 * nm * C + 2 * N;
   const size_t bytes = nd * sizeof(double) + sizeof(Ctl) + sizeof(Prob<R>) + 512;
-  rc = grow_stage(b, bytes);
+  const int r = b->stage_next;
+  b->stage_next = (r + 1) % lr_batch::kStage;
+  rc = take_stage(b, r, bytes);
   if (rc) return rc;
-  HIP_B(b, hipEventSynchronize(b->stage_ev));  // the previous admission consumed the staging
-  double *hk = reinterpret_cast<double *>(b->hstage);
+  double *hk = reinterpret_cast<double *>(b->hstage[r]);
   const size_t cnt[5] = {nm * C, nm * C, nm * C, N, N};
   size_t off = 0;
   for (int a = 0; a < 5; ++a) {
     std::memcpy(hk + off, in[a], cnt[a] * sizeof(double));
     off += cnt[a];
   }
-  char *tail = b->hstage + ((nd * sizeof(double) + 255) & ~size_t(255));
+  char *tail = b->hstage[r] + ((nd * sizeof(double) + 255) & ~size_t(255));
   Ctl *hc = reinterpret_cast<Ctl *>(tail);
   *hc = initial_ctl(0.0, t_end, limit);
   Prob<R> *hp = reinterpret_cast<Prob<R> *>(tail + ((sizeof(Ctl) + 255) & ~size_t(255)));
@@ -235,13 +259,14 @@ int batch_admit(lr_batch *b, int s, BatchReq &q, Prob<R> &P, const double *const
   b->hctl[s] = *hc;
   q.ctl0 = *hc;
   q.fresh = b->inflight;
-  HIP_B(b, hipMemcpyAsync(b->dstage, hk, nd * sizeof(double), hipMemcpyHostToDevice, b->stream));
+  HIP_B(b, hipMemcpyAsync(b->dstage[r], hk, nd * sizeof(double), hipMemcpyHostToDevice, b->stream));
   HIP_B(b, hipMemcpyAsync(b->ctl + s, hc, sizeof(Ctl), hipMemcpyHostToDevice, b->stream));
   HIP_B(b, hipMemcpyAsync(static_cast<char *>(b->dprobs) + s * b->prob_size, hp, sizeof(Prob<R>),
                           hipMemcpyHostToDevice, b->stream));
-  launch_init<R>(P, b->dstage, b->stream);
+  launch_init<R>(P, b->dstage[r], b->stream);
   HIP_B(b, hipGetLastError());
-  HIP_B(b, hipEventRecord(b->stage_ev, b->stream));
+  HIP_B(b, hipEventRecord(b->stage_ev[r], b->stream));
+  HIP_B(b, hipEventRecord(b->ready[s], b->stream));
   return LR_OK;
 }
 
@@ -297,6 +322,19 @@ void set_schedule(lr_batch *b, int c) {
 int tune_candidate(int k) { return k < lr_batch::kCand ? k : 2 * lr_batch::kCand - 1 - k; }
 bool tuning(const lr_batch *b) { return b->o.autotune && b->tune_next < 2 * lr_batch::kCand; }
 
+// the output stream waits for the work on request q (slot s): a running
+// request's, everything queued on the batch stream; another's, its set-up
+// kernels (chunks that ran it were waited for when it finished)
+int io_after(lr_batch *b, const BatchReq &q, int s) {
+  if (q.running) {
+    HIP_B(b, hipEventRecord(b->io_wait, b->stream));
+    HIP_B(b, hipStreamWaitEvent(b->io, b->io_wait, 0));
+  } else {
+    HIP_B(b, hipStreamWaitEvent(b->io, b->ready[s], 0));
+  }
+  return LR_OK;
+}
+
 int find_req(lr_batch *b, long id, BatchReq **q) {
   auto it = b->where.find(id);
   if (it == b->where.end()) return bset(b, LR_EINVAL, "unknown request id");
@@ -325,15 +363,23 @@ void lr_batch_default_opts(lr_batch_opts *o) {
 void lr_batch_destroy(lr_batch *b) {
   if (!b) return;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
+  if (b->io) (void)hipStreamSynchronize(b->io);
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-  if (b->stage_ev) (void)hipEventDestroy(b->stage_ev);
-  for (hipEvent_t e : b->tune_ev)
+  for (int r = 0; r < lr_batch::kStage; ++r) {
+    if (b->stage_ev[r]) (void)hipEventDestroy(b->stage_ev[r]);
+    if (b->dstage[r]) (void)hipFree(b->dstage[r]);
+    if (b->hstage[r]) (void)hipHostFree(b->hstage[r]);
+  }
+  for (hipEvent_t e : b->ready)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : {b->tune_ev[0], b->tune_ev[1], b->io_wait})
     if (e) (void)hipEventDestroy(e);
   for (void *p : {(void *)b->pool, b->dprobs, (void *)b->ctl, (void *)b->node_map,
-                  (void *)b->cell_map, (void *)b->dstage, (void *)b->outbuf, (void *)b->plist})
+                  (void *)b->cell_map, (void *)b->outbuf, (void *)b->plist})
     if (p) (void)hipFree(p);
   if (b->hctl) (void)hipHostFree(b->hctl);
-  if (b->hstage) (void)hipHostFree(b->hstage);
+  if (b->houtbuf) (void)hipHostFree(b->houtbuf);
+  if (b->io) (void)hipStreamDestroy(b->io);
   if (b->own) (void)hipStreamDestroy(b->own);
   delete b;
 }
@@ -359,9 +405,15 @@ int lr_batch_create(const lr_batch_opts *opts, lr_batch **out) {
   b->slots.resize(o.max_slots);
   int rc = LR_OK;
   if (hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&b->stage_ev, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&b->io, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->io_wait, hipEventDisableTiming) != hipSuccess ||
       hipEventCreate(&b->tune_ev[0]) != hipSuccess || hipEventCreate(&b->tune_ev[1]) != hipSuccess)
     rc = LR_EDEVICE;
+  for (int r = 0; rc == LR_OK && r < lr_batch::kStage; ++r)
+    if (hipEventCreateWithFlags(&b->stage_ev[r], hipEventDisableTiming) != hipSuccess) rc = LR_EDEVICE;
+  b->ready.assign(o.max_slots, nullptr);
+  for (int s = 0; rc == LR_OK && s < o.max_slots; ++s)
+    if (hipEventCreateWithFlags(&b->ready[s], hipEventDisableTiming) != hipSuccess) rc = LR_EDEVICE;
   b->stream = b->own;
   if (rc == LR_OK && (hipMalloc((void **)&b->pool, b->o.pool_bytes) != hipSuccess ||
                       hipMalloc(&b->dprobs, b->prob_size * o.max_slots) != hipSuccess ||
@@ -377,7 +429,15 @@ int lr_batch_create(const lr_batch_opts *opts, lr_batch **out) {
     for (int t = 0; t < kTileShapes; ++t)
       b->steps[t] = bfp32(b) ? step_fn_tile<float>(o.nmat, t) : step_fn_tile<double>(o.nmat, t);
     b->step = b->steps[o.tile];
-    if (hipEventRecord(b->stage_ev, b->stream) != hipSuccess) rc = LR_EDEVICE;
+    // every event recorded once, so that waiting on one never waits on nothing
+    for (int r = 0; rc == LR_OK && r < lr_batch::kStage; ++r)
+      if (hipEventRecord(b->stage_ev[r], b->stream) != hipSuccess) rc = LR_EDEVICE;
+    // staging and output buffers for requests up to about 128 x 128 cells,
+    // allocated now: an allocation while a chunk is in flight can wait for it
+    for (int r = 0; rc == LR_OK && r < lr_batch::kStage; ++r) rc = take_stage(b, r, size_t(1) << 20);
+    if (rc == LR_OK) rc = grow_outbuf(b, size_t(1) << 17, size_t(1) << 17);
+    for (int s = 0; rc == LR_OK && s < o.max_slots; ++s)
+      if (hipEventRecord(b->ready[s], b->stream) != hipSuccess) rc = LR_EDEVICE;
   }
   if (rc != LR_OK) {
     lr_batch_destroy(b);
@@ -392,7 +452,6 @@ int lr_batch_bind_stream(lr_batch *b, void *hip_stream) {
   if (b->inflight) return bset(b, LR_EINVAL, "a chunk is in flight: end it first");
   HIP_B(b, hipStreamSynchronize(b->stream));
   b->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : b->own;
-  HIP_B(b, hipEventRecord(b->stage_ev, b->stream));
   return LR_OK;
 }
 
@@ -576,11 +635,17 @@ int lr_batch_get_fields(lr_batch *b, long id, unsigned mask, double *const *out)
   int rc = find_req(b, id, &q);
   if (rc) return rc;
   const Grid &g = q->g;
-  rc = grow_outbuf(b, std::max((size_t)g.nmat * g.nx * g.ny, (size_t)(g.nx + 1) * (g.ny + 1)));
+  size_t nh = 0;
+  for (unsigned bit = 1; bit <= LR_F_IE; bit <<= 1)
+    if (mask & bit) nh += field_count(g, bit);
+  rc = grow_outbuf(b, std::max((size_t)g.nmat * g.nx * g.ny, (size_t)(g.nx + 1) * (g.ny + 1)), nh);
   if (rc) return rc;
-  const int buf = cur_slot(b->hctl[b->where[id]]);
-  return bfp32(b) ? fields_out<float>(q->pf, buf, mask, out, b->outbuf, b->stream, b->err)
-                  : fields_out<double>(q->pd, buf, mask, out, b->outbuf, b->stream, b->err);
+  const int s = b->where[id];
+  const int buf = cur_slot(b->hctl[s]);
+  rc = io_after(b, *q, s);
+  if (rc) return rc;
+  return bfp32(b) ? fields_out<float>(q->pf, buf, mask, out, b->outbuf, b->houtbuf, b->io, b->err)
+                  : fields_out<double>(q->pd, buf, mask, out, b->outbuf, b->houtbuf, b->io, b->err);
 }
 
 int lr_batch_totals(lr_batch *b, long id, double *out) {
@@ -588,9 +653,12 @@ int lr_batch_totals(lr_batch *b, long id, double *out) {
   BatchReq *q = nullptr;
   const int rc = find_req(b, id, &q);
   if (rc) return rc;
-  const int buf = cur_slot(b->hctl[b->where[id]]);
-  return bfp32(b) ? totals_out<float>(q->pf, buf, out, b->stream, b->err)
-                  : totals_out<double>(q->pd, buf, out, b->stream, b->err);
+  const int s = b->where[id];
+  const int buf = cur_slot(b->hctl[s]);
+  const int rw = io_after(b, *q, s);
+  if (rw) return rw;
+  return bfp32(b) ? totals_out<float>(q->pf, buf, out, b->io, b->err)
+                  : totals_out<double>(q->pd, buf, out, b->io, b->err);
 }
 
 int lr_batch_release(lr_batch *b, long id) {
@@ -598,9 +666,13 @@ int lr_batch_release(lr_batch *b, long id) {
   BatchReq *q = nullptr;
   const int rc = find_req(b, id, &q);
   if (rc) return rc;
-  // launches still queued may read the problem: free its range after them
-  HIP_B(b, hipStreamSynchronize(b->stream));
-  if (q->running) b->maps_dirty = true;
+  // launches still queued may read a running problem: free its range after
+  // them.  A request that is not running is in no queued launch, and its
+  // set-up kernels are ahead of any later admission's on the batch stream.
+  if (q->running) {
+    HIP_B(b, hipStreamSynchronize(b->stream));
+    b->maps_dirty = true;
+  }
   b->ranges.give(q->off, q->bytes);
   b->where.erase(id);
   *q = BatchReq{};

@@ -228,14 +228,26 @@ void launch_init(const Prob<R> &P, const double *dk, hipStream_t s) {
   k_dt_bound<R><<<nb, 256, 0, s>>>(P, 0);
 }
 
+// doubles of field `bit` of a grid
+inline size_t field_count(const Grid &g, unsigned bit) {
+  const size_t C = (size_t)g.nx * g.ny, N = (size_t)(g.nx + 1) * (g.ny + 1);
+  const bool node = bit == LR_F_UX || bit == LR_F_UY;
+  const bool per = bit == LR_F_K || bit == LR_F_RHOA || bit == LR_F_EA || bit == LR_F_PA ||
+                   bit == LR_F_VOL || bit == LR_F_MASS || bit == LR_F_IE;
+  return node ? N : (per ? g.nmat * C : C);
+}
+
 // fields of the state in buffer `buf` into host arrays, through `stage`
-// (device, at least max(nmat*C, N) doubles)
+// (device, at least max(nmat*C, N) doubles) and, when given, `hstage`
+// (pinned host memory for all the fields asked for: the copies then run
+// asynchronously on `s` alone, and the host copies out after them)
 template <typename R>
 int fields_out(const Prob<R> &P, int buf, unsigned mask, double *const *out, double *stage,
-               hipStream_t s, std::string &err) {
+               double *hstage, hipStream_t s, std::string &err) {
   const Grid &g = P.g;
-  const size_t C = (size_t)g.nx * g.ny, N = (size_t)(g.nx + 1) * (g.ny + 1);
+  const size_t N = (size_t)(g.nx + 1) * (g.ny + 1);
   int slot = 0;
+  size_t off = 0;
   for (unsigned bit = 1; bit <= LR_F_IE; bit <<= 1) {
     if (!(mask & bit)) continue;
     double *o = out[slot++];
@@ -243,15 +255,23 @@ int fields_out(const Prob<R> &P, int buf, unsigned mask, double *const *out, dou
       err = "null output pointer";
       return LR_EINVAL;
     }
-    const bool node = bit == LR_F_UX || bit == LR_F_UY;
-    const bool per = bit == LR_F_K || bit == LR_F_RHOA || bit == LR_F_EA || bit == LR_F_PA ||
-                     bit == LR_F_VOL || bit == LR_F_MASS || bit == LR_F_IE;
-    const size_t n = node ? N : (per ? g.nmat * C : C);
+    const size_t n = field_count(g, bit);
     k_fields<R><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(P, buf, bit, stage);
     HIP_TRY(err, hipGetLastError());
-    HIP_TRY(err, hipMemcpyAsync(o, stage, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(err, hipMemcpyAsync(hstage ? hstage + off : o, stage, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    off += n;
   }
   HIP_TRY(err, hipStreamSynchronize(s));
+  if (hstage) {
+    slot = 0;
+    off = 0;
+    for (unsigned bit = 1; bit <= LR_F_IE; bit <<= 1) {
+      if (!(mask & bit)) continue;
+      const size_t n = field_count(g, bit);
+      std::memcpy(out[slot++], hstage + off, n * sizeof(double));
+      off += n;
+    }
+  }
   return LR_OK;
 }
 
@@ -741,8 +761,8 @@ int lr_get_fields(lr_ctx *c, unsigned mask, double *const *out) {
   int rc = read_ctl(c);
   if (rc) return rc;
   const int buf = cur_slot(*c->hctl);
-  return fp32(c) ? fields_out<float>(c->pf, buf, mask, out, c->outbuf, c->stream, c->err)
-                 : fields_out<double>(c->pd, buf, mask, out, c->outbuf, c->stream, c->err);
+  return fp32(c) ? fields_out<float>(c->pf, buf, mask, out, c->outbuf, nullptr, c->stream, c->err)
+                 : fields_out<double>(c->pd, buf, mask, out, c->outbuf, nullptr, c->stream, c->err);
 }
 
 int lr_totals(lr_ctx *c, double *out) {

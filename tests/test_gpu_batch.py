@@ -174,6 +174,55 @@ def test_admission_while_a_chunk_is_in_flight():
     assert b.step_end() == 0  # none in flight: only counts
 
 
+def test_admissions_and_results_overlap_a_chunk():
+    """With a long chunk in flight, three requests are admitted (the staging
+    ring holds their inputs: no submit waits for the chunk) and a request
+    that finished before it is copied back and released (on the output
+    stream); all of that takes a fraction of the chunk's time, and every
+    result equals the problem alone.  (The batch's first copy during a chunk
+    pays one-time set-up costs of the runtime and is not timed.)"""
+    import time
+    big = inputs.random_mixed(71, 1024, 768, nmat=2)
+    small = [inputs.random_mixed(72 + s, 40, 32, nmat=2) for s in range(5)]
+    probe = Batch(nmat=2, precision=LR_FP64, max_slots=1, pool_bytes=1 << 20)
+    pool = probe.footprint(1024, 768) + 5 * probe.footprint(40, 32) + (16 << 20)
+    probe.close()
+    b = Batch(nmat=2, precision=LR_FP64, max_slots=6, pool_bytes=pool, chunk_steps=16)
+    firsts = [b.submit(p, 1e30, max_steps=4) for p in small[:2]]
+    rb = b.submit(big, 1e30, max_steps=64)
+    b.step()  # chunk 1: the two small requests finish in it
+    drained = b.poll()
+    assert sorted(drained) == sorted(firsts)
+    b.step_begin()  # chunk 2: the first copy during a chunk
+    f0 = b.fields(firsts[0], *FIELDS)
+    b.release(firsts[0])
+    b.step_end()
+    say("admissions and a result copy while a 16-step chunk of 1024x768 FP64 runs")
+    b.step_begin()  # chunk 3, timed
+    t0 = time.perf_counter()
+    ids = [b.submit(p, 1e30, max_steps=8) for p in small[2:]]
+    t_sub = time.perf_counter() - t0
+    f1 = b.fields(firsts[1], *FIELDS)
+    t_fld = time.perf_counter() - t0 - t_sub
+    b.release(firsts[1])
+    host = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    b.step_end()
+    wait = time.perf_counter() - t1
+    say(f"submits {t_sub * 1e3:.2f} ms, fields {t_fld * 1e3:.2f} ms, all {host * 1e3:.2f} ms; "
+        f"then the chunk's rest {wait * 1e3:.2f} ms")
+    assert all(i is not None for i in ids)
+    assert host < 0.5 * (host + wait), f"host work {host * 1e3:.1f} ms, chunk rest {wait * 1e3:.1f} ms"
+    done = drain(b)
+    assert sorted(done) == sorted(ids + [rb])
+    for f, p in zip((f0, f1), small[:2]):
+        g, _, _ = alone(p, LR_FP64, steps=4)
+        same_fields(f, g.fields(*FIELDS), "request copied during a chunk")
+    for p, rid in zip(small[2:], ids):
+        g, _, _ = alone(p, LR_FP64, steps=8)
+        same_fields(b.fields(rid, *FIELDS), g.fields(*FIELDS), p["name"])
+
+
 def test_pool_full_is_eagain_then_fits_after_release():
     p = inputs.random_mixed(41, 64, 64)
     probe = Batch(nmat=2, precision=LR_FP32, max_slots=4, pool_bytes=1 << 20)
