@@ -1360,6 +1360,16 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
         Vn[m] = Va[m].get();
         Mn[m] = Ma[m].get();
         En[m] = Ea[m].get();
+        if constexpr (sizeof(R) == 4) {
+          // FP32: a material below the presence threshold that the update
+          // leaves with a negative volume, mass or energy is removed from the
+          // cell.  Such values are rounding residues (about 1e-8 of a cell in
+          // single precision); left in place, the cell's volume change
+          // Vol^{lagCF}/A scales them step after step, and over hundreds of
+          // steps of expansion they grow past the negativity tolerance.
+          if (!present(g, Vn[m]) && (Vn[m] < R(0) || Mn[m] < R(0) || En[m] < R(0)))
+            Vn[m] = Mn[m] = En[m] = R(0);
+        }
         stg(Vd + (m * C + q), Vn[m]);
         stg(Md + (m * C + q), Mn[m]);
         stg(Ed + (m * C + q), En[m]);

@@ -61,3 +61,24 @@ def test_fp32_through_presence_flips():
     nm = len(p["gammas"])
     # masses of each material (Kahan sums in FP32) agree to single precision
     np.testing.assert_allclose(tg[nm:2 * nm], tr[nm:2 * nm], rtol=1e-5)
+
+
+def test_fp32_negative_traces_are_removed():
+    """Request 384 of the seeded four-quadrant stream (544 x 544): in FP32 a
+    rounding residue of material 0 below the presence threshold, scaled by
+    its cell's volume change step after step, reached V/A = -1e-5 (the FP32
+    negativity tolerance) at step 709 of 745 when it was kept.  Absent
+    materials left negative by an update are removed from the cell in FP32,
+    and the run reaches t_end with the per-material masses of the FP64 run."""
+    from paper_2208_13409_amd import inputs
+    from paper_2208_13409_amd.lr import LR_FP64
+    r = inputs.four_quadrant(inputs.BASE_SEED + 384)
+    print(f"{r['name']} FP32 and FP64 to t_end", flush=True)
+    tot = {}
+    for prec in (LR_FP32, LR_FP64):
+        g = Solver(r["nx"], r["ny"], r["gammas"], r["domain"], precision=prec)
+        g.set_state(0.0, r["k"], r["rho"], r["e"], r["ux"], r["uy"])
+        n, t = g.run(r["t_end"])
+        assert t == r["t_end"]
+        tot[prec] = g.totals()
+    np.testing.assert_allclose(tot[LR_FP32][2:4], tot[LR_FP64][2:4], rtol=1e-6)
