@@ -65,6 +65,12 @@ typedef struct {
   int stages;            /* 1 = keep the intermediates of each step for lr_debug_get      */
   int remap;             /* LR_REMAP_DIRECTCF (default) or LR_REMAP_AD; batches and
                             lr_run_noalloc run DirectCF only                              */
+  int mix_list;          /* initial capacity (cells) of the list of mixed cells; 0
+                            (default): the larger of nx*ny/32, 256 and twice the mixed
+                            cells of the initial state.  A step that finds more mixed
+                            cells stops before it changes the state; the list grows
+                            and the step runs again (lr_run_noalloc: the largest list
+                            its workspace holds, no growth)                              */
 } lr_opts;
 
 /* field mask bits for lr_get_fields, in the order the output pointers are
@@ -263,8 +269,8 @@ void lr_batch_destroy(lr_batch *b);
  *   hip_stream: the hipStream_t to run on (NULL: the null stream);
  *   steps_out, t_out (may be NULL): steps taken and time reached;
  *   errbuf[errlen] (may be NULL): the failure text.
- * A problem whose arrays do not fit in the workspace (about 460 bytes per
- * cell for FP64 with 3 materials, so up to about 140,000 cells) is LR_ENOMEM,
+ * A problem whose arrays do not fit in the workspace (about 265 bytes per
+ * cell for FP64 with 3 materials, so up to about 240,000 cells) is LR_ENOMEM,
  * with the sizes in errbuf.  Every call on a device shares that device's
  * workspace, and the workspace keeps the last call's contents: calls that
  * overlap on one device (other host threads, other streams) race, so callers

@@ -63,7 +63,8 @@ struct BatchReq {
   bool fresh = false;
   Ctl ctl0{};
   int rc = LR_OK;
-  size_t off = 0, bytes = 0;
+  size_t off = 0, bytes = 0;            // the problem's pool range
+  size_t list_off = 0, list_bytes = 0;  // ... and its mixed-cell list's (grows)
   Grid g{};
   Prob<double> pd{};
   Prob<float> pf{};
@@ -150,6 +151,38 @@ size_t prob_bytes(const Grid &g, int precision) {
   Prob<double> P;
   return carve_prob(P, nullptr, g, false, nullptr);
 }
+size_t list_bytes_of(const Grid &g, int precision, int cap) {
+  return precision == LR_FP32 ? list_bytes<float>(g, cap) : list_bytes<double>(g, cap);
+}
+
+// request q (slot s) found more mixed cells than its list holds: a larger
+// list from the pool, the descriptor on the device and the control record
+// restored to the start of the step that stopped (see run_steps).  No pool
+// range large enough: the request fails with LR_ENOMEM.
+template <typename R>
+int batch_list_grow(lr_batch *b, int s, BatchReq &q, Prob<R> &P) {
+  Ctl &k = b->hctl[s];
+  const int par = cur_slot(k);
+  const int cap = mix_cap_grown(q.g, P.mix_cap, k.slot[par].nmix);
+  const size_t nb = list_bytes<R>(q.g, cap);
+  size_t off = 0;
+  if (!b->ranges.take(nb, &off)) return LR_ENOMEM;
+  b->ranges.give(q.list_off, q.list_bytes);  // no chunk is in flight: nothing reads it
+  q.list_off = off;
+  q.list_bytes = nb;
+  carve_list(P, b->pool + off, q.g, cap);
+  // chunks start at launch parity 0: the stopped step's slot becomes the
+  // problem's parity-0 slot (the steps after it in the chunk did not count)
+  P.flip = par;
+  k.err = 0;
+  k.slot[par].nmix = 0;
+  k.slot[par].done = 0;
+  HIP_B(b, hipMemcpyAsync(static_cast<char *>(b->dprobs) + s * b->prob_size, &P, sizeof(Prob<R>),
+                          hipMemcpyHostToDevice, b->stream));
+  HIP_B(b, hipMemcpyAsync(b->ctl + s, &k, sizeof(Ctl), hipMemcpyHostToDevice, b->stream));
+  HIP_B(b, hipStreamSynchronize(b->stream));  // the host copies are read before they change
+  return LR_OK;
+}
 
 // staging buffer r, free (its last request's set-up ran) and of `bytes` at least
 int take_stage(lr_batch *b, int r, size_t bytes) {
@@ -232,10 +265,11 @@ int rebuild_maps(lr_batch *b) {
 
 template <typename R>
 int batch_admit(lr_batch *b, int s, BatchReq &q, Prob<R> &P, const double *const in[5], double t_end,
-                long long limit) {
+                long long limit, int cap) {
   const Grid &g = q.g;
   const size_t C = (size_t)g.nx * g.ny, N = (size_t)(g.nx + 1) * (g.ny + 1), nm = g.nmat;
   carve_prob(P, b->pool + q.off, g, false, b->ctl + s);
+  carve_list(P, b->pool + q.list_off, g, cap);
   int rc = clear_prob(P, b->stream, b->err);
   if (rc) return rc;
   const size_t nd = 3 * nm * C + 2 * N;
@@ -461,7 +495,7 @@ size_t lr_batch_footprint(int nx, int ny, int nmat, int precision) {
   g.nx = nx;
   g.ny = ny;
   g.nmat = nmat;
-  return prob_bytes(g, precision);
+  return prob_bytes(g, precision) + list_bytes_of(g, precision, mix_cap_initial(g, 0));
 }
 
 int lr_batch_submit(lr_batch *b, int nx, int ny, const lr_eos *eos, const lr_opts *opts, double t_end,
@@ -491,18 +525,27 @@ int lr_batch_submit(lr_batch *b, int nx, int ny, const lr_eos *eos, const lr_opt
     }
   if (s < 0) return bset(b, LR_EAGAIN, "no free slot");
   const size_t bytes = prob_bytes(g, b->o.precision);
-  size_t off = 0;
+  const int cap = mix_cap_initial(g, count_mixed_host(g, k));
+  const size_t lbytes = list_bytes_of(g, b->o.precision, cap);
+  size_t off = 0, loff = 0;
   if (!b->ranges.take(bytes, &off)) return bset(b, LR_EAGAIN, "no pool range large enough");
+  if (!b->ranges.take(lbytes, &loff)) {
+    b->ranges.give(off, bytes);
+    return bset(b, LR_EAGAIN, "no pool range large enough");
+  }
   BatchReq &q = b->slots[s];
   q = BatchReq{};
   q.g = g;
   q.off = off;
   q.bytes = bytes;
+  q.list_off = loff;
+  q.list_bytes = lbytes;
   const double *in[5] = {k, rho, e, ux, uy};
-  const int rc = bfp32(b) ? batch_admit<float>(b, s, q, q.pf, in, t_end, max_steps)
-                          : batch_admit<double>(b, s, q, q.pd, in, t_end, max_steps);
+  const int rc = bfp32(b) ? batch_admit<float>(b, s, q, q.pf, in, t_end, max_steps, cap)
+                          : batch_admit<double>(b, s, q, q.pd, in, t_end, max_steps, cap);
   if (rc != LR_OK) {
     b->ranges.give(off, bytes);
+    b->ranges.give(loff, lbytes);
     q = BatchReq{};
     return rc;
   }
@@ -577,6 +620,15 @@ int lr_batch_step_end(lr_batch *b, int *n_running) {
     BatchReq &q = b->slots[s];
     if (!q.running) continue;
     const Ctl &k = b->hctl[s];
+    if (k.err == ERR_MIXCAP) {  // a step stopped for a larger list: grow it, the request goes on
+      const int rg = bfp32(b) ? batch_list_grow<float>(b, (int)s, q, q.pf)
+                              : batch_list_grow<double>(b, (int)s, q, q.pd);
+      if (rg == LR_OK) {
+        ++running;
+        continue;
+      }
+      if (rg != LR_ENOMEM) return rg;
+    }
     if (k.slot[cur_slot(k)].done || k.err) {
       const char *msg = "";
       q.rc = err_code(k.err, &msg);
@@ -674,6 +726,7 @@ int lr_batch_release(lr_batch *b, long id) {
     b->maps_dirty = true;
   }
   b->ranges.give(q->off, q->bytes);
+  b->ranges.give(q->list_off, q->list_bytes);
   b->where.erase(id);
   *q = BatchReq{};
   return LR_OK;

@@ -39,6 +39,7 @@ struct Grid {
   double pinf[MAXMAT];  // stiffened-gas pi (0: perfect gas)
   int ndt;  // CFL partial minima the problem uses (a power of two, 32..NDT)
   int remap;  // LR_REMAP_DIRECTCF or LR_REMAP_AD
+  int mix_list;  // requested initial capacity of the mixed-cell list (0: automatic)
 };
 
 // Device-side time control.  Step n of a problem reads slot[n & 1 ^ flip];
@@ -115,7 +116,7 @@ struct Prob {
   R *cs;                          // [C] sound speed of the updated state
   R *MX, *MY, *MC;                // signed total mass flux of x-faces, y-faces, corners
   int *mix_cell, *mix_slot;       // compacted mixed cells; cell -> list position or -1
-  int mix_cap;
+  int mix_cap;                    // capacity of mix_cell and mix_W (grows on overflow)
   R *mix_W;                       // [mix_cap][8][nmat] outflow partial volumes (formed in
                                   // FP64, stored in the bulk precision)
   Ctl *ctl;

@@ -51,9 +51,7 @@ size_t carve_prob(Prob<R> &P, char *base, const Grid &g, bool stages, Ctl *ctl) 
   P.eL = cv.take<R>(m * C);
   P.cs = cv.take<R>(C);
   P.MX = cv.take<R>(nX); P.MY = cv.take<R>(nY); P.MC = cv.take<R>(N);
-  P.mix_cell = cv.take<int>(C); P.mix_slot = cv.take<int>(C);
-  P.mix_cap = (int)C;
-  P.mix_W = cv.take<R>(C * 8 * m);
+  P.mix_slot = cv.take<int>(C);  // the list itself (mix_cell, mix_W) is carved by carve_list
   if (g.remap == LR_REMAP_AD) {
     const size_t nF = std::max(nX, nY);
     AdArrays<R> &a = P.ad;
@@ -75,6 +73,45 @@ size_t carve_prob(Prob<R> &P, char *base, const Grid &g, bool stages, Ctl *ctl) 
   }
   P.ctl = ctl;
   return (cv.off + 255) & ~size_t(255);
+}
+
+// The list of mixed cells and their outflow partial volumes, sized to need:
+// a separate allocation (or pool range) that grows when a step finds more
+// mixed cells than it holds.
+inline long long count_mixed_host(const Grid &g, const double *k) {
+  const size_t C = (size_t)g.nx * g.ny;
+  long long n = 0;
+  for (size_t q = 0; q < C; ++q) {
+    int np = 0;
+    for (int a = 0; a < g.nmat; ++a) np += k[a * C + q] > g.k_eps;
+    n += np >= 2;
+  }
+  return n;
+}
+// initial capacity: as asked, else the larger of C/32, 256 and twice the
+// mixed cells of the initial state (at most C)
+inline int mix_cap_initial(const Grid &g, long long nmix0) {
+  const long long C = (long long)g.nx * g.ny;
+  const long long cap = g.mix_list > 0 ? g.mix_list : std::max(std::max(C / 32, 256ll), 2 * nmix0);
+  return (int)std::min(cap, C);
+}
+// capacity after a step needed `need` entries
+inline int mix_cap_grown(const Grid &g, int cap, long long need) {
+  const long long C = (long long)g.nx * g.ny;
+  return (int)std::min(C, std::max(2ll * cap, need + need / 4 + 64));
+}
+template <typename R>
+size_t carve_list(Prob<R> &P, char *base, const Grid &g, int cap) {
+  Carver cv{base};
+  P.mix_cell = cv.take<int>((size_t)cap);
+  P.mix_W = cv.take<R>((size_t)cap * 8 * g.nmat);
+  P.mix_cap = cap;
+  return (cv.off + 255) & ~size_t(255);
+}
+template <typename R>
+size_t list_bytes(const Grid &g, int cap) {
+  Prob<R> P{};
+  return carve_list(P, nullptr, g, cap);
 }
 
 // wall regions are never written: keep them zero (outside any graph)
@@ -107,7 +144,7 @@ int make_grid(int nx, int ny, int nmat, const lr_eos *eos, const int bc[4], cons
   if (!(o.x1 > o.x0) || !(o.y1 > o.y0) || !(o.cfl > 0) || o.recon_order < 1 || o.recon_order > 3 ||
       (o.remap == LR_REMAP_AD && o.recon_order == 3) ||
       !(o.k_eps >= 0) || o.fixed_dt < 0 || (o.precision != LR_FP64 && o.precision != LR_FP32) ||
-      (o.remap != LR_REMAP_DIRECTCF && o.remap != LR_REMAP_AD))
+      (o.remap != LR_REMAP_DIRECTCF && o.remap != LR_REMAP_AD) || o.mix_list < 0)
     return LR_EINVAL;
   g = Grid{};
   g.nx = nx; g.ny = ny; g.nmat = nmat;
@@ -116,6 +153,7 @@ int make_grid(int nx, int ny, int nmat, const lr_eos *eos, const int bc[4], cons
   g.Lx = o.x1 - o.x0; g.Ly = o.y1 - o.y0;
   g.x0 = o.x0; g.x1 = o.x1; g.y0 = o.y0; g.y1 = o.y1;
   g.remap = o.remap;
+  g.mix_list = o.mix_list;
   g.cfl = o.cfl; g.a1 = o.a1; g.a2 = o.a2; g.k_eps = o.k_eps; g.fixed_dt = o.fixed_dt;
   // FP32 rounding leaves residues of about 1e-7 of a cell behind a material
   // that moved out: presence and negativity thresholds above that level
@@ -314,6 +352,7 @@ struct lr_ctx {
   hipEvent_t ctl_ev[2] = {nullptr, nullptr};  // ... their copies done
   hipGraphExec_t chunk_graph[2] = {nullptr, nullptr};  // a full chunk from parity 0 / 1
   bool graph_failed = false;  // capture refused: chunks are launched directly
+  char *list_mem = nullptr;   // the mixed-cell list (its own allocation: it grows)
   hipStream_t own = nullptr, stream = nullptr;
   std::vector<void *> allocs;
   bool have_state = false;
@@ -352,6 +391,25 @@ int dalloc(lr_ctx *c, T **p, size_t n) {
 
 bool fp32(const lr_ctx *c) { return c->o.precision == LR_FP32; }
 
+// the context's mixed-cell list with room for `cap` cells (the old one
+// freed: nothing may be queued that reads it), and the device descriptor
+template <typename R>
+int ctx_list(lr_ctx *c, Prob<R> &P, int cap) {
+  HIP_CHECK(c, hipStreamSynchronize(c->stream));
+  if (c->list_mem) (void)hipFree(c->list_mem);
+  c->list_mem = nullptr;
+  if (hipMalloc((void **)&c->list_mem, list_bytes<R>(c->g, cap)) != hipSuccess)
+    return set_err(c, LR_ENOMEM, "mixed-cell list");
+  carve_list(P, c->list_mem, c->g, cap);
+  HIP_CHECK(c, hipMemcpyAsync(c->dprob, &P, sizeof(Prob<R>), hipMemcpyHostToDevice, c->stream));
+  HIP_CHECK(c, hipStreamSynchronize(c->stream));
+  return LR_OK;
+}
+int ctx_list_grow(lr_ctx *c, int cap) {
+  return fp32(c) ? ctx_list<float>(c, c->pf, cap) : ctx_list<double>(c, c->pd, cap);
+}
+int ctx_list_cap(const lr_ctx *c) { return fp32(c) ? c->pf.mix_cap : c->pd.mix_cap; }
+
 template <typename R>
 int alloc_prob(lr_ctx *c, Prob<R> &P) {
   const size_t bytes = carve_prob(P, nullptr, c->g, c->o.stages != 0, c->ctl);
@@ -363,9 +421,9 @@ int alloc_prob(lr_ctx *c, Prob<R> &P) {
   Prob<R> *d = nullptr;
   if (dalloc(c, &d, 1)) return LR_ENOMEM;
   c->dprob = d;
-  HIP_CHECK(c, hipMemcpyAsync(d, &P, sizeof(Prob<R>), hipMemcpyHostToDevice, c->own));
+  HIP_CHECK(c, hipStreamSynchronize(c->own));
   c->step = step_fn<R>(c->g.nmat, c->g.remap);
-  return LR_OK;
+  return ctx_list<R>(c, P, mix_cap_initial(c->g, 0));
 }
 
 int build_maps(lr_ctx *c) {
@@ -449,6 +507,13 @@ int launch_chunk_graph(lr_ctx *c, int gpar) {
 // ended (at t_end, which the host learns only from the record) does nothing:
 // its kernels see the done flag and return.  Full chunks replay a HIP graph,
 // except while kernels are timed.
+//
+// A step that finds more mixed cells than the list holds sets ERR_MIXCAP in
+// its Lagrange kernel; the step's other kernels and every later one then
+// return at once, so the state and the step's control slot are those of the
+// step's start, except the slot's mixed-cell count and done flag (the later
+// steps, returning, mark both slots done).  The list grows to the count the
+// step found, the record is restored and the run goes on from that step.
 int run_steps(lr_ctx *c, double t_end, long long max_steps) {
   int rc = read_ctl(c);
   if (rc) return rc;
@@ -467,47 +532,61 @@ int run_steps(lr_ctx *c, double t_end, long long max_steps) {
   const Launch L = ctx_launch(c);
   for (hipEvent_t &e : c->ctl_ev)
     if (!e) HIP_CHECK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  long long queued = 0;  // steps launched (at most max_steps)
-  int chunk = 0, pending = 0;
+  long long left = max_steps;  // steps still to launch
   for (;;) {
-    if (queued < max_steps) {
-      const long long left = max_steps - queued;
-      const int n = left < kChunk ? (int)left : kChunk;
-      if (n == kChunk && !c->prof && !c->graph_failed) {
-        rc = launch_chunk_graph(c, gpar);
-        if (rc) return rc;
-      } else {
-        for (int st = 0; st < n; ++st) {
-          hipEvent_t *ev = nullptr;
-          if (c->prof && c->prof_steps < kChunk) ev = &c->ev[(size_t)c->prof_steps++ * 2 * kKernels];
-          c->step(L, gpar ^ (st & 1), c->stream, ev);
+    long long queued = 0;  // steps launched in this pass (at most left)
+    int chunk = 0, pending = 0;
+    for (;;) {
+      if (queued < left) {
+        const long long rest = left - queued;
+        const int n = rest < kChunk ? (int)rest : kChunk;
+        if (n == kChunk && !c->prof && !c->graph_failed) {
+          rc = launch_chunk_graph(c, gpar);
+          if (rc) return rc;
+        } else {
+          for (int st = 0; st < n; ++st) {
+            hipEvent_t *ev = nullptr;
+            if (c->prof && c->prof_steps < kChunk) ev = &c->ev[(size_t)c->prof_steps++ * 2 * kKernels];
+            c->step(L, gpar ^ (st & 1), c->stream, ev);
+          }
+          HIP_CHECK(c, hipGetLastError());
         }
-        HIP_CHECK(c, hipGetLastError());
+        gpar ^= n & 1;
+        queued += n;
+        const int m = chunk & 1;
+        HIP_CHECK(c, hipMemcpyAsync(c->hctl + 1 + m, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+        HIP_CHECK(c, hipEventRecord(c->ctl_ev[m], c->stream));
+        ++chunk;
+        ++pending;
+        if (c->prof) {  // timed chunks one at a time: the event pairs are reused
+          rc = collect_profile(c);
+          if (rc) return rc;
+        }
+        if (pending < 2 && queued < left) continue;  // keep two chunks in flight
       }
-      gpar ^= n & 1;
-      queued += n;
-      const int m = chunk & 1;
-      HIP_CHECK(c, hipMemcpyAsync(c->hctl + 1 + m, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
-      HIP_CHECK(c, hipEventRecord(c->ctl_ev[m], c->stream));
-      ++chunk;
-      ++pending;
-      if (c->prof) {  // timed chunks one at a time: the event pairs are reused
-        rc = collect_profile(c);
-        if (rc) return rc;
-      }
-      if (pending < 2 && queued < max_steps) continue;  // keep two chunks in flight
+      // the oldest chunk in flight: its record says whether the run goes on
+      const int m = (chunk - pending) & 1;
+      HIP_CHECK(c, hipEventSynchronize(c->ctl_ev[m]));
+      --pending;
+      const Ctl &k = c->hctl[1 + m];
+      if (k.slot[cur_slot(k)].done || k.err || (queued >= left && pending == 0)) break;
     }
-    // the oldest chunk in flight: its record says whether the run goes on
-    const int m = (chunk - pending) & 1;
-    HIP_CHECK(c, hipEventSynchronize(c->ctl_ev[m]));
-    --pending;
-    const Ctl &k = c->hctl[1 + m];
-    if (k.slot[cur_slot(k)].done || k.err || (queued >= max_steps && pending == 0)) break;
+    rc = read_ctl(c);  // the record after everything queued
+    if (rc) return rc;
+    rc = collect_profile(c);
+    if (rc) return rc;
+    Ctl &k = *c->hctl;
+    if (k.err != ERR_MIXCAP) break;
+    const int par = cur_slot(k);
+    rc = ctx_list_grow(c, mix_cap_grown(c->g, ctx_list_cap(c), k.slot[par].nmix));
+    if (rc) return rc;
+    k.err = 0;
+    k.slot[par].nmix = 0;
+    k.slot[par].done = 0;
+    HIP_CHECK(c, hipMemcpyAsync(c->ctl, c->hctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+    gpar = par;
+    left = k.slot[par].limit - k.slot[par].step;
   }
-  rc = read_ctl(c);  // the record after everything queued
-  if (rc) return rc;
-  rc = collect_profile(c);
-  if (rc) return rc;
   return ctx_err(c, c->hctl->err);
 }
 
@@ -605,6 +684,7 @@ void lr_destroy(lr_ctx *c) {
     if (e) (void)hipEventDestroy(e);
   for (hipGraphExec_t x : c->chunk_graph)
     if (x) (void)hipGraphExecDestroy(x);
+  if (c->list_mem) (void)hipFree(c->list_mem);
   for (void *p : c->allocs) (void)hipFree(p);
   if (c->hctl) (void)hipHostFree(c->hctl);
   if (c->own) (void)hipStreamDestroy(c->own);
@@ -664,6 +744,11 @@ int lr_set_state(lr_ctx *c, double t, const double *k, const double *rho, const 
   const char *msg = "";
   const int chk = check_state_host(g, k, rho, e, ux, uy, &msg);
   if (chk) return set_err(c, chk, msg);
+  const int cap = mix_cap_initial(g, count_mixed_host(g, k));
+  if (cap > ctx_list_cap(c)) {
+    const int rl = ctx_list_grow(c, cap);
+    if (rl) return rl;
+  }
   double *dk = nullptr;
   if (hipMalloc(&dk, (3 * nm * C + 2 * N) * sizeof(double)) != hipSuccess)
     return set_err(c, LR_ENOMEM, "staging");

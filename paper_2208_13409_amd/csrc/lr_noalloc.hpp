@@ -112,7 +112,9 @@ int noalloc_run(const Grid &g, char *base, NoallocArgs &a, NoallocErr &err) {
   const int node_blocks = (g.nx / TX + 1) * (g.ny / TY + 1);
   const int cell_blocks = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
   // layout: control record, descriptor, problem list, check word, block
-  // maps, then the problem's arrays as lr_create carves them
+  // maps, the problem's arrays as lr_create carves them, then the list of
+  // mixed cells, as long as the rest of the workspace allows (up to one
+  // entry per cell; it cannot grow here)
   Carver cv{nullptr};
   cv.take<Ctl>(1);
   cv.take<Prob<R>>(1);
@@ -122,12 +124,18 @@ int noalloc_run(const Grid &g, char *base, NoallocArgs &a, NoallocErr &err) {
   cv.take<BlockMap>(cell_blocks);
   const size_t head = (cv.off + 255) & ~size_t(255);
   Prob<R> P;
-  const size_t need = head + carve_prob(P, nullptr, g, false, nullptr);
+  const size_t body = carve_prob(P, nullptr, g, false, nullptr);
+  const int cap_min = mix_cap_initial(g, 0);
+  const size_t need = head + body + list_bytes<R>(g, cap_min);
   if (need > (size_t)LR_NOALLOC_BYTES) {
     std::snprintf(err.m, sizeof err.m, "problem needs %zu bytes of device memory; the static workspace holds %zu",
                   need, (size_t)LR_NOALLOC_BYTES);
     return LR_ENOMEM;
   }
+  // the largest list that fits, one entry per cell at most
+  const size_t entry = sizeof(int) + 8 * (size_t)g.nmat * sizeof(R);
+  const size_t room = (size_t)LR_NOALLOC_BYTES - head - body - 512;
+  const int cap = (int)std::min<size_t>(C, std::max<size_t>(cap_min, room / entry));
   cv = Carver{base};
   Ctl *ctl = cv.take<Ctl>(1);
   Prob<R> *dprob = cv.take<Prob<R>>(1);
@@ -136,6 +144,11 @@ int noalloc_run(const Grid &g, char *base, NoallocArgs &a, NoallocErr &err) {
   BlockMap *node_map = cv.take<BlockMap>(node_blocks);
   BlockMap *cell_map = cv.take<BlockMap>(cell_blocks);
   carve_prob(P, base + head, g, false, ctl);
+  carve_list(P, base + head + body, g, cap);
+  if (head + body + list_bytes<R>(g, cap) > (size_t)LR_NOALLOC_BYTES) {
+    std::snprintf(err.m, sizeof err.m, "mixed-cell list does not fit the workspace");
+    return LR_ENOMEM;
+  }
   hipStream_t s = a.s;
 
   // descriptor, maps, control record; wall flux entries cleared (the

@@ -49,7 +49,7 @@ class lr_opts(C.Structure):
                 ("y1", C.c_double), ("cfl", C.c_double), ("a1", C.c_double),
                 ("a2", C.c_double), ("precision", C.c_int), ("recon_order", C.c_int),
                 ("kinematic", C.c_int), ("k_eps", C.c_double), ("fixed_dt", C.c_double),
-                ("stages", C.c_int), ("remap", C.c_int)]
+                ("stages", C.c_int), ("remap", C.c_int), ("mix_list", C.c_int)]
 
 
 class lr_batch_opts(C.Structure):
@@ -174,7 +174,7 @@ class Solver:
 
     def __init__(self, nx, ny, gammas, domain=(0.0, 1.0, 0.0, 1.0), cfl=0.5, a1=0.5, a2=1.0,
                  recon_order=2, kinematic=False, k_eps=1e-10, fixed_dt=0.0, precision=LR_FP64,
-                 stages=False, stream=None, pinfs=None, remap=0):
+                 stages=False, stream=None, pinfs=None, remap=0, mix_list=0):
         self.lib = load()
         self.nx, self.ny, self.nmat = int(nx), int(ny), len(gammas)
         o = lr_default_opts()
@@ -184,6 +184,7 @@ class Solver:
         o.k_eps, o.fixed_dt, o.precision = float(k_eps), float(fixed_dt), int(precision)
         o.stages = int(bool(stages))
         o.remap = int(remap)
+        o.mix_list = int(mix_list)
         self.h = lr_create(nx, ny, gammas, o, pinfs)
         if stream is not None:
             self.bind_stream(stream)
@@ -367,13 +368,14 @@ class Batch:
         return int(self.lib.lr_batch_footprint(int(nx), int(ny), self.nmat, self.precision))
 
     def submit(self, prob, t_end, max_steps=1 << 40, cfl=0.5, a1=0.5, a2=1.0, recon_order=2,
-               kinematic=False, k_eps=1e-10, fixed_dt=0.0):
+               kinematic=False, k_eps=1e-10, fixed_dt=0.0, mix_list=0):
         """prob: dict with nx, ny, gammas, domain, k, rho, e, ux, uy."""
         o = lr_default_opts()
         o.x0, o.x1, o.y0, o.y1 = map(float, prob["domain"])
         o.cfl, o.a1, o.a2 = float(cfl), float(a1), float(a2)
         o.recon_order, o.kinematic = int(recon_order), int(bool(kinematic))
         o.k_eps, o.fixed_dt, o.precision = float(k_eps), float(fixed_dt), self.precision
+        o.mix_list = int(mix_list)
         gam = prob["gammas"]
         if len(gam) != self.nmat:
             raise LRError(LR_EINVAL, f"{len(gam)} materials in a batch of nmat={self.nmat}")

@@ -389,3 +389,46 @@ def test_at_rest_skips_give_the_same_bits():
     rc, st, _ = b.status(rs)
     assert rc == LR_OK and st == steps
     same_fields(b.fields(rs, *FIELDS), ref, "triple point")
+
+
+@pytest.mark.parametrize("precision", [LR_FP64, LR_FP32])
+def test_mixed_list_grows_and_the_step_runs_again(precision):
+    """A problem whose list of mixed cells starts at 16 entries (far fewer
+    than its mixed cells) stops at its first step, grows the list to the
+    count the step found and runs the step again: alone and in a batch its
+    fields equal those of the problem run with room from the start."""
+    p = inputs.random_mixed(81, 90, 70, nmat=3)
+    k = p["k"]
+    assert ((k > 1e-6).sum(0) >= 2).sum() > 200
+    kw = dict(k_eps=1e-6) if precision == LR_FP32 else {}
+    say(f"mixed-cell list of 16 entries, 90x70, 3 materials, precision {precision}")
+    ref = Solver(p["nx"], p["ny"], p["gammas"], p["domain"], precision=precision, **kw)
+    ref.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+    ref.run(1e30, max_steps=12)
+    want = ref.fields(*FIELDS)
+    small = Solver(p["nx"], p["ny"], p["gammas"], p["domain"], precision=precision, mix_list=16, **kw)
+    small.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+    n, _ = small.run(1e30, max_steps=5)
+    for _ in range(7):  # and one step at a time
+        small.step()
+    assert n == 5
+    same_fields(small.fields(*FIELDS), want, "alone with a growing list")
+    b = Batch(nmat=3, precision=precision, max_slots=2, pool_bytes=64 << 20, chunk_steps=4)
+    rid = b.submit(p, 1e30, max_steps=12, mix_list=16, **kw)
+    drain(b)
+    rc, st, _ = b.status(rid)
+    assert rc == LR_OK and st == 12
+    same_fields(b.fields(rid, *FIELDS), want, "in a batch with a growing list")
+    # a list just large enough for the initial state: it overflows later, as
+    # the bubble's interface lengthens, in the middle of a chunk
+    q = inputs.shock_bubble(83, grid=(96, 64))
+    nmix0 = int(((q["k"] > 1e-6).sum(0) >= 2).sum())
+    ref = Solver(q["nx"], q["ny"], q["gammas"], q["domain"], precision=precision, **kw)
+    ref.set_state(0.0, q["k"], q["rho"], q["e"], q["ux"], q["uy"])
+    ref.run(1e30, max_steps=60)
+    b = Batch(nmat=2, precision=precision, max_slots=2, pool_bytes=64 << 20, chunk_steps=4)
+    rid = b.submit(q, 1e30, max_steps=60, mix_list=nmix0 + 1, **kw)
+    drain(b)
+    rc, st, _ = b.status(rid)
+    assert rc == LR_OK and st == 60
+    same_fields(b.fields(rid, *FIELDS), ref.fields(*FIELDS), "shock-bubble with a list that grows mid-chunk")
