@@ -66,7 +66,7 @@ typedef struct {
   int remap;             /* LR_REMAP_DIRECTCF (default) or LR_REMAP_AD; batches and
                             lr_run_noalloc run DirectCF only                              */
   int mix_list;          /* initial capacity (cells) of the list of mixed cells; 0
-                            (default): the larger of nx*ny/32, 256 and twice the mixed
+                            (default): the larger of nx*ny/16, 256 and twice the mixed
                             cells of the initial state.  A step that finds more mixed
                             cells stops before it changes the state; the list grows
                             and the step runs again (lr_run_noalloc: the largest list
@@ -151,9 +151,12 @@ int lr_totals(lr_ctx *c, double *out);
  * "volcf", "VL" [ny][nx];
  * "eL", "rhocf", "P_half" [nmat][ny][nx]; "mp", "uhx", "uhy", "uLx", "uLy",
  * "dpx", "dpy", "muD", "muA" [ny+1][nx+1]; "muX" [ny][nx+1]; "muY" [ny+1][nx];
- * "Wpx" [nmat][ny][nx+1]; "Wpy" [nmat][ny+1][nx]; "Wpc" [nmat][ny+1][nx+1].
- * Fluxes are signed along +x, +y, the main diagonal (SW->NE) or the
- * anti-diagonal (NW->SE). */
+ * "Wpx" [nmat][ny][nx+1]; "Wpy" [nmat][ny+1][nx]; "Wpc" [nmat][ny+1][nx+1];
+ * "dxL", "dyL" [ny][nx].  Fluxes are signed along +x, +y, the main diagonal
+ * (SW->NE) or the anti-diagonal (NW->SE).  "run" [3] (no stages needed): the
+ * capacity of the mixed-cell list, 1 if full chunks of lr_run replay a
+ * captured HIP graph (0 before the first, or if capture failed), 1 if
+ * capture failed. */
 int lr_debug_get(lr_ctx *c, const char *name, double *out);
 
 /* Kernel timing for benchmarks.  lr_profile(c, 1) makes every later step

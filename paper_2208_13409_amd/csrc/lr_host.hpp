@@ -88,11 +88,11 @@ inline long long count_mixed_host(const Grid &g, const double *k) {
   }
   return n;
 }
-// initial capacity: as asked, else the larger of C/32, 256 and twice the
+// initial capacity: as asked, else the larger of C/16, 256 and twice the
 // mixed cells of the initial state (at most C)
 inline int mix_cap_initial(const Grid &g, long long nmix0) {
   const long long C = (long long)g.nx * g.ny;
-  const long long cap = g.mix_list > 0 ? g.mix_list : std::max(std::max(C / 32, 256ll), 2 * nmix0);
+  const long long cap = g.mix_list > 0 ? g.mix_list : std::max(std::max(C / 16, 256ll), 2 * nmix0);
   return (int)std::min(cap, C);
 }
 // capacity after a step needed `need` entries
@@ -624,6 +624,12 @@ int debug_impl(lr_ctx *c, Prob<R> &P, const std::string &n, double *out) {
   const int cur = cur_slot(k);
   const double dt = host_slot_dt(g, k.slot[cur ^ 1]);
   if (n == "dt") { out[0] = dt; return LR_OK; }
+  if (n == "run") {
+    out[0] = P.mix_cap;
+    out[1] = c->chunk_graph[0] || c->chunk_graph[1] ? 1.0 : 0.0;
+    out[2] = c->graph_failed ? 1.0 : 0.0;
+    return LR_OK;
+  }
   if (n == "t") { out[0] = k.slot[cur].t; return LR_OK; }
   if (n == "Q") return debug_copy(c, P.dbg.Q, C, out);
   if (n == "S") return debug_copy(c, P.dbg.S, C, out);

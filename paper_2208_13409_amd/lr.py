@@ -261,7 +261,7 @@ class Solver:
                   "dxL": (ny, nx), "dyL": (ny, nx), "eL": (nm, ny, nx), "rhocf": (nm, ny, nx),
                   "P_half": (nm, ny, nx), "muX": (ny, nx + 1), "muY": (ny + 1, nx),
                   "Wpx": (nm, ny, nx + 1), "Wpy": (nm, ny + 1, nx), "Wpc": (nm, ny + 1, nx + 1),
-                  "dt": (1,), "t": (1,)}
+                  "dt": (1,), "t": (1,), "run": (3,)}
         out = np.zeros(shapes.get(name, (ny + 1, nx + 1)))
         self._check(self.lib.lr_debug_get(self.h, name.encode(), _dptr(out)))
         return out

@@ -101,8 +101,8 @@ def test_batch_argument_validation_without_device():
     f64 = lib.lr_batch_footprint(64, 64, 2, lr.LR_FP64)
     big = lib.lr_batch_footprint(128, 128, 2, lr.LR_FP32)
     assert 0 < f32 < f64 and 3.5 * f32 < big < 4.5 * f32
-    # the list of mixed cells is sized to need (1/32 of the cells to start
-    # with): 2 materials in FP32 take about 106 bytes per cell, 3 in FP64 270
+    # the list of mixed cells is sized to need (1/16 of the cells to start
+    # with): 2 materials in FP32 take about 108 bytes per cell, 3 in FP64 273
     assert lib.lr_batch_footprint(512, 512, 2, lr.LR_FP32) / 512 ** 2 < 112
     assert lib.lr_batch_footprint(512, 512, 3, lr.LR_FP64) / 512 ** 2 < 280
     assert lib.lr_batch_footprint(1, 64, 2, lr.LR_FP32) == 0

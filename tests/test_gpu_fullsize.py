@@ -104,7 +104,9 @@ def test_triple_point_1792x768_fp32_two_steps_vs_oracle(tp4):
 def test_triple_point_1792x768_fp32_vs_fp64_window():
     """FP32 against FP64 on the GPU over 400 steps from t = 0: the FP32
     error report of the large triple point (relative L1 of density and
-    pressure, per-material mass drift of the FP32 run)."""
+    pressure, per-material mass drift of the FP32 run), held to the FP32
+    tolerance and to a drift of 5e-8 (measured: L1 about 2e-5, drift about
+    7e-9; the whole run to t_end is in tests/test_gpu_longrun.py)."""
     p = inputs.triple_point(4)
     runs = {}
     for prec in (LR_FP64, LR_FP32):
@@ -120,8 +122,8 @@ def test_triple_point_1792x768_fp32_vs_fp64_window():
     drift = np.abs(m1 - m0) / m0
     say(f"1792x768 FP32 vs FP64 after 400 steps (t {runs[LR_FP64][3]:.4f}): L1 rho {l1r:.2e} "
         f"p {l1p:.2e}; FP32 per-material mass drift {drift}")
-    assert l1r <= 1e-3 and l1p <= 1e-3
-    assert np.all(drift <= 1e-6)
+    assert l1r <= 1e-4 and l1p <= 1e-4
+    assert np.all(drift <= 5e-8)
 
 
 def test_batch_in_bench_configuration():
