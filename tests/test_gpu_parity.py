@@ -141,7 +141,8 @@ def test_sod_full_run():
 
 def test_triple_point_full_size_steps():
     """Triple point at its full 448x192 size, 20 steps (the oracle computes
-    every cell), then 200 more on the GPU alone checked by conservation."""
+    every cell), then 200 more on the GPU alone checked by conservation.
+    Those run as full chunks of lr_run, replayed from a captured HIP graph."""
     p = inputs.triple_point(1)
     say("triple point 448x192, 20 steps")
     g, r = pair(p)
@@ -152,6 +153,9 @@ def test_triple_point_full_size_steps():
     t0 = g.totals()
     g.run(p["t_end"], max_steps=200)
     t1 = g.totals()
+    cap, replayed, failed = g.stage("run")
+    assert replayed == 1 and failed == 0, "full chunks did not replay a graph"
+    assert cap == 448 * 192 // 16
     m0, m1 = t0[3:6], t1[3:6]
     assert np.all(np.abs(m1 - m0) <= 1e-12 * m0)
     assert abs(t1[:3].sum() - 21.0) < 1e-12 * 21.0
