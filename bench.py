@@ -24,6 +24,9 @@ line carries
   "triple_point_1792x768": the large triple point in FP64 and FP32 from its
       developed state (t = 1.75), and the L1 of FP32 against FP64 over the
       timed window from the same state;
+  "ad_comparator_fp64": the paper's alternate-direction remap against the
+      DirectCF remap, FP64, 100 steps from the same developed triple-point
+      state, at 448x192 and 1792x768;
   "serving": a seeded Poisson stream of four-quadrant Riemann problems
       (grids 128^2..1024^2, FP32, t_end 0.25; 1000 requests at 50/s) served
       with continuous batching; p50/p99 latency from arrival to result fields
@@ -409,6 +412,40 @@ def large_leg(steps, warmup):
     return out
 
 
+def ad_leg(steps, warmup):
+    """The paper's comparator: the alternate-direction remap (an X and a Y
+    pass per step, nine kernel launches) against the one-step DirectCF remap
+    (four launches), FP64, each timed from the same developed state of the
+    triple point (t = 1.75) at 448x192 and 1792x768."""
+    import torch
+
+    from paper_2208_13409_amd import inputs
+    from paper_2208_13409_amd.lr import LR_REMAP_AD, LR_REMAP_DIRECTCF, Solver
+    out = {}
+    for scale in (1, 4):
+        p = inputs.triple_point(scale)
+        nx, ny = p["nx"], p["ny"]
+        g = Solver(nx, ny, p["gammas"], p["domain"])
+        g.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+        t_dev = 0.5 * p["t_end"]
+        g.run(t_dev)
+        x0, x1, y0, y1 = p["domain"]
+        st = inputs.restart_state(g.fields("vol", "mass", "ie", "ux", "uy"), (x1 - x0) / nx * (y1 - y0) / ny)
+        g.close()
+        rec = {}
+        for name, remap in (("directcf", LR_REMAP_DIRECTCF), ("ad", LR_REMAP_AD)):
+            stream = torch.cuda.Stream()
+            h = Solver(nx, ny, p["gammas"], p["domain"], stream=stream, remap=remap)
+            h.set_state(t_dev, *st)
+            _, n, wall, _ = timed_window(h, stream, warmup, steps)
+            rec[name] = {"us_per_step": wall * 1e6 / n, "value": nx * ny * n / wall}
+            h.close()
+        rec["directcf_speedup"] = rec["ad"]["us_per_step"] / rec["directcf"]["us_per_step"]
+        out[f"triple_point_{nx}x{ny}"] = rec
+    out["launches_per_step"] = {"directcf": 4, "ad": 9}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -427,6 +464,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--large-steps", type=int, default=100)
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-ad", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--no-serve", action="store_true")
@@ -524,6 +562,8 @@ def main():
         out["fp32_batched"]["vs_fp64_plain"] = out["fp32_batched"]["value"] / value
     if not args.no_large:
         out["triple_point_1792x768"] = large_leg(args.large_steps, 10)
+    if not args.no_ad:
+        out["ad_comparator_fp64"] = ad_leg(100, 10)
     if not args.no_serve:
         out["serving"] = serve_leg(args.serve_requests, args.serve_rate)
     if not args.no_cpu_baseline:
