@@ -1785,19 +1785,24 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
         const int hS = b * TX + a, hN = hS + TX;
         const int hSW = b * (TX + 1) + a, hNE = (b + 1) * (TX + 1) + a + 1;  // cells (I-1,J-1), (I,J)
         const int hNW = (b + 1) * (TX + 1) + a, hSE = b * (TX + 1) + a + 1;  // cells (I-1,J), (I,J-1)
-        R m = mp3;
-        R mu = m * sh.ulx[b + 2][a + 2], mv = m * sh.uly[b + 2][a + 2];  // u^{lag} of the node
+        // the node's mass and momentum sums, compensated in FP32 as the
+        // remap's cell sums are; the node's u^{lag} starts the momentum
+        Acc<R> am, au, av;
+        am.init(mp3);
+        au.init(mp3 * sh.ulx[b + 2][a + 2]);
+        av.init(mp3 * sh.uly[b + 2][a + 2]);
         // mass fluxes of the eight dual regions, as stage 2 formed them
         const R *fmx = &sh.mx[0][0], *fmy = &sh.my[0][0], *fmd = &sh.cd[0][0], *fma = &sh.ca[0][0];
-        m += fmx[hW]; mu += sh.fx[0][hW]; mv += sh.fx[1][hW];
-        m -= fmx[hE]; mu -= sh.fx[0][hE]; mv -= sh.fx[1][hE];
-        m += fmy[hS]; mu += sh.fy[0][hS]; mv += sh.fy[1][hS];
-        m -= fmy[hN]; mu -= sh.fy[0][hN]; mv -= sh.fy[1][hN];
-        m += fmd[hSW]; mu += sh.fd[0][hSW]; mv += sh.fd[1][hSW];
-        m -= fmd[hNE]; mu -= sh.fd[0][hNE]; mv -= sh.fd[1][hNE];
         const R *fa = &sh.dxy[0][0][0];  // anti-diagonal fluxes (x at k, y at FA + k)
-        m += fma[hNW]; mu += fa[hNW]; mv += fa[SH::FA + hNW];
-        m -= fma[hSE]; mu -= fa[hSE]; mv -= fa[SH::FA + hSE];
+        am.add(fmx[hW]); au.add(sh.fx[0][hW]); av.add(sh.fx[1][hW]);
+        am.add(-fmx[hE]); au.add(-sh.fx[0][hE]); av.add(-sh.fx[1][hE]);
+        am.add(fmy[hS]); au.add(sh.fy[0][hS]); av.add(sh.fy[1][hS]);
+        am.add(-fmy[hN]); au.add(-sh.fy[0][hN]); av.add(-sh.fy[1][hN]);
+        am.add(fmd[hSW]); au.add(sh.fd[0][hSW]); av.add(sh.fd[1][hSW]);
+        am.add(-fmd[hNE]); au.add(-sh.fd[0][hNE]); av.add(-sh.fd[1][hNE]);
+        am.add(fma[hNW]); au.add(fa[hNW]); av.add(fa[SH::FA + hNW]);
+        am.add(-fma[hSE]); au.add(-fa[hSE]); av.add(-fa[SH::FA + hSE]);
+        const R m = am.get(), mu = au.get(), mv = av.get();
         if (!(m > R(0))) atomicOr(&ctl->err, ERR_NODEMASS);
         ux = qdiv(mu, m);
         uy = qdiv(mv, m);
