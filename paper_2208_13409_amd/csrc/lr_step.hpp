@@ -695,14 +695,17 @@ struct RemapShared {
   R xv[XH][XW], yv[YH][YW];
   R xc[NCY][NCX], yc[NCY][NCX];
   signed char pure[NCY][NCX];  // material of a pure cell, -1 mixed; +16 once P5 keeps order 2
-  // a pure cell's mass of its material (positivity guard, P5); once P5 is
-  // done, a mixed cell's position in the list of partial volumes (P6)
+  // for the donors [i0-1, i0+TX] x [j0-1, j0+TY]: a pure cell's mass of its
+  // material (positivity guard, P5); once P5 is done, a mixed cell's position
+  // in the list of partial volumes (P6)
   union MassOrSlot {
     R mass;
     int slot;
-  } mps[NCY][NCX];
+  } mps[TY + 2][TX + 2];
   R rcf[NM][NCY][NCX], el[NM][NCY][NCX];
-  R vcfo[TY][TX];  // Vol^{lagCF} of the owned cells (P3 for P6)
+  // FP64: Vol^{lagCF} of the owned cells (P3 for P6); FP32 keeps it in a
+  // register (the owned cell's record is its thread's first, see P3)
+  R vcfo[sizeof(R) == 8 ? TY : 1][TX];
   // per region (x-faces, then y-faces, then corners): the order-2 mass and
   // energy fluxes of a pure donor in the window (set for those regions only)
   R vm[NV], vq[NV];
@@ -744,7 +747,27 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   // phases): u^{n+1/2} of the staged nodes (P1), the owned cell's V, M (P6)
   // and the records' V, M, e^{lag} and list positions (P3).
   constexpr int NIT1 = (SH::NNX * SH::NNY + NT - 1) / NT;
-  constexpr int NIT3 = (SH::NCX * SH::NCY + NT - 1) / NT;
+  // P3's records.  FP32: first the one of the thread's own cell (its
+  // Vol^{lagCF} then stays in a register until P6, and the tile's LDS fits
+  // one more block per CU), then the ring of the two-deep halo.  FP64 (two
+  // blocks per CU whatever the LDS saved): in row order, which keeps every
+  // wave's loads of the records in few rows.
+  constexpr bool OWN_FIRST = sizeof(R) == 4;
+  constexpr int NRING = SH::NCX * SH::NCY - TX * TY;
+  constexpr int NIT3 = OWN_FIRST ? 1 + (NRING + NT - 1) / NT : (SH::NCX * SH::NCY + NT - 1) / NT;
+  auto rec = [&](int it) {
+    if constexpr (!OWN_FIRST) {
+      const int l = tid + it * NT;
+      return l < SH::NCX * SH::NCY ? l : -1;
+    }
+    if (it == 0) return (tid / TX + 2) * SH::NCX + tid % TX + 2;
+    const int k = tid + (it - 1) * NT;
+    if (k >= NRING) return -1;
+    if (k < 2 * SH::NCX) return k;                                       // rows j0-2, j0-1
+    if (k < 4 * SH::NCX) return (TY + 2) * SH::NCX + (k - 2 * SH::NCX);  // rows j0+TY, j0+TY+1
+    const int r = k - 4 * SH::NCX, c = r & 3;  // two records each side of rows j0 .. j0+TY-1
+    return (2 + (r >> 2)) * SH::NCX + (c < 2 ? c : TX + c);
+  };
   R pre1[NIT1][2];
 #pragma unroll
   for (int it = 0; it < NIT1; ++it) {
@@ -773,7 +796,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   constexpr bool PRE3 = sizeof(R) == 4 && !REST;
   auto fetch3 = [&](int l, R *out) {
     const int i = i0 - 2 + l % SH::NCX, j = j0 - 2 + l / SH::NCX;
-    if (l >= SH::NCX * SH::NCY || i > nx + 1 || j > ny + 1) return;
+    if (l < 0 || i > nx + 1 || j > ny + 1) return;
     const int q = refl_cell(j, ny) * nx + refl_cell(i, nx);
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
@@ -785,7 +808,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   R pre3[PRE3 ? NIT3 : 1][3 * NM];
   if constexpr (PRE3) {
 #pragma unroll
-    for (int it = 0; it < NIT3; ++it) fetch3(tid + it * NT, pre3[it]);
+    for (int it = 0; it < NIT3; ++it) fetch3(rec(it), pre3[it]);
   }
   bool last;
   const double dtd = slot_dt(g, S, last);
@@ -900,11 +923,12 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
 
   // ---- P3: cell records; ghost cells mirror the real ones
   int ms3[NIT3];  // list position of a mixed record (-1: not listed); -2 not mixed
+  R vcf_own = A;  // Vol^{lagCF} of the thread's own cell
 #pragma unroll
   for (int it = 0; it < NIT3; ++it) {
     ms3[it] = -2;
-    const int l = tid + it * NT;
-    if (tile_rest || l >= SH::NCX * SH::NCY) continue;
+    const int l = rec(it);
+    if (tile_rest || l < 0) continue;
     const int a = l % SH::NCX, b = l / SH::NCX;
     const int i = i0 - 2 + a, j = j0 - 2 + b;
     if (i > nx + 1 || j > ny + 1) continue;
@@ -930,7 +954,11 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
     if (rj != j) yc = (j < 0 ? R(0) : R(2.0 * g.Ly)) - yc;
     sh.xc[b][a] = xc;
     sh.yc[b][a] = yc;
-    if (a >= 2 && b >= 2 && a < TX + 2 && b < TY + 2) sh.vcfo[b - 2][a - 2] = v;
+    if constexpr (OWN_FIRST) {
+      if (it == 0) vcf_own = v;
+    } else if (a >= 2 && b >= 2 && a < TX + 2 && b < TY + 2) {
+      sh.vcfo[b - 2][a - 2] = v;
+    }
     int np = 0, pm = -1;
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
@@ -946,12 +974,13 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
     sh.pure[b][a] = np == 1 ? pm : -1;
     // a mixed record's list position: loaded here, stored in LDS after P5,
     // so that the load's latency is spent on P4 and P5
-    ms3[it] = np >= 2 ? ldg(P.mix_slot + q) : -2;
+    const bool ring1 = a >= 1 && b >= 1 && a <= TX + 2 && b <= TY + 2;  // a donor of the tile's regions
+    ms3[it] = np >= 2 && ring1 ? ldg(P.mix_slot + q) : -2;
     R mp = R(0);
 #pragma unroll
     for (int m = 0; m < NM; ++m)
       if (m == pm) mp = vme[NM + m];
-    sh.mps[b][a].mass = mp;
+    if (ring1) sh.mps[b - 1][a - 1].mass = mp;
     if (ri == i && rj == j && a >= 2 && b >= 2 && a < TX + 2 && b < TY + 2) {
       if (!(v > R(0))) atomicOr(&ctl->err, ERR_VOLCF);
       if (P.dbg.volcf) stg(P.dbg.volcf + q, v);
@@ -1050,9 +1079,12 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
         if (ok) {
           const R xD = sh.xc[cb][ca], yD = sh.yc[cb][ca];
           R s11 = R(0), s12 = R(0), s22 = R(0), br1 = R(0), br2 = R(0), be1 = R(0), be2 = R(0);
-#pragma unroll
+          // (rolled loops: unrolled, the neighbours' loads are all hoisted
+          // and their registers would set the kernel's occupancy for every
+          // reconstruction order)
+#pragma unroll 1
           for (int b = -1; b <= 1; ++b)
-#pragma unroll
+#pragma unroll 1
             for (int a = -1; a <= 1; ++a) {
               if (a == 0 && b == 0) continue;
               const R X1 = sh.xc[cb + b][ca + a] - xD, X2 = sh.yc[cb + b][ca + a] - yD;
@@ -1083,7 +1115,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
             const R Ge1 = (s22 * be1 - s12 * be2) / det, Ge2 = (s11 * be2 - s12 * be1) / det;
             // the four limited slopes: x, y, v, v_perp
             R limr = R(INFINITY), lime = R(INFINITY);
-#pragma unroll
+#pragma unroll 1
             for (int dd = 0; dd < 4; ++dd) {
               const int si = dd == 1 ? 0 : 1, sj = dd == 0 ? 0 : (dd == 3 ? -1 : 1);
               const R vx = dd == 0 ? R(1) : (dd == 1 ? R(0) : dgx);
@@ -1153,7 +1185,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
       const int ca = di - (i0 - 2), cb = dj - (j0 - 2);
       const int pm = sh.pure[cb][ca];
       if (pm < 0) continue;
-      const R Mpm = sh.mps[cb][ca].mass;
+      const R Mpm = sh.mps[cb - 1][ca - 1].mass;
       const R eD = sh.el[pm][cb][ca];
       // the donor's eight regions in the region arrays: W, E faces, S, N
       // faces, corners at its BL, BR, TL, TR nodes.  A region is an outflow
@@ -1187,8 +1219,8 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
   }
 #pragma unroll
   for (int it = 0; it < NIT3; ++it) {
-    const int l = tid + it * NT;
-    if (l < SH::NCX * SH::NCY && ms3[it] != -2) sh.mps[l / SH::NCX][l % SH::NCX].slot = ms3[it];
+    const int l = rec(it);  // (ms3 is -2 outside the donor ring)
+    if (l >= 0 && ms3[it] != -2) sh.mps[l / SH::NCX - 1][l % SH::NCX - 1].slot = ms3[it];
   }
   __syncthreads();
 
@@ -1207,7 +1239,8 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
 #pragma unroll
           for (int m = 0; m < NM; ++m) elc[m] = ldg(P.eL + (m * C + q));
         } else {
-          v = sh.vcfo[b][a];
+          if constexpr (OWN_FIRST) v = vcf_own;
+          else v = sh.vcfo[b][a];
 #pragma unroll
           for (int m = 0; m < NM; ++m) elc[m] = sh.el[m][cb][ca];
         }
@@ -1288,7 +1321,7 @@ __device__ __forceinline__ void remap_tile(const Prob<R> *probs, const BlockMap 
         pqs[s] = need ? int(sh.pure[db][da]) : -2;  // -2: no flux
         mss[s] = -1;
         if (pqs[s] == -1) {
-          const int ms = sh.mps[db][da].slot;
+          const int ms = sh.mps[db - 1][da - 1].slot;
           if (ms >= 0 && ms < P.mix_cap) {
             mss[s] = ms;
             const R *src = P.mix_W + (size_t)ms * 8 * NM + rf.s * NM;
