@@ -317,51 +317,50 @@ __device__ __forceinline__ bool corner_main(R dx, R dy) {
 
 // Area of the part of the rectangle [x0,x1] x [y0,y1] where nx x + ny y >= s,
 // in closed form.  With the rectangle centred (half sizes a, b), P = |nx|,
-// Q = |ny| and t = P a + Q b - s' (depth of the cut below the far corner), the
-// cut-off piece is a triangle t^2/(2PQ) while the line meets two adjacent
+// Q = |ny| and t = P a + Q b - |s'| (depth of the cut below the far corner),
+// the cut-off piece is a triangle t^2/(2PQ) while the line meets two adjacent
 // sides, and a trapezoid 2a(t - aP)/Q or 2b(t - bQ)/P once it meets two
-// opposite sides; s' < 0 uses the complement.
-__device__ __forceinline__ double corner_piece(double a, double b, double P, double Q, double t) {
-  if (t <= 0.0) return 0.0;
-  if (a * P <= b * Q) {  // the line leaves the x-range first
-    if (t <= 2.0 * a * P) return t * t / (2.0 * P * Q);
-    return 2.0 * a * (t - a * P) / Q;
-  }
-  if (t <= 2.0 * b * Q) return t * t / (2.0 * P * Q);
-  return 2.0 * b * (t - b * Q) / P;
-}
+// opposite sides; s' < 0 uses the complement.  Written without branches, the
+// case picking the numerator and denominator of the one quotient: a lane that
+// forms several of these areas (one per material) then overlaps their
+// latencies instead of running them one after another.
 __device__ __forceinline__ double rect_halfplane_area(double x0, double x1, double y0, double y1,
                                                       double nx, double ny, double s) {
-  if (!(x1 > x0) || !(y1 > y0)) return 0.0;
   const double a = 0.5 * (x1 - x0), b = 0.5 * (y1 - y0);
   const double sc = s - (nx * (0.5 * (x0 + x1)) + ny * (0.5 * (y0 + y1)));
   const double P = fabs(nx), Q = fabs(ny);
   const double h = P * a + Q * b;
   const double full = 4.0 * a * b;
   const double whole = (x1 - x0) * (y1 - y0);
-  if (sc >= h) return 0.0;
-  if (sc <= -h) return whole;
-  const double area = sc >= 0.0 ? corner_piece(a, b, P, Q, h - sc)
-                                : full - corner_piece(a, b, P, Q, h + sc);
-  return area < 0.0 ? 0.0 : (area > whole ? whole : area);
+  const double t = sc >= 0.0 ? h - sc : h + sc;
+  const bool xfirst = a * P <= b * Q;  // the line leaves the x-range first
+  const bool tri = t <= (xfirst ? 2.0 * a * P : 2.0 * b * Q);
+  const double num = tri ? t * t : (xfirst ? 2.0 * a * (t - a * P) : 2.0 * b * (t - b * Q));
+  const double den = tri ? 2.0 * P * Q : (xfirst ? Q : P);
+  const double piece = t <= 0.0 ? 0.0 : num / den;
+  double area = sc >= 0.0 ? piece : full - piece;
+  area = area < 0.0 ? 0.0 : (area > whole ? whole : area);
+  area = sc >= h ? 0.0 : (sc <= -h ? whole : area);
+  return (x1 > x0 && y1 > y0) ? area : 0.0;
 }
 
-// Inverse of corner_piece for T in [0, 2ab]: the depth t giving area T.
+// Inverse of the cut-off piece's area for T in [0, 2ab]: the depth t giving
+// area T (the triangle's root while T stays below the area Tt at which the
+// triangle spans the first range the line leaves, the trapezoid's beyond).
+// The three candidate quotients and the root are formed side by side and one
+// is selected: no branch waits on the quotient Tt.
 __device__ __forceinline__ double corner_depth(double a, double b, double P, double Q, double T) {
-  if (T <= 0.0) return 0.0;
-  if (a * P <= b * Q) {
-    const double Tt = 2.0 * a * a * P / Q;  // area when the triangle spans the x-range
-    if (T <= Tt) return sqrt(2.0 * P * Q * T);
-    return T * Q / (2.0 * a) + a * P;
-  }
-  const double Tt = 2.0 * b * b * Q / P;
-  if (T <= Tt) return sqrt(2.0 * P * Q * T);
-  return T * P / (2.0 * b) + b * Q;
+  const bool xfirst = a * P <= b * Q;
+  const double Tt = xfirst ? 2.0 * a * a * P / Q : 2.0 * b * b * Q / P;
+  const double root = sqrt(2.0 * P * Q * T);
+  const double trap = xfirst ? T * Q / (2.0 * a) + a * P : T * P / (2.0 * b) + b * Q;
+  return T <= 0.0 ? 0.0 : (T <= Tt ? root : trap);
 }
 
 // Offset s of the line n.x = s such that the part of the rectangle where
 // n.x >= s has area frac*|R| (§4.4, placement of the interface), in closed
 // form from the piecewise-quadratic area; frac in [0,1], n a unit vector.
+// Past half the rectangle the complement's depth is taken, and negated.
 __device__ __forceinline__ double interface_offset(double x0, double x1, double y0, double y1,
                                                    double nx, double ny, double frac) {
   const double a = 0.5 * (x1 - x0), b = 0.5 * (y1 - y0);
@@ -369,9 +368,9 @@ __device__ __forceinline__ double interface_offset(double x0, double x1, double 
   const double h = P * a + Q * b;
   const double full = 4.0 * a * b;
   const double T = frac * full;
-  double sc;
-  if (T <= 0.5 * full) sc = h - corner_depth(a, b, P, Q, T);
-  else sc = -(h - corner_depth(a, b, P, Q, full - T));
+  const bool lower = T <= 0.5 * full;
+  const double d = h - corner_depth(a, b, P, Q, lower ? T : full - T);
+  const double sc = lower ? d : -d;
   return sc + (nx * (0.5 * (x0 + x1)) + ny * (0.5 * (y0 + y1)));
 }
 

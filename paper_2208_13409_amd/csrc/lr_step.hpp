@@ -194,15 +194,17 @@ __device__ void mixed_region_partials(const ProbT &P, const R *Vs, int i, int j,
   const int grp = __lane_id() & ~7;
   // this lane's material's gradient (formed on every lane, used from lanes
   // s < NM: the group runs the same instructions either way)
+  // (the volume fractions V/A share the cell area: the stencil takes the
+  // volumes and one quotient divides by A)
   double gxs, gys;
   {
     double k[3][3];
 #pragma unroll
     for (int bb = 0; bb < 3; ++bb)
 #pragma unroll
-      for (int aa = 0; aa < 3; ++aa) k[bb][aa] = double(kr[bb][aa]) / g.A;
-    gxs = ((k[0][2] + 2.0 * k[1][2] + k[2][2]) - (k[0][0] + 2.0 * k[1][0] + k[2][0])) / (8.0 * g.dx);
-    gys = ((k[2][0] + 2.0 * k[2][1] + k[2][2]) - (k[0][0] + 2.0 * k[0][1] + k[0][2])) / (8.0 * g.dy);
+      for (int aa = 0; aa < 3; ++aa) k[bb][aa] = double(kr[bb][aa]);
+    gxs = ((k[0][2] + 2.0 * k[1][2] + k[2][2]) - (k[0][0] + 2.0 * k[1][0] + k[2][0])) / (8.0 * g.dx * g.A);
+    gys = ((k[2][0] + 2.0 * k[2][1] + k[2][2]) - (k[0][0] + 2.0 * k[0][1] + k[0][2])) / (8.0 * g.dy * g.A);
   }
   int a0 = -1, b0 = -1;
 #pragma unroll
@@ -278,13 +280,11 @@ __device__ void mixed_region_partials(const ProbT &P, const R *Vs, int i, int j,
     double raw[NM], sum = 0.0;
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
-      raw[m] = 0.0;
-      if (!pr[m]) continue;
-      if (DG[m]) {
-        degenerate = true;
-        continue;
-      }
-      raw[m] = rect_halfplane_area(x0, x1, y0, y1, NX[m], NY[m], OF[m]);
+      // formed for every material, then kept or not: straight-line code, so
+      // that the materials' areas are computed side by side
+      const double ar = rect_halfplane_area(x0, x1, y0, y1, NX[m], NY[m], OF[m]);
+      raw[m] = pr[m] && !DG[m] ? ar : 0.0;
+      if (pr[m] && DG[m]) degenerate = true;
     }
     if (out && vol != 0.0) {
 #pragma unroll
