@@ -1907,12 +1907,12 @@ struct Resident {  // blocks of each step kernel resident on the whole device
 
 // blocks per problem of the mixed-cell kernel in a launch of nprob problems
 // whose largest has `cells` cells: one 32-cell group per block for up to
-// C/1024 groups (mixed cells are a small fraction of the cells), each block
-// striding over the rest.  With many problems the launch is held near 2048
-// blocks: a block with no group still takes a launch slot and reads the
+// C/512 groups (the list's starting capacity, C/16 cells, in one pass), each
+// block striding over the rest.  With many problems the launch is held near
+// 2048 blocks: a block with no group still takes a launch slot and reads the
 // problem's control record.
 inline int mix_chunks_for(long long cells, int nprob = 1) {
-  const long long c = cells / 1024;
+  const long long c = cells / 512;
   int n = (int)(c < 16 ? 16 : (c > 1024 ? 1024 : c));
   const int cap = 2048 / (nprob > 0 ? nprob : 1);
   if (n > cap) n = cap < 4 ? 4 : cap;
