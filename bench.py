@@ -420,7 +420,7 @@ def ad_leg(steps, warmup):
     import torch
 
     from paper_2208_13409_amd import inputs
-    from paper_2208_13409_amd.lr import LR_REMAP_AD, LR_REMAP_DIRECTCF, Solver
+    from paper_2208_13409_amd.lr import LR_REMAP_AD, LR_REMAP_DIRECTCF, LR_TILE_32x8, Solver
     out = {}
     for scale in (1, 4):
         p = inputs.triple_point(scale)
@@ -435,7 +435,9 @@ def ad_leg(steps, warmup):
         rec = {}
         for name, remap in (("directcf", LR_REMAP_DIRECTCF), ("ad", LR_REMAP_AD)):
             stream = torch.cuda.Stream()
-            h = Solver(nx, ny, p["gammas"], p["domain"], stream=stream, remap=remap)
+            # both on the 32x8 tiles (the shape the alternate-direction
+            # remap runs on), so that the two differ in the remap only
+            h = Solver(nx, ny, p["gammas"], p["domain"], stream=stream, remap=remap, tile=LR_TILE_32x8)
             h.set_state(t_dev, *st)
             _, n, wall, _ = timed_window(h, stream, warmup, steps)
             rec[name] = {"us_per_step": wall * 1e6 / n, "value": nx * ny * n / wall}
@@ -479,7 +481,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2208_13409_amd.lr import Solver
+    from paper_2208_13409_amd.lr import TILE_SHAPES, Solver
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
@@ -540,7 +542,8 @@ def main():
         "dtype": "f32" if fp32 else "f64",
         "data": "synthetic",
         "config": {"workload": p["name"], "nx": nx, "ny": ny, "nmat": nmat, "precision": args.precision,
-                   "t_start": t_prep, "developed_from_step": n_prep, "cfl": 0.5},
+                   "t_start": t_prep, "developed_from_step": n_prep, "cfl": 0.5,
+                   "tile": "%dx%d" % TILE_SHAPES[int(g.stage("run")[3])]},
         "gpu_event_ms_per_step": gpu_ms / n,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

@@ -71,6 +71,14 @@ typedef struct {
                             cells stops before it changes the state; the list grows
                             and the step runs again (lr_run_noalloc: the largest list
                             its workspace holds, no growth)                              */
+  int tile;              /* tile shape of a context's step kernels (LR_TILE_*, below):
+                            LR_TILE_AUTO (default) takes 32x12 where the grid's 32x12
+                            node tiles fit on the device's CUs one block each and its
+                            32x8 ones do not (a small grid, one latency-bound round of
+                            blocks instead of two blocks on some CUs), else 32x8.
+                            LR_REMAP_AD runs on 32x8 only; batches take their shape
+                            from lr_batch_opts and lr_run_noalloc runs 32x8.  Results
+                            do not depend on it.                                      */
 } lr_opts;
 
 /* field mask bits for lr_get_fields, in the order the output pointers are
@@ -153,10 +161,10 @@ int lr_totals(lr_ctx *c, double *out);
  * "dpx", "dpy", "muD", "muA" [ny+1][nx+1]; "muX" [ny][nx+1]; "muY" [ny+1][nx];
  * "Wpx" [nmat][ny][nx+1]; "Wpy" [nmat][ny+1][nx]; "Wpc" [nmat][ny+1][nx+1];
  * "dxL", "dyL" [ny][nx].  Fluxes are signed along +x, +y, the main diagonal
- * (SW->NE) or the anti-diagonal (NW->SE).  "run" [3] (no stages needed): the
+ * (SW->NE) or the anti-diagonal (NW->SE).  "run" [4] (no stages needed): the
  * capacity of the mixed-cell list, 1 if full chunks of lr_run replay a
  * captured HIP graph (0 before the first, or if capture failed), 1 if
- * capture failed. */
+ * capture failed, the tile shape of the step kernels (LR_TILE_*). */
 int lr_debug_get(lr_ctx *c, const char *name, double *out);
 
 /* Kernel timing for benchmarks.  lr_profile(c, 1) makes every later step
@@ -197,14 +205,16 @@ typedef struct {
                            per cell-step is kept (persistent, use_graph and tile
                            are then ignored).  Results do not depend on it. */
   int tile;             /* tile shape of the step kernels: LR_TILE_32x8 (default),
-                           LR_TILE_16x16 or LR_TILE_32x16 (cells per block in x by
-                           y; 32x16 blocks have 512 threads).  Results do not
-                           depend on it. */
+                           LR_TILE_16x16, LR_TILE_32x16 or LR_TILE_32x12 (cells per
+                           block in x by y; 32x16 blocks have 512 threads, 32x12
+                           384).  Results do not depend on it. */
 } lr_batch_opts;
-enum { LR_TILE_32x8 = 0, LR_TILE_16x16 = 1, LR_TILE_32x16 = 2 };
-#define LR_NTILE 3
-/* schedules the autotuner times: c = persistent + 2*use_graph + 4*tile */
-#define LR_NSCHED (4 * LR_NTILE)
+enum { LR_TILE_AUTO = -1, LR_TILE_32x8 = 0, LR_TILE_16x16 = 1, LR_TILE_32x16 = 2, LR_TILE_32x12 = 3 };
+#define LR_NTILE 4
+/* schedules the autotuner times: c = persistent + 2*use_graph + 4*tile, over
+ * the first LR_NTUNE_TILE shapes (32x12 is the shape of small single grids) */
+#define LR_NTUNE_TILE 3
+#define LR_NSCHED (4 * LR_NTUNE_TILE)
 typedef struct lr_batch lr_batch;
 
 void lr_batch_default_opts(lr_batch_opts *o);

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "liblr.so")
 # one translation unit per tile shape of the step kernels, compiled in parallel
-SOURCES = ["csrc/lr_kernels.hip", "csrc/lr_tile16x16.hip", "csrc/lr_tile32x16.hip"]
+SOURCES = ["csrc/lr_kernels.hip", "csrc/lr_tile16x16.hip", "csrc/lr_tile32x16.hip", "csrc/lr_tile32x12.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -24,7 +24,7 @@ struct TileShape {
 };
 using TileDefault = TileShape<32, 8>;
 constexpr int kTileShapes = LR_NTILE;
-constexpr int kTileX[kTileShapes] = {32, 16, 32}, kTileY[kTileShapes] = {8, 16, 16};
+constexpr int kTileX[kTileShapes] = {32, 16, 32, 32}, kTileY[kTileShapes] = {8, 16, 16, 12};
 
 // Problem constants (FP64 whatever the bulk precision).
 struct Grid {
@@ -148,6 +148,7 @@ using StepFn = void (*)(const Launch &, int, hipStream_t, hipEvent_t *);
 // translation unit
 StepFn step_fn_tile16x16(int fp32, int nmat);
 StepFn step_fn_tile32x16(int fp32, int nmat);
+StepFn step_fn_tile32x12(int fp32, int nmat);
 // Workgroups are dispatched to the eight XCDs in turn (block b to XCD b % 8),
 // each XCD with its own L2.  Block b takes map entry xcd_tile(b, n) instead of
 // b, so that each XCD works through a contiguous run of the map and

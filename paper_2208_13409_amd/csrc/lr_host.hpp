@@ -346,6 +346,7 @@ struct lr_ctx {
   int node_blocks = 0, cell_blocks = 0;
   int *plist = nullptr;  // device {0}: the problem list of the mixed-cell launch
   StepFn step = nullptr;
+  int tile = LR_TILE_32x8;  // tile shape of the step kernels (LR_TILE_*)
   Ctl *ctl = nullptr;   // device
   Ctl *hctl = nullptr;  // pinned host mirror [3]: the context's, then two for
                         // the chunks of a run in flight
@@ -422,13 +423,29 @@ int alloc_prob(lr_ctx *c, Prob<R> &P) {
   if (dalloc(c, &d, 1)) return LR_ENOMEM;
   c->dprob = d;
   HIP_CHECK(c, hipStreamSynchronize(c->own));
-  c->step = step_fn<R>(c->g.nmat, c->g.remap);
+  c->step = c->g.remap == LR_REMAP_AD ? step_fn<R>(c->g.nmat, c->g.remap) : step_fn_tile<R>(c->g.nmat, c->tile);
   return ctx_list<R>(c, P, mix_cap_initial(c->g, 0));
+}
+
+// LR_TILE_AUTO: a grid whose 32x8 node tiles outnumber the device's CUs while
+// its 32x12 ones do not steps on 32x12 tiles.  Such a grid's launches are one
+// latency-bound round of blocks; on 32x8 tiles some CUs would hold two of
+// them and set every kernel's time.  Larger grids keep 32x8 (more blocks per
+// CU fit its smaller LDS tiles).
+int auto_tile(const Grid &g) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    return LR_TILE_32x8;
+  auto node_tiles = [&](int t) {
+    return (long long)(g.nx / kTileX[t] + 1) * (long long)(g.ny / kTileY[t] + 1);
+  };
+  return node_tiles(LR_TILE_32x8) > cus && node_tiles(LR_TILE_32x12) <= cus ? LR_TILE_32x12 : LR_TILE_32x8;
 }
 
 int build_maps(lr_ctx *c) {
   std::vector<BlockMap> nm, cm;
-  tile_maps(c->g, 0, nm, cm);
+  tile_maps(c->g, 0, nm, cm, kTileX[c->tile], kTileY[c->tile]);
   c->node_blocks = (int)nm.size();
   c->cell_blocks = (int)cm.size();
   if (dalloc(c, &c->node_map, nm.size()) || dalloc(c, &c->cell_map, cm.size()) || dalloc(c, &c->plist, 1))
@@ -628,6 +645,7 @@ int debug_impl(lr_ctx *c, Prob<R> &P, const std::string &n, double *out) {
     out[0] = P.mix_cap;
     out[1] = c->chunk_graph[0] || c->chunk_graph[1] ? 1.0 : 0.0;
     out[2] = c->graph_failed ? 1.0 : 0.0;
+    out[3] = c->tile;
     return LR_OK;
   }
   if (n == "t") { out[0] = k.slot[cur].t; return LR_OK; }
@@ -680,6 +698,7 @@ void lr_default_opts(lr_opts *o) {
   o->cfl = 0.5; o->a1 = 0.5; o->a2 = 1.0;
   o->precision = LR_FP64; o->recon_order = 2; o->kinematic = 0;
   o->k_eps = 1e-10; o->fixed_dt = 0.0; o->stages = 0; o->remap = LR_REMAP_DIRECTCF;
+  o->tile = LR_TILE_AUTO;
 }
 
 void lr_destroy(lr_ctx *c) {
@@ -706,12 +725,15 @@ int lr_create(int nx, int ny, int nmat, const lr_eos *eos, const int bc[4], cons
   else lr_default_opts(&o);
   Grid g;
   if (make_grid(nx, ny, nmat, eos, bc, o, g) != LR_OK) return LR_EINVAL;
+  if (o.tile < LR_TILE_AUTO || o.tile >= LR_NTILE || (o.remap == LR_REMAP_AD && o.tile > LR_TILE_32x8))
+    return LR_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return LR_EDEVICE;
   lr_ctx *c = new (std::nothrow) lr_ctx();
   if (!c) return LR_ENOMEM;
   c->o = o;
   c->g = g;
+  c->tile = o.tile != LR_TILE_AUTO ? o.tile : (o.remap == LR_REMAP_AD ? LR_TILE_32x8 : auto_tile(g));
   if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) {
     lr_destroy(c);
     return LR_EDEVICE;

@@ -233,6 +233,7 @@ StepFn step_fn_tile(int nmat, int tile) {
   switch (tile) {
     case LR_TILE_16x16: return step_fn_tile16x16(fp32, nmat);
     case LR_TILE_32x16: return step_fn_tile32x16(fp32, nmat);
+    case LR_TILE_32x12: return step_fn_tile32x12(fp32, nmat);
     default: return tiled_step<R, TileDefault>(nmat);
   }
 }

@@ -1938,8 +1938,8 @@ void launch(K kernel, dim3 grid, hipStream_t s, hipEvent_t *ev, Args... args) {
 }
 
 // one step on tiles of shape T: ev (optional) holds a start/stop pair per
-// kernel.  The 512-thread FP64 forms of small launches exist for the default
-// shape only.
+// kernel.  The FP64 forms of small launches with two threads per cell exist
+// for the default 32x8 shape and the 32x12 shape of small single grids.
 template <typename R, int NM, typename T>
 void step_impl(const Launch &L, int gpar, hipStream_t s, hipEvent_t *ev) {
   const Resident<R, NM, T> &res = resident<R, NM, T>();
@@ -1949,7 +1949,8 @@ void step_impl(const Launch &L, int gpar, hipStream_t s, hipEvent_t *ev) {
   const bool loop = L.persistent && res.n[0] > 0 && res.n[1] > 0 && res.n[2] > 0 && res.n[3] > 0;
   const BlockMap *nm = L.node_map, *cm = L.cell_map;
   const int nb = L.node_blocks, cb = L.cell_blocks;
-  constexpr bool kWideForm = sizeof(R) == 8 && std::is_same<T, TileDefault>::value;
+  constexpr bool kWideForm =
+      sizeof(R) == 8 && (std::is_same<T, TileDefault>::value || std::is_same<T, TileShape<32, 12>>::value);
   // the Lagrange kernel runs over the cell tiles: node tiles of a boundary
   // node column or row alone would be one thirty-second or one eighth full
   if (loop) {

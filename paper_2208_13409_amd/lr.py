@@ -20,10 +20,11 @@ LR_OK, LR_EINVAL, LR_ENOMEM, LR_EDEVICE, LR_ENEGATIVE, LR_ENAN, LR_EDT, LR_EAGAI
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 LR_FP64, LR_FP32 = 0, 1
 LR_REMAP_DIRECTCF, LR_REMAP_AD = 0, 1
-LR_TILE_32x8, LR_TILE_16x16, LR_TILE_32x16 = 0, 1, 2
-LR_NTILE = 3
-LR_NSCHED = 4 * LR_NTILE
-TILE_SHAPES = ((32, 8), (16, 16), (32, 16))
+LR_TILE_AUTO, LR_TILE_32x8, LR_TILE_16x16, LR_TILE_32x16, LR_TILE_32x12 = -1, 0, 1, 2, 3
+LR_NTILE = 4
+LR_NTUNE_TILE = 3
+LR_NSCHED = 4 * LR_NTUNE_TILE
+TILE_SHAPES = ((32, 8), (16, 16), (32, 16), (32, 12))
 F_RHO, F_P, F_E, F_K, F_RHOA, F_EA, F_PA, F_UX, F_UY, F_VOL, F_MASS, F_IE = (1 << i for i in range(12))
 PER_MAT = {F_K, F_RHOA, F_EA, F_PA, F_VOL, F_MASS, F_IE}
 NODE = {F_UX, F_UY}
@@ -49,7 +50,7 @@ class lr_opts(C.Structure):
                 ("y1", C.c_double), ("cfl", C.c_double), ("a1", C.c_double),
                 ("a2", C.c_double), ("precision", C.c_int), ("recon_order", C.c_int),
                 ("kinematic", C.c_int), ("k_eps", C.c_double), ("fixed_dt", C.c_double),
-                ("stages", C.c_int), ("remap", C.c_int), ("mix_list", C.c_int)]
+                ("stages", C.c_int), ("remap", C.c_int), ("mix_list", C.c_int), ("tile", C.c_int)]
 
 
 class lr_batch_opts(C.Structure):
@@ -174,7 +175,7 @@ class Solver:
 
     def __init__(self, nx, ny, gammas, domain=(0.0, 1.0, 0.0, 1.0), cfl=0.5, a1=0.5, a2=1.0,
                  recon_order=2, kinematic=False, k_eps=1e-10, fixed_dt=0.0, precision=LR_FP64,
-                 stages=False, stream=None, pinfs=None, remap=0, mix_list=0):
+                 stages=False, stream=None, pinfs=None, remap=0, mix_list=0, tile=LR_TILE_AUTO):
         self.lib = load()
         self.nx, self.ny, self.nmat = int(nx), int(ny), len(gammas)
         o = lr_default_opts()
@@ -185,6 +186,7 @@ class Solver:
         o.stages = int(bool(stages))
         o.remap = int(remap)
         o.mix_list = int(mix_list)
+        o.tile = int(tile)
         self.h = lr_create(nx, ny, gammas, o, pinfs)
         if stream is not None:
             self.bind_stream(stream)
@@ -261,7 +263,7 @@ class Solver:
                   "dxL": (ny, nx), "dyL": (ny, nx), "eL": (nm, ny, nx), "rhocf": (nm, ny, nx),
                   "P_half": (nm, ny, nx), "muX": (ny, nx + 1), "muY": (ny + 1, nx),
                   "Wpx": (nm, ny, nx + 1), "Wpy": (nm, ny + 1, nx), "Wpc": (nm, ny + 1, nx + 1),
-                  "dt": (1,), "t": (1,), "run": (3,)}
+                  "dt": (1,), "t": (1,), "run": (4,)}
         out = np.zeros(shapes.get(name, (ny + 1, nx + 1)))
         self._check(self.lib.lr_debug_get(self.h, name.encode(), _dptr(out)))
         return out

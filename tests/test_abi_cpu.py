@@ -137,3 +137,23 @@ def test_eos_arguments_checked_without_device():
     for g, pi in ((1.4, -1.0), (1.4, float("inf")), (1.0, 0.0)):
         eos = (lr.lr_eos * 1)(lr.lr_eos(g, pi))
         assert lib.lr_create(8, 8, 1, eos, None, ctypes.byref(o), ctypes.byref(h)) == lr.LR_EINVAL
+
+
+def test_tile_option_checked_without_device():
+    """lr_opts.tile defaults to automatic; a shape outside LR_TILE_* and the
+    alternate-direction remap on any shape but 32x8 are rejected before any
+    device call."""
+    from paper_2208_13409_amd import lr
+    lib = lr.load()
+    o = lr.lr_default_opts()
+    assert o.tile == lr.LR_TILE_AUTO
+    eos = (lr.lr_eos * 1)(lr.lr_eos(1.4, 0.0))
+    h = ctypes.c_void_p()
+    for tile in (-2, lr.LR_NTILE):
+        o.tile = tile
+        assert lib.lr_create(8, 8, 1, eos, None, ctypes.byref(o), ctypes.byref(h)) == lr.LR_EINVAL
+    o.remap = lr.LR_REMAP_AD
+    for tile in (lr.LR_TILE_16x16, lr.LR_TILE_32x16, lr.LR_TILE_32x12):
+        o.tile = tile
+        assert lib.lr_create(8, 8, 1, eos, None, ctypes.byref(o), ctypes.byref(h)) == lr.LR_EINVAL
+    assert lr.TILE_SHAPES[lr.LR_TILE_32x12] == (32, 12) and len(lr.TILE_SHAPES) == lr.LR_NTILE

@@ -9,7 +9,7 @@ import pytest
 
 from oracle import RefSolver
 from paper_2208_13409_amd import inputs
-from paper_2208_13409_amd.lr import LRError, Solver
+from paper_2208_13409_amd.lr import LR_TILE_32x12, LRError, Solver
 
 pytestmark = pytest.mark.gpu
 
@@ -153,9 +153,11 @@ def test_triple_point_full_size_steps():
     t0 = g.totals()
     g.run(p["t_end"], max_steps=200)
     t1 = g.totals()
-    cap, replayed, failed = g.stage("run")
+    cap, replayed, failed, tile = g.stage("run")
     assert replayed == 1 and failed == 0, "full chunks did not replay a graph"
     assert cap == 448 * 192 // 16
+    # 375 node tiles of 32x8 against 255 of 32x12 on the 256 CUs
+    assert tile == LR_TILE_32x12
     m0, m1 = t0[3:6], t1[3:6]
     assert np.all(np.abs(m1 - m0) <= 1e-12 * m0)
     assert abs(t1[:3].sum() - 21.0) < 1e-12 * 21.0
