@@ -72,13 +72,12 @@ typedef struct {
                             and the step runs again (lr_run_noalloc: the largest list
                             its workspace holds, no growth)                              */
   int tile;              /* tile shape of a context's step kernels (LR_TILE_*, below):
-                            LR_TILE_AUTO (default) takes 32x12 where the grid's 32x12
-                            node tiles fit on the device's CUs one block each and its
-                            32x8 ones do not (a small grid, one latency-bound round of
-                            blocks instead of two blocks on some CUs), else 32x8.
-                            LR_REMAP_AD runs on 32x8 only; batches take their shape
-                            from lr_batch_opts and lr_run_noalloc runs 32x8.  Results
-                            do not depend on it.                                      */
+                            LR_TILE_AUTO (default) counts the grid's node tiles against
+                            the device's CUs: 32x8 if its 32x8 tiles fit one block per
+                            CU, else 32x12 if those do (one latency-bound round instead
+                            of two blocks on some CUs), else 32x16.  LR_REMAP_AD runs
+                            on 32x8 only; batches take their shape from lr_batch_opts
+                            and lr_run_noalloc runs 32x8.  Results do not depend on it. */
 } lr_opts;
 
 /* field mask bits for lr_get_fields, in the order the output pointers are

@@ -427,11 +427,11 @@ int alloc_prob(lr_ctx *c, Prob<R> &P) {
   return ctx_list<R>(c, P, mix_cap_initial(c->g, 0));
 }
 
-// LR_TILE_AUTO: a grid whose 32x8 node tiles outnumber the device's CUs while
-// its 32x12 ones do not steps on 32x12 tiles.  Such a grid's launches are one
-// latency-bound round of blocks; on 32x8 tiles some CUs would hold two of
-// them and set every kernel's time.  Larger grids keep 32x8 (more blocks per
-// CU fit its smaller LDS tiles).
+// LR_TILE_AUTO, by the grid's node tiles against the device's CUs: a grid
+// whose 32x8 tiles take one round of blocks keeps them; one whose 32x12 tiles
+// do (and 32x8 would not) steps on 32x12, one block per CU (on 32x8 some CUs
+// would hold two blocks of the one latency-bound round and set every kernel's
+// time); larger grids step on 32x16 (less halo per owned cell, several rounds).
 int auto_tile(const Grid &g) {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -440,7 +440,8 @@ int auto_tile(const Grid &g) {
   auto node_tiles = [&](int t) {
     return (long long)(g.nx / kTileX[t] + 1) * (long long)(g.ny / kTileY[t] + 1);
   };
-  return node_tiles(LR_TILE_32x8) > cus && node_tiles(LR_TILE_32x12) <= cus ? LR_TILE_32x12 : LR_TILE_32x8;
+  if (node_tiles(LR_TILE_32x8) <= cus) return LR_TILE_32x8;
+  return node_tiles(LR_TILE_32x12) <= cus ? LR_TILE_32x12 : LR_TILE_32x16;
 }
 
 int build_maps(lr_ctx *c) {

@@ -346,10 +346,13 @@ def test_tile_shapes_give_the_same_bits(tile, precision, nmat, persistent):
 def test_single_problem_tile_shapes_give_the_same_bits(precision, nmat):
     """A problem alone on each tile shape (the FP64 32x12 launches with two
     threads per cell in the Lagrange and dual kernels, as 32x8) gives the bits
-    of 32x8, on ragged grids; the automatic choice takes 32x12 for a grid whose
-    32x8 node tiles outnumber the CUs while its 32x12 ones do not."""
+    of 32x8, on ragged grids; the automatic choice keeps 32x8 for a grid whose
+    32x8 node tiles fit on the 256 CUs, takes 32x12 for one whose 32x12 ones do,
+    and 32x16 beyond."""
     steps = 12
-    for i, (nx, ny) in enumerate(((70, 37), (448, 192), (130, 250))):
+    auto = {(70, 37): LR_TILE_32x8, (448, 192): LR_TILE_32x12, (130, 250): LR_TILE_32x8,
+            (700, 400): LR_TILE_32x16}
+    for i, (nx, ny) in enumerate(auto):
         p = inputs.random_mixed(70 + i, nx, ny, nmat=nmat)
         g0, n0, _ = alone(p, precision, steps=steps, tile=LR_TILE_32x8)
         assert n0 == steps and g0.stage("run")[3] == LR_TILE_32x8
@@ -359,7 +362,7 @@ def test_single_problem_tile_shapes_give_the_same_bits(precision, nmat):
             g, n, _ = alone(p, precision, steps=steps, tile=tile)
             assert n == steps
             if tile == LR_TILE_AUTO:
-                assert g.stage("run")[3] == (LR_TILE_32x12 if (nx, ny) == (448, 192) else LR_TILE_32x8)
+                assert g.stage("run")[3] == auto[(nx, ny)]
             same_fields(g.fields(*FIELDS), ref, f"{nx}x{ny} on tile {tile}")
 
 
