@@ -248,7 +248,7 @@ class FourQuadrantStream:
         self.pool.shutdown(wait=False, cancel_futures=True)
 
 
-def serve_leg(n_requests, rate):
+def serve_leg(n_requests, rate, tile=None):
     """The seeded Poisson stream of four-quadrant problems served with
     continuous batching: served and offered cell-updates/s (offered = the
     work of the stream over its arrival span), the share of wall time with a
@@ -257,12 +257,15 @@ def serve_leg(n_requests, rate):
     import numpy as np
 
     from paper_2208_13409_amd import inputs
-    from paper_2208_13409_amd.lr import LR_FP32, Batch
+    from paper_2208_13409_amd.lr import LR_FP32, LR_TILE_16x16, TILE_SHAPES, Batch
     from paper_2208_13409_amd.serve import percentile, serve
+    # 16x16: the shape the batch autotuner keeps for FP32 two-material
+    # launches (the stream's mix changes too often to time schedules on it)
+    tile = LR_TILE_16x16 if tile is None else tile
     reqs = FourQuadrantStream(n_requests)
     reqs.warm(8)  # the first requests built before the clock starts
     arrivals = inputs.poisson_arrivals(n_requests, rate=rate)
-    b = Batch(nmat=2, precision=LR_FP32, max_slots=64, pool_bytes=16 << 30, chunk_steps=8)
+    b = Batch(nmat=2, precision=LR_FP32, max_slots=64, pool_bytes=16 << 30, chunk_steps=8, tile=tile)
     out = serve(b, reqs, arrivals)
     b.close()
     reqs.close()
@@ -280,7 +283,7 @@ def serve_leg(n_requests, rate):
             "arrival_span_s": float(arrivals[-1]), "gpu_busy": out["busy"], "max_running": out["max_running"],
             "latency_by_arrival_quarter": [{"p50_s": percentile(lat[q], 50), "p99_s": percentile(lat[q], 99)}
                                            for q in quarters],
-            "failed_requests": failed,
+            "failed_requests": failed, "tile": "%dx%d" % TILE_SHAPES[tile],
             "workload": f"four_quadrant stream, first {n_requests} requests of the seeded stream, FP32"}
 
 
