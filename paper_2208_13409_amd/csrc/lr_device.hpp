@@ -14,10 +14,11 @@ constexpr int MAXMAT = LR_MAXMAT;
 constexpr int NTHREADS = 256;  // block of the kernels that work on lists or whole arrays
 
 // Tile of cells (or nodes) handled by one block of the step kernels, one
-// thread per cell.  The default shape serves single problems; the batch's
-// autotuner also times the others (each compiled in a translation unit of
-// its own).  Every shape computes the same bits: the tile only decides which
-// block forms a value, never how.
+// thread per cell.  A single problem takes its shape from its size (32x8,
+// 32x12 or 32x16, or the caller's choice); the batch's autotuner times 32x8,
+// 16x16 and 32x16 (each shape compiled in a translation unit of its own).
+// Every shape computes the same bits: the tile only decides which block
+// forms a value, never how.
 template <int X, int Y>
 struct TileShape {
   static constexpr int TX = X, TY = Y, NT = X * Y;

@@ -6,8 +6,8 @@
 // A step is four launches, each over a whole batch of problems (a block map
 // gives every block its problem and tile, 32x8 cells by default; the
 // mixed-cell kernel has a grid of list chunks x problems; small FP64 launches
-// on the default shape run the Lagrange and dual tiles with 512 threads, the
-// others with one thread per cell of the tile):
+// on 32x8 and 32x12 tiles run the Lagrange and dual tiles with two threads per
+// cell or node, the others with one thread per cell of the tile):
 //   k_lagrange  cell tiles: predictor per cell staged in LDS (EOS, Wilkins Q,
 //               Vol^{n+1/2}, P_a^{n+1/2}; §1.2, §4.1), nodal mass and gradient
 //               of P+Q, u^{n+1/2}, u^{lag} of the tile's nodes; corrector
@@ -608,7 +608,8 @@ __device__ __forceinline__ void lagrange_tile(const Prob<R> *probs, const BlockM
 // one block per tile of the map (LOOP false: grid = map), or a grid smaller
 // than the map whose blocks walk it (LOOP true; a separate instantiation,
 // since the loop keeps values live across tiles and costs registers)
-// WIDE: 512 threads per tile, for small FP64 launches (as the dual kernel)
+// WIDE: two threads per cell of the tile, for small FP64 launches (as the
+// dual kernel)
 template <typename R, int NM, bool LOOP, bool WIDE, typename T>
 __global__ void __launch_bounds__(WIDE ? 2 * T::NT : T::NT)
     k_lagrange(const Prob<R> *probs, const BlockMap *map, int nmap, int gpar) {
@@ -1676,7 +1677,8 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
                   IT2C = (SH::NXF + SH::NYF) / BT;
     // regions without mass flux (material at rest) carry no momentum: their
     // fluxes are written as zero without the reconstruction, except in the
-    // 512-thread tiles of small FP64 launches, timed by their slowest tile
+    // two-threads-per-node tiles of small FP64 launches, timed by their
+    // slowest tile
     constexpr bool REST = BT == T::NT;
     R ha[IT2 - IT2C][2];
     // each region's mass flux, kept for stage 3 (written over the primal
@@ -1859,10 +1861,10 @@ __device__ __forceinline__ void dual_tile(const Prob<R> *probs, const BlockMap b
 // one block per tile of the map (LOOP false: grid = map), or a grid smaller
 // than the map whose blocks walk it (LOOP true; a separate instantiation,
 // since the loop keeps values live across tiles and costs registers)
-// WIDE: 512 threads per tile (two per node), so that each thread stages and
+// WIDE: two threads per node of the tile, so that each thread stages and
 // forms half as many items.  For small FP64 launches, where the grid is one
-// round of blocks and its time one tile's latency; with many tiles the 256-
-// thread form keeps more tiles per CU.
+// round of blocks and its time one tile's latency; with many tiles the one-
+// thread-per-node form keeps more tiles per CU.
 template <typename R, int NM, bool LOOP, bool WIDE, typename T>
 __global__ void __launch_bounds__(WIDE ? 2 * T::NT : T::NT)
     k_dual(const Prob<R> *probs, const BlockMap *map, int nmap, int gpar) {
