@@ -248,7 +248,7 @@ class FourQuadrantStream:
         self.pool.shutdown(wait=False, cancel_futures=True)
 
 
-def serve_leg(n_requests, rate, tile=None):
+def serve_leg(n_requests, rate, tile=None, max_slots=64, pool_gib=16):
     """The seeded Poisson stream of four-quadrant problems served with
     continuous batching: served and offered cell-updates/s (offered = the
     work of the stream over its arrival span), the share of wall time with a
@@ -265,7 +265,7 @@ def serve_leg(n_requests, rate, tile=None):
     reqs = FourQuadrantStream(n_requests)
     reqs.warm(8)  # the first requests built before the clock starts
     arrivals = inputs.poisson_arrivals(n_requests, rate=rate)
-    b = Batch(nmat=2, precision=LR_FP32, max_slots=64, pool_bytes=16 << 30, chunk_steps=8, tile=tile)
+    b = Batch(nmat=2, precision=LR_FP32, max_slots=max_slots, pool_bytes=pool_gib << 30, chunk_steps=8, tile=tile)
     out = serve(b, reqs, arrivals)
     b.close()
     reqs.close()
