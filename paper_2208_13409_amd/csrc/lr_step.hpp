@@ -67,15 +67,18 @@ __device__ __forceinline__ R eos_krc2(const GridT &g, int m, R k, R P) {
   return k * R(g.gamma[m]) * P + k * R(g.pinf[m]);
 }
 
-// compensated accumulation (Kahan–Neumaier) for the FP32 cell totals
+// compensated accumulation for the FP32 cell totals: each addition's exact
+// rounding error, the Kahan–Neumaier correction, is formed branch-free by
+// Knuth's two-sum (the same error, so the same bits, one instruction fewer
+// than choosing the Fast2Sum order by magnitude); needs contraction off
 template <typename R>
 struct Acc {
   R s, c;
   __device__ __forceinline__ void init(R v) { s = v; c = R(0); }
   __device__ __forceinline__ void add(R v) {
     const R t = s + v;
-    if (fabs(s) >= fabs(v)) c += (s - t) + v;
-    else c += (v - t) + s;
+    const R bv = t - s;
+    c += (s - (t - bv)) + (v - bv);
     s = t;
   }
   __device__ __forceinline__ R get() const { return s + c; }
