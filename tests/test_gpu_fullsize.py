@@ -21,7 +21,7 @@ import pytest
 
 from oracle import RefSolver
 from paper_2208_13409_amd import inputs
-from paper_2208_13409_amd.lr import LR_FP32, LR_FP64, Batch, Solver
+from paper_2208_13409_amd.lr import LR_FP32, LR_FP64, LR_TILE_32x16, Batch, Solver
 
 pytestmark = pytest.mark.gpu
 
@@ -42,6 +42,8 @@ def developed_state(p, steps):
     renormalised (both sides get the same arrays)"""
     g = Solver(p["nx"], p["ny"], p["gammas"], p["domain"])
     g.set_state(0.0, p["k"], p["rho"], p["e"], p["ux"], p["uy"])
+    if p["nx"] * p["ny"] >= 1792 * 768:  # beyond one round of blocks: 32x16 tiles
+        assert g.stage("run")[3] == LR_TILE_32x16
     n, t = g.run(1e30, max_steps=steps)
     f = g.fields("k", "rho_a", "e_a", "ux", "uy")
     k, rho, e = f["k"], f["rho_a"], f["e_a"]
